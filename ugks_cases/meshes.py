@@ -1,0 +1,403 @@
+"""Unstructured meshes stored as face lists.
+
+A mesh is the input the scheme's finite-volume partition needs (the control
+volumes Omega_i, the interface areas S_ij, unit normals n_ij and neighbour
+sets N(i) of Sec. 2.1, Eqs. (physical_partition) and (fv_micro_update)):
+
+* ``cell_volume[i]``, ``cell_centroid[i]``
+* ``face_cells[f] = (L, R)`` with ``R = -1`` on a physical boundary
+* ``face_area[f]``, ``face_normal[f]`` (unit, pointing from L to R, i.e.
+  outward from L on a boundary), ``face_centroid[f]`` (as seen from L)
+* ``face_shift[f]``: for a periodic face, the translation that carries R's
+  centroid next to L (R's image is ``cell_centroid[R] + face_shift[f]``)
+* ``face_bc[f]`` (0 interior/periodic, 1 wall, 2 far field, 3 outflow) and
+  ``face_bc_id[f]`` (row of the boundary-condition table, -1 for interior)
+
+Everything here is geometry of the input; none of it is the scheme.
+"""
+
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BC_INTERIOR, BC_WALL, BC_FARFIELD, BC_OUTFLOW = 0, 1, 2, 3
+
+
+@dataclass
+class Mesh:
+    dim: int
+    cell_volume: np.ndarray
+    cell_centroid: np.ndarray
+    face_cells: np.ndarray
+    face_area: np.ndarray
+    face_normal: np.ndarray
+    face_centroid: np.ndarray
+    face_shift: np.ndarray
+    face_bc: np.ndarray
+    face_bc_id: np.ndarray
+    name: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_volume.shape[0])
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.face_area.shape[0])
+
+    def contiguous(self) -> "Mesh":
+        """Return the same mesh with every array C-contiguous and typed."""
+        f8 = lambda a: np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
+        return Mesh(
+            dim=int(self.dim),
+            cell_volume=f8(self.cell_volume),
+            cell_centroid=f8(self.cell_centroid.reshape(-1, self.dim)),
+            face_cells=np.ascontiguousarray(self.face_cells, dtype=np.int64).reshape(-1, 2),
+            face_area=f8(self.face_area),
+            face_normal=f8(self.face_normal.reshape(-1, self.dim)),
+            face_centroid=f8(self.face_centroid.reshape(-1, self.dim)),
+            face_shift=f8(self.face_shift.reshape(-1, self.dim)),
+            face_bc=np.ascontiguousarray(self.face_bc, dtype=np.int32),
+            face_bc_id=np.ascontiguousarray(self.face_bc_id, dtype=np.int32),
+            name=self.name,
+            extra=dict(self.extra),
+        )
+
+    def validate(self, tol: float = 1e-12) -> None:
+        """Raise ValueError unless the face list describes a closed, oriented mesh.
+
+        Checks: positive volumes and areas; unit normals; valid cell indices;
+        interior faces join two distinct cells with the normal pointing from L
+        towards R's (possibly shifted) centroid; boundary normals point out of
+        L; and every cell is closed, sum_j sigma_ij S_j n_j = 0.
+        """
+        d = self.dim
+        nc, nf = self.n_cells, self.n_faces
+        if d not in (2, 3):
+            raise ValueError("dim must be 2 or 3")
+        if np.any(self.cell_volume <= 0):
+            raise ValueError("non-positive cell volume")
+        if np.any(self.face_area <= 0):
+            raise ValueError("non-positive face area")
+        if np.max(np.abs(np.linalg.norm(self.face_normal, axis=1) - 1.0)) > 1e-12:
+            raise ValueError("face normals must be unit vectors")
+        L = self.face_cells[:, 0]
+        R = self.face_cells[:, 1]
+        if np.any(L < 0) or np.any(L >= nc) or np.any(R >= nc) or np.any(R < -1):
+            raise ValueError("face_cells out of range")
+        interior = self.face_bc == BC_INTERIOR
+        if np.any((R < 0) & interior) or np.any((R >= 0) & ~interior):
+            raise ValueError("interior faces need R >= 0, boundary faces R = -1")
+        if np.any(L[interior] == R[interior]):
+            raise ValueError("interior face joins a cell to itself")
+        xl = self.cell_centroid[L]
+        dn = np.where(
+            interior[:, None],
+            self.cell_centroid[np.maximum(R, 0)] + self.face_shift - xl,
+            self.face_centroid - xl,
+        )
+        if np.any(np.einsum("fd,fd->f", dn, self.face_normal) <= 0):
+            raise ValueError("face normal not oriented from L to R / outward")
+        closure = np.zeros((nc, d))
+        sn = self.face_area[:, None] * self.face_normal
+        np.add.at(closure, L, sn)
+        np.add.at(closure, R[interior], -sn[interior])
+        scale = np.zeros(nc)
+        np.add.at(scale, L, self.face_area)
+        np.add.at(scale, R[interior], self.face_area[interior])
+        if np.max(np.linalg.norm(closure, axis=1) / scale) > tol * 100:
+            raise ValueError("mesh cells are not closed")
+
+
+def quad_mesh(nx: int, ny: int | None = None, *, lx: float = 1.0, ly: float = 1.0,
+              periodic_x: bool = False, periodic_y: bool = False, wall_ids=(0, 1, 2, 3),
+              name: str = "") -> Mesh:
+    """Uniform nx x ny quadrilateral mesh of [0,lx]x[0,ly] as a face list.
+
+    Cell (i, j) has index i + nx*j.  Boundary tags: ``wall_ids`` gives the BC
+    table row of the (bottom y=0, right x=lx, top y=ly, left x=0) sides.  With
+    ``periodic_x`` the left/right sides become one periodic seam of interior
+    faces (L = last column, R = first column, shift = (+lx, 0)); likewise
+    ``periodic_y`` for the bottom/top sides.
+    """
+    ny = nx if ny is None else ny
+    hx, hy = lx / nx, ly / ny
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    cid = (ii + nx * jj).ravel()
+    cen = np.zeros((nx * ny, 2))
+    cen[cid, 0] = ((ii + 0.5) * hx).ravel()
+    cen[cid, 1] = ((jj + 0.5) * hy).ravel()
+    vol = np.full(nx * ny, hx * hy)
+    fc, fa, fn, fx, fs, fb, fi = [], [], [], [], [], [], []
+
+    def add(L, R, area, n, x, s=(0.0, 0.0), bc=BC_INTERIOR, bid=-1):
+        fc.append((L, R)); fa.append(area); fn.append(n); fx.append(x)
+        fs.append(s); fb.append(bc); fi.append(bid)
+
+    c = lambda i, j: i + nx * j  # noqa: E731
+    bottom, right, top, left = wall_ids
+    for j in range(ny):
+        y = (j + 0.5) * hy
+        if periodic_x:
+            add(c(nx - 1, j), c(0, j), hy, (1.0, 0.0), (lx, y), s=(lx, 0.0))
+        else:
+            add(c(0, j), -1, hy, (-1.0, 0.0), (0.0, y), bc=BC_WALL, bid=left)
+        for i in range(1, nx):
+            add(c(i - 1, j), c(i, j), hy, (1.0, 0.0), (i * hx, y))
+        if not periodic_x:
+            add(c(nx - 1, j), -1, hy, (1.0, 0.0), (lx, y), bc=BC_WALL, bid=right)
+    for i in range(nx):
+        x = (i + 0.5) * hx
+        if periodic_y:
+            add(c(i, ny - 1), c(i, 0), hx, (0.0, 1.0), (x, ly), s=(0.0, ly))
+        else:
+            add(c(i, 0), -1, hx, (0.0, -1.0), (x, 0.0), bc=BC_WALL, bid=bottom)
+        for j in range(1, ny):
+            add(c(i, j - 1), c(i, j), hx, (0.0, 1.0), (x, j * hy))
+        if not periodic_y:
+            add(c(i, ny - 1), -1, hx, (0.0, 1.0), (x, ly), bc=BC_WALL, bid=top)
+    m = Mesh(2, vol, cen, np.array(fc), np.array(fa), np.array(fn), np.array(fx),
+             np.array(fs), np.array(fb), np.array(fi), name=name or f"quad{nx}x{ny}")
+    m = m.contiguous()
+    m.validate()
+    return m
+
+
+def _tri_geometry(a, b, c):
+    cr = np.cross(b - a, c - a)
+    area2 = np.linalg.norm(cr, axis=1)
+    return 0.5 * area2, cr / area2[:, None], (a + b + c) / 3.0
+
+
+def _faces_from_simplices(verts: np.ndarray, tets: np.ndarray):
+    """Match the triangular faces of a conforming tet mesh.
+
+    Returns (L, R, tri) with R = -1 for boundary faces, and tri the three vertex
+    ids of each face.
+    """
+    nt = tets.shape[0]
+    opp = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]])
+    tri = tets[:, opp].reshape(-1, 3)
+    owner = np.repeat(np.arange(nt), 4)
+    key = np.sort(tri, axis=1)
+    order = np.lexsort((key[:, 2], key[:, 1], key[:, 0]))
+    ks = key[order]
+    same = np.all(ks[1:] == ks[:-1], axis=1)
+    if np.any(same[1:] & same[:-1]):
+        raise ValueError("a face is shared by more than two tets")
+    Ls, Rs, Ts = [], [], []
+    i = 0
+    n = ks.shape[0]
+    pair_start = np.zeros(n, dtype=bool)
+    pair_start[:-1] = same
+    is_second = np.zeros(n, dtype=bool)
+    is_second[1:] = same
+    firsts = np.where(pair_start)[0]
+    singles = np.where(~pair_start & ~is_second)[0]
+    Ls.append(owner[order[firsts]]); Rs.append(owner[order[firsts + 1]])
+    Ts.append(tri[order[firsts]])
+    Ls.append(owner[order[singles]]); Rs.append(np.full(singles.size, -1))
+    Ts.append(tri[order[singles]])
+    del i
+    L = np.concatenate(Ls); R = np.concatenate(Rs); T = np.concatenate(Ts)
+    # deterministic face order: sort by (min(L,R) for interior, L) then vertex key
+    srt = np.lexsort((np.sort(T, axis=1)[:, 2], np.sort(T, axis=1)[:, 1],
+                      np.sort(T, axis=1)[:, 0], L))
+    return L[srt], R[srt], T[srt]
+
+
+def _tet_mesh_from_vertices(verts, tets, side_of_face, name, extra=None) -> Mesh:
+    """Build a Mesh from tet connectivity; ``side_of_face(centroids)`` tags walls."""
+    p = verts[tets]
+    vol6 = np.einsum("ti,ti->t", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])
+    if np.any(vol6 <= 0):
+        raise ValueError("inverted or degenerate tetrahedron")
+    vol = vol6 / 6.0
+    cen = p.mean(axis=1)
+    L, R, T = _faces_from_simplices(verts, tets)
+    area, nrm, fcen = _tri_geometry(verts[T[:, 0]], verts[T[:, 1]], verts[T[:, 2]])
+    interior = R >= 0
+    d = np.where(interior[:, None], cen[np.maximum(R, 0)] - cen[L], fcen - cen[L])
+    flip = np.einsum("fd,fd->f", d, nrm) < 0
+    nrm[flip] *= -1.0
+    bc = np.where(interior, BC_INTERIOR, BC_WALL).astype(np.int32)
+    bid = np.full(L.size, -1, dtype=np.int32)
+    if np.any(~interior):
+        kind, ids = side_of_face(fcen[~interior])
+        bc[~interior] = kind
+        bid[~interior] = ids
+    m = Mesh(3, vol, cen, np.stack([L, R], axis=1), area, nrm, fcen,
+             np.zeros_like(fcen), bc, bid, name=name, extra=extra or {})
+    m = m.contiguous()
+    m.validate()
+    return m
+
+
+def kuhn_tet_cube(n: int, *, jitter: float = 0.15, seed: int = 0, name: str = "") -> Mesh:
+    """Unit cube of n^3 hexes, each split into 6 Kuhn tets along (0,0,0)-(1,1,1).
+
+    Every vertex is moved by a uniform random offset in [-jitter*h, jitter*h]
+    per coordinate (numpy ``default_rng(seed)``); a vertex on a boundary plane
+    keeps that coordinate, so boundary vertices move only within their face or
+    edge and corners stay fixed.  All six walls get boundary-table rows
+    0..5 for the sides x=0, x=1, y=0, y=1, z=0, z=1.
+    """
+    h = 1.0 / n
+    g = np.arange(n + 1)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    ijk = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
+    verts = ijk * h
+    if jitter > 0:
+        rng = np.random.default_rng(seed)
+        off = rng.uniform(-jitter * h, jitter * h, size=verts.shape)
+        on_bnd = (ijk == 0) | (ijk == n)
+        off[on_bnd] = 0.0
+        verts = verts + off
+    vid = lambda i, j, k: (i * (n + 1) + j) * (n + 1) + k  # noqa: E731
+    tets = []
+    base = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"),
+                    axis=-1).reshape(-1, 3)
+    for perm in itertools.permutations(range(3)):
+        e = np.eye(3, dtype=np.int64)
+        v0 = base
+        v1 = v0 + e[perm[0]]
+        v2 = v1 + e[perm[1]]
+        v3 = v2 + e[perm[2]]
+        t = np.stack([vid(*v.T) for v in (v0, v1, v2, v3)], axis=1)
+        # orient positively on the unjittered lattice
+        p = ijk[t].astype(np.float64)
+        s = np.einsum("ti,ti->t", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])
+        t[s < 0] = t[s < 0][:, [0, 2, 1, 3]]
+        tets.append(t)
+    # hex-major cell order: the six tets of one hex are consecutive
+    tets = np.stack(tets, axis=1).reshape(-1, 4)
+
+    def sides(fc):
+        ids = np.full(fc.shape[0], -1, dtype=np.int32)
+        for ax in range(3):
+            ids[np.abs(fc[:, ax]) < 1e-12] = 2 * ax
+            ids[np.abs(fc[:, ax] - 1.0) < 1e-12] = 2 * ax + 1
+        if np.any(ids < 0):
+            raise ValueError("boundary face not on a cube side")
+        return np.full(fc.shape[0], BC_WALL, dtype=np.int32), ids
+
+    return _tet_mesh_from_vertices(verts, tets, sides, name or f"kuhn{n}_j{jitter}_s{seed}")
+
+
+def cubed_sphere_shell(n_ang: int = 11, n_rad: int = 23, *, r0: float = 1.0, r1: float = 6.0,
+                       first: float = 0.02, name: str = "") -> Mesh:
+    """Spherical shell r0 <= r <= r1 around a unit sphere, meshed with tets.
+
+    The sphere is split into the six faces of a cube, each gnomonically
+    projected and divided into n_ang x n_ang patches; radially there are n_rad
+    layers with first thickness ``first`` and a constant growth ratio chosen so
+    the layers end at r1.  Each hexahedral (patch x layer) element is split into
+    6 Kuhn tets over a global vertex numbering whose ordering is the same on
+    both sides of every shared quad, so the tet faces conform.  Tags: the inner
+    sphere is BC row 0 (wall), the outer sphere row 1 (far field).
+    """
+    # radial distribution with geometric growth
+    def total(q):
+        return first * (q ** n_rad - 1.0) / (q - 1.0)
+    lo, hi = 1.0 + 1e-9, 2.0
+    target = r1 - r0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if total(mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    q = 0.5 * (lo + hi)
+    radii = r0 + np.concatenate([[0.0], np.cumsum(first * q ** np.arange(n_rad))])
+    radii[-1] = r1
+    # unique surface vertices of the cube [-1,1]^3 surface lattice
+    m = n_ang
+    t = np.tan(np.linspace(-np.pi / 4, np.pi / 4, m + 1))  # equiangular
+    pts = {}
+    quads = []
+    def key(v):
+        return tuple(np.round(v, 12))
+    def vid(v):
+        k = key(v)
+        if k not in pts:
+            pts[k] = len(pts)
+        return pts[k]
+    faces_def = []
+    for ax in range(3):
+        for sgn in (-1.0, 1.0):
+            faces_def.append((ax, sgn))
+    for ax, sgn in faces_def:
+        a1, a2 = [x for x in range(3) if x != ax]
+        for i in range(m):
+            for j in range(m):
+                corner = []
+                for di, dj in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                    v = np.zeros(3)
+                    v[ax] = sgn
+                    v[a1] = t[i + di]
+                    v[a2] = t[j + dj]
+                    corner.append(vid(v))
+                quads.append(corner)
+    surf = np.zeros((len(pts), 3))
+    for k, i in pts.items():
+        surf[i] = k
+    surf /= np.linalg.norm(surf, axis=1, keepdims=True)
+    ns = surf.shape[0]
+    verts = (radii[:, None, None] * surf[None, :, :]).reshape(-1, 3)
+    gid = lambda layer, s: layer * ns + s  # noqa: E731
+    tets = []
+    for quad in quads:
+        for layer in range(n_rad):
+            # hex vertices: bottom quad (layer) then top quad (layer+1)
+            hexv = [gid(layer, s) for s in quad] + [gid(layer + 1, s) for s in quad]
+            tets.extend(_split_hex_by_global_order(hexv, verts))
+    tets = np.array(tets, dtype=np.int64)
+    p = verts[tets]
+    s6 = np.einsum("ti,ti->t", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])
+    tets[s6 < 0] = tets[s6 < 0][:, [0, 2, 1, 3]]
+
+    def sides(fc):
+        r = np.linalg.norm(fc, axis=1)
+        inner = r < 0.5 * (r0 + radii[1])
+        kind = np.where(inner, BC_WALL, BC_FARFIELD).astype(np.int32)
+        ids = np.where(inner, 0, 1).astype(np.int32)
+        return kind, ids
+
+    return _tet_mesh_from_vertices(verts, tets, sides, name or f"sphere{n_ang}x{n_rad}",
+                                   extra={"radii": radii})
+
+
+def _split_hex_by_global_order(hexv, verts):
+    """Split a hexahedron into tets so that shared quads are cut consistently.
+
+    ``hexv`` lists the hex's vertices as bottom quad (a,b,c,d) then top quad
+    (e,f,g,h), each quad in cyclic order.  The hex is split into 6 tets along
+    the diagonal from its lowest global id through Kuhn paths, using the rule
+    that every quad face is cut along the diagonal through its smallest global
+    vertex id.  That rule depends only on the quad's own vertices, so the two
+    hexes sharing a quad cut it the same way.
+    """
+    # local lattice coordinates of the 8 vertices (cube corners)
+    loc = {0: (0, 0, 0), 1: (1, 0, 0), 2: (1, 1, 0), 3: (0, 1, 0),
+           4: (0, 0, 1), 5: (1, 0, 1), 6: (1, 1, 1), 7: (0, 1, 1)}
+    inv = {v: k for k, v in loc.items()}
+    # choose the corner with the smallest global id as the Kuhn origin, and
+    # flip local axes so that it becomes (0,0,0)
+    k0 = int(np.argmin(hexv))
+    o = loc[k0]
+    def g(c):
+        cc = tuple((ci ^ oi) for ci, oi in zip(c, o))
+        return hexv[inv[cc]]
+    out = []
+    for perm in itertools.permutations(range(3)):
+        c = [0, 0, 0]
+        path = [g(tuple(c))]
+        for ax in perm:
+            c[ax] = 1
+            path.append(g(tuple(c)))
+        out.append(path)
+    return out

@@ -1,0 +1,62 @@
+"""Discrete velocity sets {u_k, omega_k} (Sec. 2.1, Eqs. velocity_quadrature, omega_k).
+
+Points are ordered as a tensor product with the first axis slowest, so for a
+grid that is symmetric about zero the mirror image -u_k of point k is point
+N_v - 1 - k.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Velocity:
+    dim: int
+    u: np.ndarray          # (nv, dim)
+    w: np.ndarray          # (nv,) ordinary quadrature weights
+    axes: tuple = ()       # per-axis 1-D nodes when the set is a tensor product
+    axis_w: tuple = ()     # per-axis 1-D weights
+    name: str = ""
+
+    @property
+    def nv(self) -> int:
+        return int(self.w.shape[0])
+
+
+def _tensor(dim, nodes, weights, name):
+    grids = np.meshgrid(*([nodes] * dim), indexing="ij")
+    u = np.stack([g.ravel() for g in grids], axis=1)
+    wg = np.meshgrid(*([weights] * dim), indexing="ij")
+    w = np.ones(u.shape[0])
+    for g in wg:
+        w = w * g.ravel()
+    return Velocity(dim, np.ascontiguousarray(u), np.ascontiguousarray(w),
+                    tuple([np.asarray(nodes)] * dim), tuple([np.asarray(weights)] * dim), name)
+
+
+def midpoint_grid(n: int, a: float, dim: int) -> Velocity:
+    """Uniform midpoint rule on [-a, a]^dim with n points per axis.
+
+    Each point is the centre of a velocity cell of side 2a/n and carries that
+    cell's volume (2a/n)^dim as its weight (the cell-average reading of
+    Eq. omega_k).
+    """
+    du = 2.0 * a / n
+    nodes = -a + (np.arange(n) + 0.5) * du
+    return _tensor(dim, nodes, np.full(n, du), f"mid{n}^{dim}[{a}]")
+
+
+def gauss_hermite_grid(n_gh: int, u_max: float, dim: int) -> Velocity:
+    """Tensor Gauss-Hermite set of the cavity case (Sec. 3.1, Eqs. cavity_dvs_*).
+
+    The roots xi_i of the physicists' Hermite polynomial of degree n_gh are
+    scaled by s = u_max / max|xi_i|; the ordinary weights are
+    s * w_i^GH * exp(xi_i^2) so that sum_k omega_k Q(u_k) approximates the
+    plain integral of Q.
+    """
+    xi, wgh = np.polynomial.hermite.hermgauss(n_gh)
+    s = u_max / np.max(np.abs(xi))
+    return _tensor(dim, s * xi, s * wgh * np.exp(xi ** 2), f"gh{n_gh}^{dim}[{u_max}]")
