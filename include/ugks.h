@@ -1,0 +1,228 @@
+/*
+ * ugks.h - C ABI of the MI355X (gfx950) UGKS phase-space step.
+ *
+ * The library advances the discrete-velocity BGK-Shakhov model with the
+ * unified gas-kinetic scheme on an unstructured mesh held by one GPU: the
+ * sweep over all discrete velocities of microscopic least-squares
+ * reconstruction, time-integrated interface flux (equilibrium part plus
+ * upwind free-transport part), velocity-moment reduction to the conservative
+ * variables, and the two-stage trapezoidal collision update (paper Sec. 2.1,
+ * Eqs. fv_micro_update ... f_final; one step = the one-step algorithm of
+ * Sec. 2.2 with a single physical subdomain that owns every velocity block).
+ *
+ * Conventions shared by every call
+ *   - Every call returns an int status: UGKS_OK (0) or a negative UGKS_E*
+ *     code.  No C++ exception crosses this boundary.  After a failure,
+ *     ugks_last_error() on the same context (or with NULL for failures of
+ *     ugks_create) returns a human-readable reason.
+ *   - Host arrays passed in are read during the call and copied; the caller
+ *     keeps ownership.  Output buffers belong to the caller.  A pointer
+ *     documented "on_device" is a device address in the library's current
+ *     HIP device (for example a PyTorch CUDA tensor's data_ptr()).
+ *   - All device memory is allocated by ugks_create / ugks_batch_create and
+ *     freed by ugks_destroy / ugks_batch_destroy.
+ *   - A context is used by one host thread at a time.  The library keeps no
+ *     global mutable state; calls on different contexts are independent.
+ *   - Units are the caller's; the workloads of this project use rho0 = 1,
+ *     T0 = 1, length 1, speed sqrt(2 R T0) (so R = 1/2).
+ *   - Only monatomic gases (K = 0) are supported: then K_xi = 3 - D and, in
+ *     3-D, b = B = B+ = 0 so only h is stored.  K > 0 returns
+ *     UGKS_EUNSUPPORTED (the reduced Shakhov b-equation, Eq. B_plus, is only
+ *     consistent with the Shakhov model, Eq. shakhov_fp, for K = 0).
+ */
+#ifndef UGKS_H
+#define UGKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define UGKS_OK 0
+#define UGKS_EINVAL (-1)        /* invalid argument, mesh or velocity set   */
+#define UGKS_ENOMEM (-2)        /* device allocation failed                  */
+#define UGKS_EHIP (-3)          /* a HIP runtime call failed                 */
+#define UGKS_ENUMERIC (-4)      /* non-positive density or temperature      */
+#define UGKS_EUNSUPPORTED (-5)  /* valid request outside the built features */
+
+/* ---- boundary kinds (ugks_mesh.face_bc, ugks_bc.kind) ------------------ */
+#define UGKS_BC_INTERIOR 0 /* two cells; periodic faces are interior + shift */
+#define UGKS_BC_WALL 1     /* diffuse Maxwell wall (Eqs. wall_bc .. wall_density_condition) */
+#define UGKS_BC_FARFIELD 2 /* ghost cell: W_inf when U_inf.n < 0, else the interior state */
+#define UGKS_BC_OUTFLOW 3  /* ghost cell: the interior state */
+
+/* ---- precision forms (ugks_options.precision) -------------------------- */
+#define UGKS_FP64 64 /* h, b, their gradients and fluxes in FP64 */
+#define UGKS_FP32 32 /* h, b stored and fluxed in FP32; moments, the
+                        macroscopic update and the interface equilibrium in FP64 */
+
+typedef struct ugks_ctx ugks_ctx;
+
+/*
+ * Unstructured mesh as a face list (Sec. 2.1: control volumes Omega_i,
+ * interfaces S_ij with unit normal n_ij, neighbour sets N(i)).
+ *   cell_volume[n_cells]            |Omega_i| > 0
+ *   cell_centroid[n_cells*dim]      row-major (x, y[, z]) per cell
+ *   face_cells[2*n_faces]           (L, R) per face; R = -1 on a physical boundary
+ *   face_area[n_faces]              S_ij > 0
+ *   face_normal[n_faces*dim]        unit normal pointing from L to R (outward on boundaries)
+ *   face_centroid[n_faces*dim]      face centroid as seen from L
+ *   face_shift[n_faces*dim] or NULL periodic translation: R's image is centroid[R] + shift
+ *   face_bc[n_faces]                UGKS_BC_* kind (INTERIOR for periodic faces)
+ *   face_bc_id[n_faces]             row of the ugks_bc table for boundary faces
+ * Every cell must be closed (sum_j sigma_ij S_j n_j = 0) and have at most 8
+ * faces.  Validation failures return UGKS_EINVAL.
+ */
+typedef struct {
+  int32_t dim; /* 2 or 3 */
+  int64_t n_cells, n_faces;
+  const double* cell_volume;
+  const double* cell_centroid;
+  const int64_t* face_cells;
+  const double* face_area;
+  const double* face_normal;
+  const double* face_centroid;
+  const double* face_shift;
+  const int32_t* face_bc;
+  const int32_t* face_bc_id;
+} ugks_mesh;
+
+/*
+ * Discrete velocity set {u_k, omega_k} (Eqs. velocity_quadrature, omega_k):
+ *   u[nv*dim] row-major points, w[nv] ordinary quadrature weights (> 0).
+ * The library pads the set to a multiple of its velocity block with
+ * zero-weight points (Eq. padded_velocity_number), which leaves every moment
+ * unchanged.
+ */
+typedef struct {
+  int64_t nv;
+  const double* u;
+  const double* w;
+} ugks_velocity;
+
+/*
+ * Gas model (Eqs. bgk_shakhov, shakhov_fp, lambda_def):
+ *   K internal degrees of freedom (must be 0), Pr Prandtl number, R gas
+ *   constant, mu = mu_ref (T / T_ref)^omega, tau = mu / p.
+ *   dt > 0 fixes the time step; dt = 0 takes
+ *     dt = cfl * min_i 2 |Omega_i| / max_k sum_{j in faces(i)} S_j |u_k . n_j|.
+ */
+typedef struct {
+  int32_t K;
+  double Pr, R, T_ref, mu_ref, omega;
+  double cfl, dt;
+} ugks_gas;
+
+/*
+ * One boundary-table row.  Walls use T (wall temperature) and U (wall
+ * velocity; must be tangential, U . n = 0).  Far field uses rho, U, T of
+ * the free stream.  Outflow uses nothing.
+ */
+typedef struct {
+  int32_t kind;
+  double rho;
+  double U[3];
+  double T;
+} ugks_bc;
+
+/*
+ * Options.
+ *   precision  UGKS_FP64 (default when 0) or UGKS_FP32.
+ *   block_v    velocity-block size B_v (64, 128, 256); 0 = library choice.
+ *   flags      bit 0: skip the density residual (saves one small reduction).
+ *   stream     hipStream_t to enqueue on, or NULL for a library-owned stream.
+ *              A caller stream is borrowed, never destroyed.
+ */
+typedef struct {
+  int32_t precision;
+  int32_t block_v;
+  int32_t flags;
+  void* stream;
+} ugks_options;
+
+/* Read-only facts about a context. */
+typedef struct {
+  int32_t dim, n_r;          /* n_r = 2 in 2-D (h and b), 1 in 3-D (h only) */
+  int32_t precision, block_v;
+  int64_t n_cells, n_faces, nv, nv_padded;
+  double dt;
+  int64_t steps_done;
+  int64_t device_bytes;      /* device memory held by the context */
+} ugks_info_t;
+
+/*
+ * ugks_create - build a context for one mesh, velocity set and gas, with the
+ * initial state h = H(W0), b = B(W0) (Eqs. H_def, B_def).
+ *   bcs[n_bc]   boundary table indexed by mesh.face_bc_id
+ *   W0[n_cells*(dim+2)]  conservative variables (rho, rho U, rho E) per cell
+ *   opt         may be NULL (all defaults)
+ *   out         receives the new context; unchanged on failure
+ * Errors: UGKS_EINVAL (bad mesh, velocity set, table or state),
+ *         UGKS_EUNSUPPORTED (K != 0), UGKS_ENOMEM, UGKS_EHIP.
+ */
+int ugks_create(const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas* gas,
+                const ugks_bc* bcs, int32_t n_bc, const double* W0, const ugks_options* opt,
+                ugks_ctx** out);
+
+/*
+ * ugks_step - advance n_steps >= 0 time steps (the one-step algorithm of
+ * Sec. 2.2): heat flux, macroscopic reconstruction, interface equilibrium,
+ * wall densities, the velocity sweep (microscopic reconstruction, interface
+ * flux, moment reduction, first stage, Eq. f_tilde), the conservative update
+ * (Eq. macro_update) and the second stage (Eq. f_final).
+ *   residual_out  NULL, or two doubles receiving, for the last step, the
+ *                 density residual ||rho^n - rho^{n-1}||_{2,V} normalised by
+ *                 the first non-zero such change, and the same change
+ *                 normalised by ||rho^{n-1}||_{2,V}.
+ * The work is enqueued on the context's stream; the call returns after the
+ * stream has completed (it synchronises once per call, not per step).
+ * Errors: UGKS_ENUMERIC (a cell or face density or temperature became
+ * non-positive: the state is left at the last completed step),
+ * UGKS_EHIP, UGKS_EINVAL (n_steps < 0).
+ */
+int ugks_step(ugks_ctx* ctx, int32_t n_steps, double* residual_out);
+
+/*
+ * ugks_moments - macroscopic output (Eq. macro_W).
+ *   which = 0: the conservative state W (the master state), n_cells*(dim+2)
+ *   which = 1: the discrete moments sum_k omega_k psi_k (h, b), n_cells*(dim+2)
+ *   which = 2: the heat flux q of the current distributions (Eq.
+ *              reduced_heat_flux), n_cells*dim
+ *   out           caller buffer in the caller's cell order
+ *   out_on_device 0: host pointer; 1: device pointer
+ */
+int ugks_moments(ugks_ctx* ctx, int32_t which, double* out, int32_t out_on_device);
+
+/*
+ * ugks_get_state / ugks_set_state - checkpoint, restart and warm start.
+ *   W[n_cells*(dim+2)], h[n_cells*nv], b[n_cells*nv] in the caller's cell
+ *   order and the caller's velocity order (padding excluded), FP64 on the
+ *   host.  Any of the three may be NULL (b is ignored in 3-D).  set_state
+ *   rounds h, b to FP32 in the FP32 form.
+ */
+int ugks_get_state(ugks_ctx* ctx, double* W, double* h, double* b);
+int ugks_set_state(ugks_ctx* ctx, const double* W, const double* h, const double* b);
+
+/*
+ * ugks_face_data - diagnostics of the last step, caller face order:
+ *   F[n_faces*(dim+2)] macroscopic time-integrated face fluxes (Eq. macro_flux)
+ *   rho_w[n_faces]     wall densities (Eq. wall_density_condition), 0 off walls
+ * Either pointer may be NULL.  Host buffers.
+ */
+int ugks_face_data(ugks_ctx* ctx, double* F, double* rho_w);
+
+int ugks_info(const ugks_ctx* ctx, ugks_info_t* out);
+
+/* Releases every device buffer; accepts NULL. */
+void ugks_destroy(ugks_ctx* ctx);
+
+/* Reason for the last failure on ctx (NULL: the last failed ugks_create of this thread). */
+const char* ugks_last_error(const ugks_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UGKS_H */

@@ -1,0 +1,602 @@
+// Host side of the gfx950 UGKS library: the C ABI declared in ugks.h.
+//
+// ugks_create validates the mesh and velocity set, renumbers nothing the
+// caller can see (all outputs come back in the caller's order), precomputes
+// the least-squares coefficients of every cell (unweighted, one row per face
+// neighbour or mirror ghost), pads the velocity set with zero-weight points
+// to a multiple of the velocity block, fixes the time step from the CFL bound
+// and allocates every device buffer once.  ugks_step only enqueues kernels.
+#include "ugks_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+
+using namespace ugks;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIP_TRY(call)                              \
+  do {                                             \
+    hipError_t _e = (call);                        \
+    if (_e != hipSuccess) throw HipFail{_e, #call}; \
+  } while (0)
+
+struct InvalidArg {
+  std::string msg;
+};
+
+template <typename T>
+T* dalloc(ugks_ctx* c, size_t n) {
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+  c->allocations.push_back(p);
+  c->bytes += (int64_t)(n * sizeof(T));
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+T* upload(ugks_ctx* c, const std::vector<T>& v) {
+  T* p = dalloc<T>(c, v.size());
+  if (!v.empty()) HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+// Solve the D x D SPD normal system by Cholesky; returns false if singular.
+bool chol_inverse(int D, const double* N, double* Ninv) {
+  double Lm[9] = {0};
+  for (int j = 0; j < D; ++j) {
+    double s = N[j * 3 + j];
+    for (int k = 0; k < j; ++k) s -= Lm[j * 3 + k] * Lm[j * 3 + k];
+    if (!(s > 0.0)) return false;
+    Lm[j * 3 + j] = std::sqrt(s);
+    for (int i = j + 1; i < D; ++i) {
+      double t = N[i * 3 + j];
+      for (int k = 0; k < j; ++k) t -= Lm[i * 3 + k] * Lm[j * 3 + k];
+      Lm[i * 3 + j] = t / Lm[j * 3 + j];
+    }
+  }
+  for (int col = 0; col < D; ++col) {
+    double y[3], x[3];
+    for (int i = 0; i < D; ++i) {
+      double t = (i == col) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= Lm[i * 3 + k] * y[k];
+      y[i] = t / Lm[i * 3 + i];
+    }
+    for (int i = D - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int k = i + 1; k < D; ++k) t -= Lm[k * 3 + i] * x[k];
+      x[i] = t / Lm[i * 3 + i];
+    }
+    for (int i = 0; i < D; ++i) Ninv[i * 3 + col] = x[i];
+  }
+  return true;
+}
+
+void fail_if(bool cond, const std::string& msg) {
+  if (cond) throw InvalidArg{msg};
+}
+
+void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas* gas,
+           const ugks_bc* bcs, int32_t n_bc, const double* W0, const ugks_options* opt) {
+  fail_if(!mesh || !vel || !gas || !W0, "null argument");
+  const int D = mesh->dim;
+  fail_if(D != 2 && D != 3, "mesh.dim must be 2 or 3");
+  if (gas->K != 0) throw std::pair<int, std::string>(UGKS_EUNSUPPORTED, "only K = 0 (monatomic) is supported");
+  const int64_t nc = mesh->n_cells, nf = mesh->n_faces, nv = vel->nv;
+  fail_if(nc <= 0 || nf <= 0 || nv <= 0, "empty mesh or velocity set");
+  fail_if(nc >= (int64_t)INT32_MAX || nf >= (int64_t)INT32_MAX, "mesh too large for 32-bit indices");
+  fail_if(!mesh->cell_volume || !mesh->cell_centroid || !mesh->face_cells || !mesh->face_area ||
+              !mesh->face_normal || !mesh->face_centroid || !mesh->face_bc || !mesh->face_bc_id ||
+              !vel->u || !vel->w,
+          "null mesh or velocity array");
+  fail_if(!(gas->Pr > 0.0) || !(gas->R > 0.0) || !(gas->T_ref > 0.0) || !(gas->mu_ref > 0.0),
+          "gas constants must be positive");
+  int prec = opt && opt->precision ? opt->precision : UGKS_FP64;
+  fail_if(prec != UGKS_FP64 && prec != UGKS_FP32, "precision must be 64 or 32");
+  int Bv = opt && opt->block_v ? opt->block_v : 64;
+  fail_if(Bv % WAVE != 0 || Bv < WAVE || Bv > 1024, "block_v must be a multiple of 64 in [64, 1024]");
+  c->D = D;
+  c->kxi = 3 - D;
+  c->nr = D == 2 ? 2 : 1;
+  c->prec = prec;
+  c->Bv = Bv;
+  c->flags = opt ? opt->flags : 0;
+  c->nc = nc;
+  c->nf = nf;
+  c->nv = nv;
+  c->nvp = (nv + Bv - 1) / Bv * Bv;
+
+  // ---- mesh validation and cell -> face tables --------------------------
+  for (int64_t i = 0; i < nc; ++i)
+    fail_if(!(mesh->cell_volume[i] > 0.0), "non-positive cell volume");
+  std::vector<int32_t> nfc(nc, 0), cface(nc * MAXF, -1), cnbr(nc * MAXF, -1);
+  std::vector<double> csign(nc * MAXF, 0.0);
+  std::vector<int32_t> fL(nf), fR(nf), fbc(nf), fbcid(nf), walls;
+  std::vector<double> farea(nf), fnorm(nf * 3, 0.0), fdxL(nf * 3, 0.0), fdxR(nf * 3, 0.0),
+      fmir(nf * 3, 0.0);
+  std::vector<double> cen(nc * 3, 0.0);
+  for (int64_t i = 0; i < nc; ++i)
+    for (int d = 0; d < D; ++d) cen[i * 3 + d] = mesh->cell_centroid[i * D + d];
+  std::vector<double> closure(nc * 3, 0.0), asum(nc, 0.0);
+  for (int64_t f = 0; f < nf; ++f) {
+    int64_t L = mesh->face_cells[2 * f], R = mesh->face_cells[2 * f + 1];
+    int kind = mesh->face_bc[f];
+    fail_if(L < 0 || L >= nc, "face_cells L out of range");
+    fail_if(kind < 0 || kind > 3, "unknown face_bc");
+    fail_if(kind == UGKS_BC_INTERIOR && (R < 0 || R >= nc || R == L), "interior face needs a distinct R");
+    fail_if(kind != UGKS_BC_INTERIOR && R != -1, "boundary face must have R = -1");
+    fail_if(!(mesh->face_area[f] > 0.0), "non-positive face area");
+    double nn = 0.0;
+    for (int d = 0; d < D; ++d) nn += mesh->face_normal[f * D + d] * mesh->face_normal[f * D + d];
+    fail_if(std::fabs(nn - 1.0) > 1e-10, "face normal is not a unit vector");
+    if (kind != UGKS_BC_INTERIOR) {
+      int id = mesh->face_bc_id[f];
+      fail_if(id < 0 || id >= n_bc || !bcs, "face_bc_id out of range");
+      fail_if(bcs[id].kind != kind, "face_bc does not match the boundary table kind");
+      if (kind == UGKS_BC_WALL) {
+        double un = 0.0;
+        for (int d = 0; d < D; ++d) un += bcs[id].U[d] * mesh->face_normal[f * D + d];
+        fail_if(std::fabs(un) > 1e-12, "wall velocity must be tangential");
+        walls.push_back((int32_t)f);
+      }
+    }
+    fL[f] = (int32_t)L;
+    fR[f] = (int32_t)R;
+    fbc[f] = kind;
+    fbcid[f] = mesh->face_bc_id[f];
+    farea[f] = mesh->face_area[f];
+    double dn = 0.0;
+    for (int d = 0; d < D; ++d) {
+      double n = mesh->face_normal[f * D + d];
+      double xf = mesh->face_centroid[f * D + d];
+      double sh = mesh->face_shift ? mesh->face_shift[f * D + d] : 0.0;
+      fnorm[f * 3 + d] = n;
+      fdxL[f * 3 + d] = xf - cen[L * 3 + d];
+      if (R >= 0) fdxR[f * 3 + d] = xf - sh - cen[R * 3 + d];
+      dn += (xf - cen[L * 3 + d]) * n;
+    }
+    for (int d = 0; d < D; ++d) fmir[f * 3 + d] = 2.0 * dn * fnorm[f * 3 + d];
+    auto add = [&](int64_t cell, int64_t nb, double s) {
+      fail_if(nfc[cell] >= MAXF, "a cell has more than 8 faces");
+      int p = nfc[cell]++;
+      cface[cell * MAXF + p] = (int32_t)f;
+      cnbr[cell * MAXF + p] = (int32_t)nb;
+      csign[cell * MAXF + p] = s;
+      for (int d = 0; d < D; ++d) closure[cell * 3 + d] += s * farea[f] * fnorm[f * 3 + d];
+      asum[cell] += farea[f];
+    };
+    add(L, R, 1.0);
+    if (R >= 0) add(R, L, -1.0);
+  }
+  for (int64_t i = 0; i < nc; ++i) {
+    fail_if(nfc[i] < D + 1, "a cell has fewer than D+1 faces");
+    double cl = 0.0;
+    for (int d = 0; d < D; ++d) cl += closure[i * 3 + d] * closure[i * 3 + d];
+    fail_if(std::sqrt(cl) > 1e-9 * asum[i], "a cell is not closed (sum S n != 0)");
+  }
+  // ---- least-squares coefficients --------------------------------------
+  std::vector<double> lsG(nc * 3 * MAXF, 0.0);
+  for (int64_t i = 0; i < nc; ++i) {
+    double off[MAXF][3] = {{0}};
+    for (int p = 0; p < nfc[i]; ++p) {
+      int f = cface[i * MAXF + p];
+      int j = cnbr[i * MAXF + p];
+      for (int d = 0; d < D; ++d) {
+        if (j >= 0) {
+          // offset to the neighbour's centroid (periodic image for a shifted face)
+          double sh = mesh->face_shift ? mesh->face_shift[f * D + d] : 0.0;
+          double s = csign[i * MAXF + p];
+          off[p][d] = cen[j * 3 + d] + s * sh - cen[i * 3 + d];
+        } else {
+          off[p][d] = fmir[f * 3 + d];
+        }
+      }
+    }
+    double N[9] = {0}, Ni[9];
+    for (int p = 0; p < nfc[i]; ++p)
+      for (int r = 0; r < D; ++r)
+        for (int s = 0; s < D; ++s) N[r * 3 + s] += off[p][r] * off[p][s];
+    fail_if(!chol_inverse(D, N, Ni), "degenerate least-squares stencil");
+    for (int d = 0; d < D; ++d)
+      for (int p = 0; p < nfc[i]; ++p) {
+        double s = 0.0;
+        for (int e = 0; e < D; ++e) s += Ni[d * 3 + e] * off[p][e];
+        lsG[(i * 3 + d) * MAXF + p] = s;
+      }
+  }
+  // ---- velocity set -----------------------------------------------------
+  const int64_t nvp = c->nvp;
+  std::vector<double> u(3 * nvp, 0.0), w(nvp, 0.0), u2(nvp, 0.0);
+  for (int64_t k = 0; k < nv; ++k) {
+    fail_if(!(vel->w[k] > 0.0), "velocity weights must be positive");
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) {
+      double x = vel->u[k * D + d];
+      fail_if(!std::isfinite(x), "non-finite velocity");
+      u[d * nvp + k] = x;
+      s += x * x;
+    }
+    w[k] = vel->w[k];
+    u2[k] = s;
+  }
+  // ---- initial state check ---------------------------------------------
+  for (int64_t i = 0; i < nc; ++i) {
+    const double* Wi = &W0[i * (D + 2)];
+    double rho = Wi[0], m2 = 0.0;
+    for (int d = 0; d < D; ++d) m2 += Wi[1 + d] * Wi[1 + d];
+    fail_if(!(rho > 0.0), "initial density must be positive");
+    fail_if(!(Wi[D + 1] - 0.5 * m2 / rho > 0.0), "initial internal energy must be positive");
+  }
+  // ---- stream -------------------------------------------------------------
+  if (opt && opt->stream) {
+    c->stream = (hipStream_t)opt->stream;
+    c->own_stream = false;
+  } else {
+    HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  // ---- device buffers ---------------------------------------------------
+  DevMesh& m = c->mesh;
+  m.nc = nc;
+  m.nf = nf;
+  m.vol = upload(c, std::vector<double>(mesh->cell_volume, mesh->cell_volume + nc));
+  m.cen = upload(c, cen);
+  m.nfc = upload(c, nfc);
+  m.cface = upload(c, cface);
+  m.cnbr = upload(c, cnbr);
+  m.csign = upload(c, csign);
+  m.lsG = upload(c, lsG);
+  m.fL = upload(c, fL);
+  m.fR = upload(c, fR);
+  m.fbc = upload(c, fbc);
+  m.fbcid = upload(c, fbcid);
+  m.farea = upload(c, farea);
+  m.fnorm = upload(c, fnorm);
+  m.fdxL = upload(c, fdxL);
+  m.fdxR = upload(c, fdxR);
+  m.fmir = upload(c, fmir);
+  m.walls = upload(c, walls);
+  m.nwall = (int64_t)walls.size();
+  DevVel& v = c->vel;
+  v.nv = nv;
+  v.nvp = nvp;
+  v.u = upload(c, u);
+  v.w = upload(c, w);
+  v.u2 = upload(c, u2);
+  std::vector<DevBC> hb(std::max(n_bc, 1));
+  for (int i = 0; i < n_bc; ++i) {
+    hb[i].kind = bcs[i].kind;
+    hb[i].rho = bcs[i].rho;
+    for (int d = 0; d < 3; ++d) hb[i].U[d] = bcs[i].U[d];
+    hb[i].T = bcs[i].T;
+    fail_if(bcs[i].kind != UGKS_BC_OUTFLOW && !(bcs[i].T > 0.0), "boundary temperature must be positive");
+  }
+  c->bcs = upload(c, hb);
+  c->cell_perm.resize(nc);
+  for (int64_t i = 0; i < nc; ++i) c->cell_perm[i] = i;
+  c->face_perm.resize(nf);
+  for (int64_t f = 0; f < nf; ++f) c->face_perm[f] = f;
+
+  StepBuffers& B = c->buf;
+  const size_t esz = prec == UGKS_FP32 ? sizeof(float) : sizeof(double);
+  const int NW = D + 2;
+  B.W = dalloc<double>(c, nc * NW);
+  B.Wn = dalloc<double>(c, nc * NW);
+  B.prim = dalloc<double>(c, nc * NPRIM);
+  B.primn = dalloc<double>(c, nc * NPRIM);
+  B.q = dalloc<double>(c, nc * 3);
+  B.gW = dalloc<double>(c, nc * 15);
+  B.frec = dalloc<double>(c, nf * FREC);
+  B.F = dalloc<double>(c, nf * 5);
+  B.h = dalloc<char>(c, (size_t)nc * nvp * esz);
+  B.ht = dalloc<char>(c, (size_t)nc * nvp * esz);
+  B.b = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)nc * nvp * esz) : nullptr;
+  B.bt = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)nc * nvp * esz) : nullptr;
+  B.gradh = dalloc<double>(c, (size_t)nc * 3 * nvp);
+  B.gradb = c->nr == 2 ? dalloc<double>(c, (size_t)nc * 3 * nvp) : nullptr;
+  B.fluxh = dalloc<double>(c, (size_t)nf * nvp);
+  B.fluxb = c->nr == 2 ? dalloc<double>(c, (size_t)nf * nvp) : nullptr;
+  B.resid = dalloc<double>(c, 8);
+  B.cellred = dalloc<double>(c, nc * 3);
+  B.flag = dalloc<int32_t>(c, 4);
+  HIP_TRY(hipMemsetAsync(B.frec, 0, nf * FREC * sizeof(double), c->stream));
+  HIP_TRY(hipMemsetAsync(B.resid, 0, 8 * sizeof(double), c->stream));
+  HIP_TRY(hipMemsetAsync(B.flag, 0, 4 * sizeof(int32_t), c->stream));
+  HIP_TRY(hipMemsetAsync(B.q, 0, nc * 3 * sizeof(double), c->stream));
+  HIP_TRY(hipMemcpyAsync(B.W, W0, nc * NW * sizeof(double), hipMemcpyHostToDevice, c->stream));
+
+  // ---- time step ----------------------------------------------------------
+  c->gas.Pr = gas->Pr;
+  c->gas.R = gas->R;
+  c->gas.Tref = gas->T_ref;
+  c->gas.muref = gas->mu_ref;
+  c->gas.omega = gas->omega;
+  if (gas->dt > 0.0) {
+    c->gas.dt = gas->dt;
+  } else {
+    fail_if(!(gas->cfl > 0.0), "cfl must be positive when dt = 0");
+    double* cellv = dalloc<double>(c, nc);
+    HIP_TRY(launch_dt_cells(D, m, v, cellv, c->stream));
+    std::vector<double> hc(nc);
+    HIP_TRY(hipMemcpyAsync(hc.data(), cellv, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double mn = INFINITY;
+    for (double x : hc) mn = std::min(mn, x);
+    fail_if(!(mn > 0.0) || !std::isfinite(mn), "could not derive a time step");
+    c->gas.dt = gas->cfl * mn;
+  }
+  // ---- initial distributions: the reduced Maxwellian of W0 ---------------
+  HIP_TRY(launch_prims(D, m, c->gas, B.W, B.prim, B.flag, 0, c->stream));
+  HIP_TRY(launch_init_maxwellian(D, prec, m, v, B.prim, B.h, B.b, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+}
+
+int set_err(ugks_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+// One time step, enqueued (the one-step algorithm).
+void enqueue_step(ugks_ctx* c) {
+  const int D = c->D, P = c->prec;
+  const DevMesh& m = c->mesh;
+  const DevVel& v = c->vel;
+  const GasP& g = c->gas;
+  StepBuffers& B = c->buf;
+  hipStream_t s = c->stream;
+  // 1-2 primitives and heat flux of the current state
+  HIP_TRY(launch_prims(D, m, g, B.W, B.prim, B.flag, 1, s));
+  HIP_TRY(launch_heatflux(D, P, m, v, B.h, B.b, B.prim, B.q, B.flag, s));
+  // 3-4 ghost states and macroscopic reconstruction
+  HIP_TRY(launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
+  // 6.1-6.6 interface equilibrium data
+  HIP_TRY(launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
+  // 5 microscopic reconstruction
+  HIP_TRY(launch_grad_micro(D, P, m, v, B.frec, B.h, B.b, B.gradh, B.gradb, B.flag, s));
+  // 7 wall densities
+  HIP_TRY(launch_wall_rho(D, P, m, v, g, B.h, B.gradh, B.frec, B.flag, s));
+  // 6.7-6.8 microscopic fluxes and their moments
+  HIP_TRY(launch_flux(D, P, m, v, g, B.frec, B.h, B.b, B.gradh, B.gradb, B.fluxh, B.fluxb, B.F,
+                      B.flag, s));
+  // 9 first stage
+  HIP_TRY(launch_stage1(D, P, m, v, g, B.prim, B.q, B.h, B.b, B.fluxh, B.fluxb, B.ht, B.bt,
+                        B.flag, s));
+  // 8 conservative update, 10 new equilibrium
+  HIP_TRY(launch_macro_update(D, m, B.W, B.F, B.Wn, B.cellred, B.flag, s));
+  HIP_TRY(launch_prims(D, m, g, B.Wn, B.primn, B.flag, 1, s));
+  // 11 second stage
+  HIP_TRY(launch_stage2(D, P, m, v, g, B.primn, B.q, B.ht, B.bt, B.h, B.b, B.flag, s));
+  // 12 residual, commit W^{n+1}
+  if (!(c->flags & 1)) HIP_TRY(launch_residual(m, B.cellred, B.resid, B.flag, s));
+  HIP_TRY(launch_commit_W(D, m, B.Wn, B.W, B.flag, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+int ugks_create(const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas* gas,
+                const ugks_bc* bcs, int32_t n_bc, const double* W0, const ugks_options* opt,
+                ugks_ctx** out) {
+  if (!out) return set_err(nullptr, UGKS_EINVAL, "out is NULL");
+  std::unique_ptr<ugks_ctx> c(new ugks_ctx());
+  try {
+    build(c.get(), mesh, vel, gas, bcs, n_bc, W0, opt);
+  } catch (const InvalidArg& e) {
+    ugks_destroy(c.release());
+    return set_err(nullptr, UGKS_EINVAL, e.msg);
+  } catch (const std::pair<int, std::string>& e) {
+    ugks_destroy(c.release());
+    return set_err(nullptr, e.first, e.second);
+  } catch (const HipFail& e) {
+    ugks_destroy(c.release());
+    int code = (e.e == hipErrorOutOfMemory) ? UGKS_ENOMEM : UGKS_EHIP;
+    return set_err(nullptr, code, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  *out = c.release();
+  return UGKS_OK;
+}
+
+int ugks_step(ugks_ctx* c, int32_t n_steps, double* residual_out) {
+  if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
+  if (n_steps < 0) return set_err(c, UGKS_EINVAL, "n_steps < 0");
+  try {
+    for (int32_t s = 0; s < n_steps; ++s) enqueue_step(c);
+    int32_t flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, c->buf.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    double res[2] = {0.0, 0.0};
+    if (residual_out)
+      HIP_TRY(hipMemcpyAsync(res, c->buf.resid, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (flag) {
+      // leave the flag set: the state is the last completed step and further
+      // steps would repeat the failure
+      return set_err(c, UGKS_ENUMERIC, "non-positive density or temperature (flag " +
+                                           std::to_string(flag) + ")");
+    }
+    c->steps_done += n_steps;
+    if (residual_out) {
+      residual_out[0] = res[0];
+      residual_out[1] = res[1];
+    }
+  } catch (const HipFail& e) {
+    return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return UGKS_OK;
+}
+
+int ugks_moments(ugks_ctx* c, int32_t which, double* out, int32_t on_device) {
+  if (!c || !out) return set_err(c, UGKS_EINVAL, "null argument");
+  const int D = c->D;
+  try {
+    int64_t ncol = which == 2 ? D : D + 2;
+    std::vector<double> lib(c->nc * (which == 2 ? 3 : ncol));
+    if (which == 0) {
+      HIP_TRY(hipMemcpyAsync(lib.data(), c->buf.W, c->nc * ncol * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    } else if (which == 1) {
+      double* tmp = c->buf.cellred;  // reuse: needs nc*(D+2) <= nc*3? no: use Wn scratch
+      tmp = c->buf.Wn;
+      HIP_TRY(launch_moments(D, c->prec, c->mesh, c->vel, c->buf.h, c->buf.b, tmp, c->stream));
+      HIP_TRY(hipMemcpyAsync(lib.data(), tmp, c->nc * ncol * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    } else if (which == 2) {
+      HIP_TRY(launch_prims(D, c->mesh, c->gas, c->buf.W, c->buf.prim, c->buf.flag, 0, c->stream));
+      HIP_TRY(launch_heatflux(D, c->prec, c->mesh, c->vel, c->buf.h, c->buf.b, c->buf.prim, c->buf.q,
+                              c->buf.flag, c->stream));
+      HIP_TRY(hipMemcpyAsync(lib.data(), c->buf.q, c->nc * 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    } else {
+      return set_err(c, UGKS_EINVAL, "which must be 0, 1 or 2");
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<double> user(c->nc * ncol);
+    int64_t stride = which == 2 ? 3 : ncol;
+    for (int64_t i = 0; i < c->nc; ++i)
+      for (int64_t x = 0; x < ncol; ++x) user[c->cell_perm[i] * ncol + x] = lib[i * stride + x];
+    if (on_device)
+      HIP_TRY(hipMemcpy(out, user.data(), user.size() * sizeof(double), hipMemcpyHostToDevice));
+    else
+      std::memcpy(out, user.data(), user.size() * sizeof(double));
+  } catch (const HipFail& e) {
+    return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return UGKS_OK;
+}
+
+int ugks_get_state(ugks_ctx* c, double* W, double* h, double* b) {
+  if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
+  try {
+    const int64_t nc = c->nc, nv = c->nv, nvp = c->nvp;
+    if (W) {
+      int rc = ugks_moments(c, 0, W, 0);
+      if (rc) return rc;
+    }
+    void* src[2] = {c->buf.h, c->buf.b};
+    double* dst[2] = {h, b};
+    for (int r = 0; r < 2; ++r) {
+      if (!dst[r]) continue;
+      if (r == 1 && c->nr == 1) {
+        std::fill(b, b + nc * nv, 0.0);
+        continue;
+      }
+      if (c->prec == UGKS_FP32) {
+        std::vector<float> tmp(nc * nvp);
+        HIP_TRY(hipMemcpy(tmp.data(), src[r], tmp.size() * sizeof(float), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < nc; ++i)
+          for (int64_t k = 0; k < nv; ++k) dst[r][c->cell_perm[i] * nv + k] = tmp[i * nvp + k];
+      } else {
+        std::vector<double> tmp(nc * nvp);
+        HIP_TRY(hipMemcpy(tmp.data(), src[r], tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < nc; ++i)
+          for (int64_t k = 0; k < nv; ++k) dst[r][c->cell_perm[i] * nv + k] = tmp[i * nvp + k];
+      }
+    }
+  } catch (const HipFail& e) {
+    return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return UGKS_OK;
+}
+
+int ugks_set_state(ugks_ctx* c, const double* W, const double* h, const double* b) {
+  if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
+  try {
+    const int64_t nc = c->nc, nv = c->nv, nvp = c->nvp;
+    const int NW = c->D + 2;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (W) {
+      std::vector<double> lib(nc * NW);
+      for (int64_t i = 0; i < nc; ++i)
+        for (int x = 0; x < NW; ++x) lib[i * NW + x] = W[c->cell_perm[i] * NW + x];
+      HIP_TRY(hipMemcpy(c->buf.W, lib.data(), lib.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    void* dst[2] = {c->buf.h, c->buf.b};
+    const double* src[2] = {h, b};
+    for (int r = 0; r < c->nr; ++r) {
+      if (!src[r]) continue;
+      if (c->prec == UGKS_FP32) {
+        std::vector<float> tmp(nc * nvp, 0.0f);
+        for (int64_t i = 0; i < nc; ++i)
+          for (int64_t k = 0; k < nv; ++k) tmp[i * nvp + k] = (float)src[r][c->cell_perm[i] * nv + k];
+        HIP_TRY(hipMemcpy(dst[r], tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice));
+      } else {
+        std::vector<double> tmp(nc * nvp, 0.0);
+        for (int64_t i = 0; i < nc; ++i)
+          for (int64_t k = 0; k < nv; ++k) tmp[i * nvp + k] = src[r][c->cell_perm[i] * nv + k];
+        HIP_TRY(hipMemcpy(dst[r], tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
+      }
+    }
+    // a new state restarts the residual normalisation and clears a failure
+    HIP_TRY(hipMemset(c->buf.resid, 0, 8 * sizeof(double)));
+    HIP_TRY(hipMemset(c->buf.flag, 0, 4 * sizeof(int32_t)));
+  } catch (const HipFail& e) {
+    return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return UGKS_OK;
+}
+
+int ugks_face_data(ugks_ctx* c, double* F, double* rho_w) {
+  if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
+  try {
+    const int64_t nf = c->nf;
+    const int NW = c->D + 2;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (F) {
+      std::vector<double> lib(nf * 5);
+      HIP_TRY(hipMemcpy(lib.data(), c->buf.F, lib.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int64_t f = 0; f < nf; ++f)
+        for (int x = 0; x < NW; ++x) F[c->face_perm[f] * NW + x] = lib[f * 5 + x];
+    }
+    if (rho_w) {
+      std::vector<double> lib(nf * FREC);
+      HIP_TRY(hipMemcpy(lib.data(), c->buf.frec, lib.size() * sizeof(double), hipMemcpyDeviceToHost));
+      std::vector<int32_t> kind(nf);
+      HIP_TRY(hipMemcpy(kind.data(), c->mesh.fbc, nf * sizeof(int32_t), hipMemcpyDeviceToHost));
+      for (int64_t f = 0; f < nf; ++f)
+        rho_w[c->face_perm[f]] = kind[f] == UGKS_BC_WALL ? lib[f * FREC + FR_RHOW] : 0.0;
+    }
+  } catch (const HipFail& e) {
+    return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return UGKS_OK;
+}
+
+int ugks_info(const ugks_ctx* c, ugks_info_t* out) {
+  if (!c || !out) return UGKS_EINVAL;
+  out->dim = c->D;
+  out->n_r = c->nr;
+  out->precision = c->prec;
+  out->block_v = c->Bv;
+  out->n_cells = c->nc;
+  out->n_faces = c->nf;
+  out->nv = c->nv;
+  out->nv_padded = c->nvp;
+  out->dt = c->gas.dt;
+  out->steps_done = c->steps_done;
+  out->device_bytes = c->bytes;
+  return UGKS_OK;
+}
+
+void ugks_destroy(ugks_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->allocations) (void)hipFree(p);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* ugks_last_error(const ugks_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Internal declarations of the gfx950 UGKS library: the context, device
+// records and the kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ugks.h"
+
+namespace ugks {
+
+constexpr int MAXF = 8;    // faces per cell
+constexpr int NPRIM = 8;   // rho, U[3], lambda, tau, p, spare
+constexpr int FREC = 48;   // doubles per face record
+constexpr int WAVE = 64;
+
+// Face record layout (doubles).  Interior / far-field faces hold the
+// interface equilibrium data; wall faces hold the wall Maxwellian data.
+enum FaceRec : int {
+  FR_C0 = 0,     // rho0 (lambda0/pi)^(D/2)   | wall: (lambda_w/pi)^(D/2)
+  FR_LAM = 1,    // lambda0                    | wall: lambda_w
+  FR_U = 2,      // U0[3]                      | wall: U_w[3]
+  FR_SH = 5,     // 4 (1-Pr) lambda0^2 / (5 rho0)
+  FR_Q = 6,      // q0[3]
+  FR_G = 9,      // Gamma_1..5
+  FR_A = 14,     // a[d][0..4], d < 3 (15)
+  FR_AT = 29,    // A[0..4]
+  FR_RHOW = 34,  // wall: rho_w (written by the wall pass)
+  FR_GRHO = 35,  // ghost: rho_g, U_g[3], lambda_g (far field / outflow)
+  FR_GU = 36,
+  FR_GLAM = 39,
+  FR_GC = 40,    // ghost: rho_g (lambda_g/pi)^(D/2)
+};
+
+struct DevMesh {
+  int64_t nc, nf;
+  // cells
+  const double* vol;        // [nc]
+  const double* cen;        // [nc*3]
+  const int32_t* nfc;       // [nc] faces per cell
+  const int32_t* cface;     // [nc*MAXF] face ids
+  const int32_t* cnbr;      // [nc*MAXF] neighbour cell, -1 for a boundary face
+  const double* csign;      // [nc*MAXF] +1 if the cell is L of the face, -1 if R
+  const double* lsG;        // [nc*3*MAXF] least-squares coefficients G[d][p]
+  // faces
+  const int32_t* fL;        // [nf]
+  const int32_t* fR;        // [nf] (-1 boundary)
+  const int32_t* fbc;       // [nf]
+  const int32_t* fbcid;     // [nf]
+  const double* farea;      // [nf]
+  const double* fnorm;      // [nf*3]
+  const double* fdxL;       // [nf*3] x_f - x_L
+  const double* fdxR;       // [nf*3] x_f - shift - x_R
+  const double* fmir;       // [nf*3] mirror ghost offset from L: 2((x_f-x_L).n) n
+  const int32_t* walls;     // [nwall] ids of the wall faces
+  int64_t nwall;
+};
+
+struct DevVel {
+  int64_t nv, nvp;          // true and padded counts
+  const double* u;          // [3*nvp] SoA: u[d*nvp + k]
+  const double* w;          // [nvp]
+  const double* u2;         // [nvp]
+};
+
+struct DevBC {
+  int32_t kind;
+  double rho, U[3], T;
+};
+
+struct GasP {
+  double Pr, R, Tref, muref, omega, dt;
+};
+
+// Kernel launchers (ugks_kernels.hip).  Each returns hipGetLastError().
+struct StepBuffers {
+  double* W;       // [nc*(D+2)] state W^n
+  double* Wn;      // [nc*(D+2)] W^{n+1}
+  double* prim;    // [nc*NPRIM] of W^n
+  double* primn;   // [nc*NPRIM] of W^{n+1}
+  double* q;       // [nc*3] heat flux of h^n
+  double* gW;      // [nc*3*5]
+  double* frec;    // [nf*FREC]
+  double* F;       // [nf*5]
+  void* h;         // [nc*nvp] storage type
+  void* b;         // [nc*nvp] (2-D only)
+  void* ht;        // [nc*nvp] first-stage result
+  void* bt;
+  double* gradh;   // [nc*3*nvp] microscopic gradients (staged sweep)
+  double* gradb;
+  double* fluxh;   // [nf*nvp] time-integrated microscopic fluxes (staged sweep)
+  double* fluxb;
+  double* resid;   // [8] residual accumulators and state
+  double* cellred; // [nc*3] per-cell residual contributions
+  int32_t* flag;   // numeric error flag
+};
+
+hipError_t launch_prims(int D, const DevMesh& m, const GasP& g, const double* W, double* prim,
+                        int32_t* flag, int checkflag, hipStream_t s);
+hipError_t launch_heatflux(int D, int prec, const DevMesh& m, const DevVel& v, const void* h,
+                           const void* b, const double* prim, double* q, const int32_t* flag,
+                           hipStream_t s);
+hipError_t launch_gradW(int D, const DevMesh& m, const DevBC* bcs, const GasP& g, const double* W,
+                        double* gW, const int32_t* flag, hipStream_t s);
+hipError_t launch_face_eq(int D, const DevMesh& m, const DevBC* bcs, const GasP& g,
+                          const double* W, const double* gW, const double* q, double* frec,
+                          int32_t* flag, hipStream_t s);
+hipError_t launch_grad_micro(int D, int prec, const DevMesh& m, const DevVel& v,
+                             const double* frec, const void* h, const void* b, double* gh,
+                             double* gb, const int32_t* flag, hipStream_t s);
+hipError_t launch_wall_rho(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
+                           const void* h, const double* gh, double* frec, const int32_t* flag,
+                           hipStream_t s);
+hipError_t launch_flux(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
+                       const double* frec, const void* h, const void* b, const double* gh,
+                       const double* gb, double* fh, double* fb, double* F, const int32_t* flag,
+                       hipStream_t s);
+hipError_t launch_stage1(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
+                         const double* prim, const double* q, const void* h, const void* b,
+                         const double* fh, const double* fb, void* ht, void* bt,
+                         const int32_t* flag, hipStream_t s);
+hipError_t launch_macro_update(int D, const DevMesh& m, const double* W, const double* F,
+                               double* Wn, double* cellred, const int32_t* flag, hipStream_t s);
+hipError_t launch_stage2(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
+                         const double* primn, const double* q, const void* ht, const void* bt,
+                         void* h, void* b, const int32_t* flag, hipStream_t s);
+hipError_t launch_residual(const DevMesh& m, const double* cellred, double* resid,
+                           const int32_t* flag, hipStream_t s);
+hipError_t launch_commit_W(int D, const DevMesh& m, const double* Wn, double* W,
+                           const int32_t* flag, hipStream_t s);
+hipError_t launch_init_maxwellian(int D, int prec, const DevMesh& m, const DevVel& v,
+                                  const double* prim, void* h, void* b, hipStream_t s);
+hipError_t launch_moments(int D, int prec, const DevMesh& m, const DevVel& v, const void* h,
+                          const void* b, double* out, hipStream_t s);
+hipError_t launch_dt_cells(int D, const DevMesh& m, const DevVel& v, double* cellval,
+                           hipStream_t s);
+
+}  // namespace ugks
+
+struct ugks_ctx {
+  int D = 0, kxi = 0, nr = 0, prec = 64, Bv = 64, flags = 0;
+  int64_t nc = 0, nf = 0, nv = 0, nvp = 0;
+  int64_t steps_done = 0;
+  ugks::GasP gas{};
+  std::vector<int64_t> cell_perm;   // library cell c -> caller cell
+  std::vector<int64_t> face_perm;   // library face f -> caller face
+  std::vector<int64_t> vel_perm;    // library velocity k -> caller velocity (k < nv)
+  ugks::DevMesh mesh{};
+  ugks::DevVel vel{};
+  ugks::DevBC* bcs = nullptr;
+  ugks::StepBuffers buf{};
+  std::vector<void*> allocations;
+  int64_t bytes = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+};

@@ -1,0 +1,1032 @@
+// gfx950 kernels of the UGKS phase-space step (staged form).
+//
+// Each kernel is one numbered part of the one-step algorithm (Sec. 2.2) for
+// the BGK-Shakhov model of Sec. 2.1.  Velocity is the fast (lane) index:
+// h is stored [cell][k] with k contiguous, so every per-(cell, velocity)
+// kernel issues coalesced 64-lane loads and stores, and every per-face or
+// per-cell quantity (geometry, interface coefficients) is wave-uniform.
+// Sums over velocity use wave shuffles plus LDS in a fixed order, so the
+// results are deterministic.
+#include "ugks_internal.h"
+
+#include <cmath>
+
+namespace ugks {
+
+namespace {
+
+constexpr int TPB = 256;  // threads per block for velocity-parallel kernels
+
+template <typename T>
+__device__ __forceinline__ double ld(const T* p, int64_t i) {
+  return static_cast<double>(p[i]);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* p, int64_t i, double v) {
+  p[i] = static_cast<T>(v);
+}
+
+// (lambda/pi)^(D/2)
+template <int D>
+__device__ __forceinline__ double maxw_norm(double lam) {
+  double r = lam * M_1_PI;
+  if constexpr (D == 2) return r;
+  else return r * sqrt(r);
+}
+
+// Primitive variables of a conservative state (monatomic, K = 0):
+// lambda = 3 rho / (4 (rho E - rho|U|^2/2)), p = rho/(2 lambda),
+// T = 1/(2 R lambda), tau = mu(T)/p with mu = mu_ref (T/T_ref)^omega.
+template <int D>
+__device__ __forceinline__ bool prim_of(const double* W, const GasP& g, double* P) {
+  double rho = W[0];
+  double u2 = 0.0;
+  double U[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < D; ++d) {
+    U[d] = W[1 + d] / rho;
+    u2 += U[d] * U[d];
+  }
+  double eint = W[D + 1] - 0.5 * rho * u2;
+  double lam = 3.0 * rho / (4.0 * eint);
+  double p = rho / (2.0 * lam);
+  double T = 1.0 / (2.0 * g.R * lam);
+  double tau = g.muref * pow(T / g.Tref, g.omega) / p;
+  P[0] = rho;
+  P[1] = U[0];
+  P[2] = U[1];
+  P[3] = U[2];
+  P[4] = lam;
+  P[5] = tau;
+  P[6] = p;
+  P[7] = 0.0;
+  return (rho > 0.0) && (eint > 0.0) && isfinite(lam) && isfinite(tau);
+}
+
+// Conservative state of (rho, U, T) for a monatomic gas.
+template <int D>
+__device__ __forceinline__ void cons_of(double rho, const double* U, double T, double R, double* W) {
+  double u2 = 0.0;
+  W[0] = rho;
+  for (int d = 0; d < D; ++d) {
+    W[1 + d] = rho * U[d];
+    u2 += U[d] * U[d];
+  }
+  W[D + 1] = 0.5 * rho * u2 + 1.5 * rho * R * T;
+}
+
+// Far-field / outflow ghost state: free stream when it enters through the
+// face, otherwise the interior state.
+template <int D>
+__device__ __forceinline__ void ghost_state(int kind, const DevBC& bc, const double* n,
+                                            const double* Wi, double R, double* Wg) {
+  bool inflow = false;
+  if (kind == UGKS_BC_FARFIELD) {
+    double un = 0.0;
+    for (int d = 0; d < D; ++d) un += bc.U[d] * n[d];
+    inflow = un < 0.0;
+  }
+  if (inflow) {
+    cons_of<D>(bc.rho, bc.U, bc.T, R, Wg);
+  } else {
+    for (int v = 0; v < D + 2; ++v) Wg[v] = Wi[v];
+  }
+}
+
+// Reduce N per-thread values over a block of TPB threads; the result is
+// valid in thread 0.  Fixed order: wave shuffle tree, then waves in order.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double* lds) {
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) v[n] += __shfl_down(v[n], off, WAVE);
+  }
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int nw = blockDim.x / WAVE;
+  if (lane == 0)
+#pragma unroll
+    for (int n = 0; n < N; ++n) lds[n * 16 + wv] = v[n];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      double s = lds[n * 16];
+      for (int w = 1; w < nw; ++w) s += lds[n * 16 + w];
+      v[n] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ double block_max(double v, double* lds) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, WAVE));
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) v = fmax(v, lds[w]);
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Interface equilibrium (steps 6.1-6.6)
+
+// Half-range moments <u_n^m>_{s}, m = 0, 1, 2, of a unit-density 1-D
+// Maxwellian with mean Un; s = +1 for u_n > 0, -1 for u_n < 0.
+__device__ __forceinline__ void half_range(double Un, double lam, double s, double* m) {
+  double sl = sqrt(lam);
+  m[0] = 0.5 * erfc(-s * sl * Un);
+  m[1] = Un * m[0] + s * exp(-lam * Un * Un) / (2.0 * sqrt(M_PI * lam));
+  m[2] = Un * m[1] + m[0] / (2.0 * lam);
+}
+
+// Solve E[psi psi^T] a = b for a Maxwellian (U, lam) with 3 translational plus
+// internal degrees of freedom, by elimination of a_0, a_j, a_E.
+template <int D>
+__device__ __forceinline__ void slope_solve(const double* b, const double* U, double lam, double* a) {
+  const double N = 3.0;
+  double UU = 0.0, UR = 0.0, Rj[3];
+  for (int d = 0; d < D; ++d) {
+    UU += U[d] * U[d];
+    Rj[d] = b[1 + d] - U[d] * b[0];
+    UR += U[d] * Rj[d];
+  }
+  double e2 = UU + N / (2.0 * lam);
+  double RE = 2.0 * b[D + 1] - e2 * b[0];
+  double aE = 4.0 * lam * lam / N * (RE - 2.0 * UR);
+  double a0 = b[0] - 0.5 * aE * e2;
+  for (int d = 0; d < D; ++d) {
+    double aj = 2.0 * lam * Rj[d] - U[d] * aE;
+    a[1 + d] = aj;
+    a0 -= U[d] * aj;
+  }
+  a[0] = a0;
+  a[D + 1] = aE;
+}
+
+// Gaussian moment tables for the time slope.
+template <int D>
+struct Moments {
+  double m[3][6];   // E[u_d^n], n <= 5 (m[d][0] = 1; unused dims are delta at 0)
+  double x1, x2;    // E[xi^2], E[xi^4]
+  __device__ void init(const double* U, double lam) {
+    double var = 1.0 / (2.0 * lam);
+    for (int d = 0; d < 3; ++d) {
+      double mu = d < D ? U[d] : 0.0;
+      m[d][0] = 1.0;
+      m[d][1] = mu;
+      for (int n = 1; n < 5; ++n) m[d][n + 1] = mu * m[d][n] + n * var * m[d][n - 1];
+      if (d >= D)
+        for (int n = 1; n < 6; ++n) m[d][n] = 0.0;
+    }
+    const int kxi = 3 - D;
+    x1 = kxi * var;
+    x2 = kxi * (kxi + 2.0) * var * var;
+  }
+  // E[u^e] for an exponent vector
+  __device__ double E(int e0, int e1, int e2) const { return m[0][e0] * m[1][e1] * m[2][e2]; }
+  // E[u^e psi_E] with psi_E = (|u|^2 + xi^2)/2
+  __device__ double Epe(int e0, int e1, int e2) const {
+    double s = x1 * E(e0, e1, e2);
+    s += E(e0 + 2, e1, e2);
+    if (D >= 2) s += E(e0, e1 + 2, e2);
+    if (D >= 3) s += E(e0, e1, e2 + 2);
+    return 0.5 * s;
+  }
+  // E[u^e psi_E^2]
+  __device__ double Epe2(int e0, int e1, int e2) const {
+    int e[3] = {e0, e1, e2};
+    double s = x2 * E(e0, e1, e2);
+    for (int g = 0; g < D; ++g) {
+      int f[3] = {e[0], e[1], e[2]};
+      f[g] += 2;
+      s += 2.0 * x1 * E(f[0], f[1], f[2]);
+      for (int hh = 0; hh < D; ++hh) {
+        int k[3] = {f[0], f[1], f[2]};
+        k[hh] += 2;
+        s += E(k[0], k[1], k[2]);
+      }
+    }
+    return 0.25 * s;
+  }
+};
+
+// r_alpha = -sum_d E[u_d psi_alpha (a_d . psi)]  (compatibility condition for
+// the time slope).
+template <int D>
+__device__ __forceinline__ void time_slope_rhs(const Moments<D>& M, const double (*a)[5], double* r) {
+  for (int al = 0; al < D + 2; ++al) r[al] = 0.0;
+  for (int d = 0; d < D; ++d) {
+    int ed[3] = {0, 0, 0};
+    ed[d] = 1;
+    // alpha = 0: psi_0 = 1
+    {
+      double t = a[d][0] * M.E(ed[0], ed[1], ed[2]);
+      for (int e = 0; e < D; ++e) {
+        int k[3] = {ed[0], ed[1], ed[2]};
+        k[e] += 1;
+        t += a[d][1 + e] * M.E(k[0], k[1], k[2]);
+      }
+      t += a[d][D + 1] * M.Epe(ed[0], ed[1], ed[2]);
+      r[0] -= t;
+    }
+    // alpha = f: psi_f = u_f
+    for (int f = 0; f < D; ++f) {
+      int ef[3] = {ed[0], ed[1], ed[2]};
+      ef[f] += 1;
+      double t = a[d][0] * M.E(ef[0], ef[1], ef[2]);
+      for (int e = 0; e < D; ++e) {
+        int k[3] = {ef[0], ef[1], ef[2]};
+        k[e] += 1;
+        t += a[d][1 + e] * M.E(k[0], k[1], k[2]);
+      }
+      t += a[d][D + 1] * M.Epe(ef[0], ef[1], ef[2]);
+      r[1 + f] -= t;
+    }
+    // alpha = E: psi_E
+    {
+      double t = a[d][0] * M.Epe(ed[0], ed[1], ed[2]);
+      for (int e = 0; e < D; ++e) {
+        int k[3] = {ed[0], ed[1], ed[2]};
+        k[e] += 1;
+        t += a[d][1 + e] * M.Epe(k[0], k[1], k[2]);
+      }
+      t += a[d][D + 1] * M.Epe2(ed[0], ed[1], ed[2]);
+      r[D + 1] -= t;
+    }
+  }
+}
+
+// Time integrals of c_1..c_5 over [0, dt]; closed forms for dt/tau >= 1/2,
+// power series of the same functions below (they are exact rearrangements of
+// exp(-x); the closed forms cancel catastrophically for small x).
+__device__ __forceinline__ void time_coeffs(double dt, double tau, double* G) {
+  double x = dt / tau;
+  if (x >= 0.5) {
+    double E = -expm1(-x);
+    G[0] = tau * E;
+    G[1] = tau * tau * (x * (1.0 - E) - E);
+    G[2] = tau * (x - E);
+    G[3] = tau * tau * (2.0 * E - x * (2.0 - E));
+    G[4] = tau * tau * (0.5 * x * x - x + E);
+    return;
+  }
+  // term t_n = (-x)^n / n!; accumulate each series by its own coefficient
+  double t = 1.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
+  for (int n = 1; n <= 40; ++n) {
+    t *= -x / n;           // (-1)^n x^n / n!
+    s1 -= t;               // (-1)^(n+1) x^n/n!
+    s2 -= (n - 1) * t;     // (-1)^(n-1) (n-1) x^n/n!
+    s3 += (n >= 2) ? t : 0.0;
+    s4 -= (n >= 3) ? (2 - n) * t : 0.0;
+    s5 -= (n >= 3) ? t : 0.0;
+    if (fabs(t) < 1e-40) break;
+  }
+  G[0] = tau * s1;
+  G[1] = tau * tau * s2;
+  G[2] = tau * s3;
+  G[3] = tau * tau * s4;
+  G[4] = tau * tau * s5;
+}
+
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_prims(int64_t nc, GasP g, const double* __restrict__ W, double* __restrict__ prim,
+                        int32_t* flag, int check) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  if (check && *flag) return;
+  bool ok = prim_of<D>(&W[i * (D + 2)], g, &prim[i * NPRIM]);
+  if (!ok) atomicOr(flag, 1);
+}
+
+// Heat flux q_i = 1/2 sum_k w_k c_k (|c_k|^2 h_ik + b_ik), c = u - U_i.
+template <int D, typename T>
+__global__ __launch_bounds__(TPB) void k_heatflux(DevVel v, const T* __restrict__ h,
+                                                  const T* __restrict__ b,
+                                                  const double* __restrict__ prim,
+                                                  double* __restrict__ q, const int32_t* flag) {
+  __shared__ double lds[3 * 16];
+  if (*flag) return;
+  const int64_t i = blockIdx.x;
+  const double* P = &prim[i * NPRIM];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t k = threadIdx.x; k < v.nvp; k += TPB) {
+    double c[3], c2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      c[d] = v.u[d * v.nvp + k] - P[1 + d];
+      c2 += c[d] * c[d];
+    }
+    double hv = ld(h, i * v.nvp + k);
+    double bv = (D == 2) ? ld(b, i * v.nvp + k) : 0.0;
+    double s = v.w[k] * (c2 * hv + bv);
+    for (int d = 0; d < D; ++d) acc[d] += s * c[d];
+  }
+  block_sum<3>(acc, lds);
+  if (threadIdx.x == 0) {
+    for (int d = 0; d < 3; ++d) q[i * 3 + d] = d < D ? 0.5 * acc[d] : 0.0;
+  }
+}
+
+// Macroscopic least-squares gradients of W (step 4).
+template <int D>
+__global__ void k_gradW(DevMesh m, const DevBC* __restrict__ bcs, GasP g, const double* __restrict__ W,
+                        double* __restrict__ gW, const int32_t* flag) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m.nc || *flag) return;
+  const int nfc = m.nfc[i];
+  const double* Wi = &W[i * (D + 2)];
+  double acc[3][5];
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < 5; ++v) acc[d][v] = 0.0;
+  for (int p = 0; p < nfc; ++p) {
+    const int f = m.cface[i * MAXF + p];
+    const int j = m.cnbr[i * MAXF + p];
+    double nb[5];
+    if (j >= 0) {
+      for (int v = 0; v < D + 2; ++v) nb[v] = W[(int64_t)j * (D + 2) + v];
+    } else if (m.fbc[f] == UGKS_BC_WALL) {
+      for (int v = 0; v < D + 2; ++v) nb[v] = Wi[v];
+    } else {
+      ghost_state<D>(m.fbc[f], bcs[m.fbcid[f]], &m.fnorm[f * 3], Wi, g.R, nb);
+    }
+    for (int d = 0; d < D; ++d) {
+      const double G = m.lsG[(i * 3 + d) * MAXF + p];
+      for (int v = 0; v < D + 2; ++v) acc[d][v] += G * (nb[v] - Wi[v]);
+    }
+  }
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < 5; ++v) gW[(i * 3 + d) * 5 + v] = (d < D && v < D + 2) ? acc[d][v] : 0.0;
+}
+
+// Interface equilibrium data of every face (steps 6.1-6.6), wall Maxwellian
+// data of wall faces.
+template <int D>
+__global__ void k_face_eq(DevMesh m, const DevBC* __restrict__ bcs, GasP g,
+                          const double* __restrict__ W, const double* __restrict__ gW,
+                          const double* __restrict__ q, double* __restrict__ frec, int32_t* flag) {
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= m.nf || *flag) return;
+  double* R = &frec[f * FREC];
+  const int kind = m.fbc[f];
+  const int L = m.fL[f];
+  if (kind == UGKS_BC_WALL) {
+    const DevBC& bc = bcs[m.fbcid[f]];
+    double lamw = 1.0 / (2.0 * g.R * bc.T);
+    R[FR_C0] = maxw_norm<D>(lamw);
+    R[FR_LAM] = lamw;
+    for (int d = 0; d < 3; ++d) R[FR_U + d] = d < D ? bc.U[d] : 0.0;
+    return;
+  }
+  const bool ghost = kind != UGKS_BC_INTERIOR;
+  const int Rc = ghost ? -1 : m.fR[f];
+  const double* n = &m.fnorm[f * 3];
+  double Wg[5];
+  if (ghost) {
+    ghost_state<D>(kind, bcs[m.fbcid[f]], n, &W[(int64_t)L * (D + 2)], g.R, Wg);
+    double Pg[NPRIM];
+    prim_of<D>(Wg, g, Pg);
+    R[FR_GRHO] = Pg[0];
+    for (int d = 0; d < 3; ++d) R[FR_GU + d] = Pg[1 + d];
+    R[FR_GLAM] = Pg[4];
+    R[FR_GC] = Pg[0] * maxw_norm<D>(Pg[4]);
+  }
+  // 6.1 reconstructed states on both sides
+  double Wl[5], Wr[5];
+  for (int v = 0; v < D + 2; ++v) {
+    double sl = W[(int64_t)L * (D + 2) + v];
+    for (int d = 0; d < D; ++d) sl += m.fdxL[f * 3 + d] * gW[((int64_t)L * 3 + d) * 5 + v];
+    Wl[v] = sl;
+    if (ghost) {
+      Wr[v] = Wg[v];
+    } else {
+      double sr = W[(int64_t)Rc * (D + 2) + v];
+      for (int d = 0; d < D; ++d) sr += m.fdxR[f * 3 + d] * gW[((int64_t)Rc * 3 + d) * 5 + v];
+      Wr[v] = sr;
+    }
+  }
+  double Pl[NPRIM], Pr[NPRIM];
+  if (!prim_of<D>(Wl, g, Pl)) {
+    for (int v = 0; v < D + 2; ++v) Wl[v] = W[(int64_t)L * (D + 2) + v];
+    prim_of<D>(Wl, g, Pl);
+  }
+  if (!prim_of<D>(Wr, g, Pr)) {
+    for (int v = 0; v < D + 2; ++v) Wr[v] = ghost ? Wg[v] : W[(int64_t)Rc * (D + 2) + v];
+    prim_of<D>(Wr, g, Pr);
+  }
+  // 6.2 interface state from the two half-range Maxwellians
+  double W0[5] = {0, 0, 0, 0, 0};
+  const double* Ps[2] = {Pl, Pr};
+  for (int s = 0; s < 2; ++s) {
+    const double* P = Ps[s];
+    double rho = P[0], lam = P[4];
+    double Un = 0.0;
+    for (int d = 0; d < D; ++d) Un += P[1 + d] * n[d];
+    double Ut2 = 0.0, Ut[3];
+    for (int d = 0; d < D; ++d) {
+      Ut[d] = P[1 + d] - Un * n[d];
+      Ut2 += Ut[d] * Ut[d];
+    }
+    double mo[3];
+    half_range(Un, lam, s == 0 ? 1.0 : -1.0, mo);
+    W0[0] += rho * mo[0];
+    for (int d = 0; d < D; ++d) W0[1 + d] += rho * (mo[1] * n[d] + mo[0] * Ut[d]);
+    W0[D + 1] += 0.5 * rho * (mo[2] + mo[0] * (Ut2 + 2.0 / (2.0 * lam)));
+  }
+  // 6.3 interface primitives, relaxation time and time coefficients
+  double P0[NPRIM];
+  if (!prim_of<D>(W0, g, P0)) {
+    atomicOr(flag, 2);
+    return;
+  }
+  const double rho0 = P0[0], lam0 = P0[4];
+  double U0[3] = {P0[1], P0[2], P0[3]};
+  R[FR_C0] = rho0 * maxw_norm<D>(lam0);
+  R[FR_LAM] = lam0;
+  for (int d = 0; d < 3; ++d) R[FR_U + d] = U0[d];
+  R[FR_SH] = 4.0 * (1.0 - g.Pr) * lam0 * lam0 / (5.0 * rho0);
+  time_coeffs(g.dt, P0[5], &R[FR_G]);
+  // 6.4 spatial slopes from the averaged gradient
+  double a[3][5];
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < 5; ++v) a[d][v] = 0.0;
+  for (int d = 0; d < D; ++d) {
+    double bvec[5];
+    for (int v = 0; v < D + 2; ++v) {
+      double gl = gW[((int64_t)L * 3 + d) * 5 + v];
+      double gr = ghost ? 0.0 : gW[((int64_t)Rc * 3 + d) * 5 + v];
+      bvec[v] = 0.5 * (gl + gr) / rho0;
+    }
+    slope_solve<D>(bvec, U0, lam0, a[d]);
+  }
+  // 6.5 time slope from compatibility
+  Moments<D> M;
+  M.init(U0, lam0);
+  double r[5], At[5];
+  time_slope_rhs<D>(M, a, r);
+  slope_solve<D>(r, U0, lam0, At);
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < 5; ++v) R[FR_A + d * 5 + v] = (d < D && v < D + 2) ? a[d][v] : 0.0;
+  for (int v = 0; v < 5; ++v) R[FR_AT + v] = v < D + 2 ? At[v] : 0.0;
+  // 6.6 interface heat flux
+  for (int d = 0; d < 3; ++d) {
+    double ql = q[(int64_t)L * 3 + d];
+    double qr = ghost ? 0.0 : q[(int64_t)Rc * 3 + d];
+    R[FR_Q + d] = d < D ? 0.5 * (ql + qr) : 0.0;
+  }
+}
+
+// Microscopic gradients of h (and b) for every (cell, velocity) (step 5).
+template <int D, typename T>
+__global__ __launch_bounds__(TPB) void k_grad_micro(DevMesh m, DevVel v,
+                                                    const double* __restrict__ frec,
+                                                    const T* __restrict__ h, const T* __restrict__ b,
+                                                    double* __restrict__ gh, double* __restrict__ gb,
+                                                    const int32_t* flag) {
+  const int64_t nch = (v.nvp + TPB - 1) / TPB;
+  const int64_t i = blockIdx.x / nch;
+  const int64_t k = (blockIdx.x % nch) * TPB + threadIdx.x;
+  if (k >= v.nvp || *flag) return;
+  const int64_t nvp = v.nvp;
+  const double hi = ld(h, i * nvp + k);
+  const double bi = (D == 2) ? ld(b, i * nvp + k) : 0.0;
+  double ah[3] = {0, 0, 0}, ab[3] = {0, 0, 0};
+  const int nfc = m.nfc[i];
+  for (int p = 0; p < nfc; ++p) {
+    const int j = m.cnbr[i * MAXF + p];
+    double hn, bn;
+    if (j >= 0) {
+      hn = ld(h, (int64_t)j * nvp + k);
+      bn = (D == 2) ? ld(b, (int64_t)j * nvp + k) : 0.0;
+    } else {
+      const int f = m.cface[i * MAXF + p];
+      if (m.fbc[f] == UGKS_BC_WALL) {
+        hn = hi;
+        bn = bi;
+      } else {
+        const double* R = &frec[(int64_t)f * FREC];
+        double c2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+          double c = v.u[d * nvp + k] - R[FR_GU + d];
+          c2 += c * c;
+        }
+        hn = R[FR_GC] * exp(-R[FR_GLAM] * c2);
+        bn = (3 - D) / (2.0 * R[FR_GLAM]) * hn;
+      }
+    }
+    for (int d = 0; d < D; ++d) {
+      const double G = m.lsG[(i * 3 + d) * MAXF + p];
+      ah[d] += G * (hn - hi);
+      if (D == 2) ab[d] += G * (bn - bi);
+    }
+  }
+  for (int d = 0; d < D; ++d) {
+    gh[(i * 3 + d) * nvp + k] = ah[d];
+    if (D == 2) gb[(i * 3 + d) * nvp + k] = ab[d];
+  }
+}
+
+// Wall density from the zero normal mass flux condition (step 7).
+template <int D, typename T>
+__global__ __launch_bounds__(TPB) void k_wall_rho(DevMesh m, DevVel v, GasP g,
+                                                  const T* __restrict__ h,
+                                                  const double* __restrict__ gh,
+                                                  double* __restrict__ frec, const int32_t* flag) {
+  __shared__ double lds[2 * 16];
+  if (*flag) return;
+  const int f = m.walls[blockIdx.x];
+  const int L = m.fL[f];
+  const int64_t nvp = v.nvp;
+  double* R = &frec[(int64_t)f * FREC];
+  const double lamw = R[FR_LAM], Cw = R[FR_C0];
+  const double dt = g.dt;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t k = threadIdx.x; k < nvp; k += TPB) {
+    double un = 0.0;
+    for (int d = 0; d < D; ++d) un += v.u[d * nvp + k] * m.fnorm[f * 3 + d];
+    if (un > 0.0) {
+      double hf = ld(h, (int64_t)L * nvp + k), ugh = 0.0;
+      for (int d = 0; d < D; ++d) {
+        double gd = gh[((int64_t)L * 3 + d) * nvp + k];
+        hf += m.fdxL[f * 3 + d] * gd;
+        ugh += v.u[d * nvp + k] * gd;
+      }
+      acc[0] += v.w[k] * un * (dt * hf - 0.5 * dt * dt * ugh);
+    } else if (un < 0.0) {
+      double c2 = 0.0;
+      for (int d = 0; d < D; ++d) {
+        double c = v.u[d * nvp + k] - R[FR_U + d];
+        c2 += c * c;
+      }
+      acc[1] += v.w[k] * un * Cw * exp(-lamw * c2);
+    }
+  }
+  block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) R[FR_RHOW] = -acc[0] / (dt * acc[1]);
+}
+
+// Time-integrated microscopic flux of one (face, velocity) (steps 6.7, 7).
+template <int D, typename T>
+__device__ __forceinline__ void face_flux(const DevMesh& m, const DevVel& v, const GasP& g,
+                                          const double* R, int64_t f, int64_t k,
+                                          const T* __restrict__ h, const T* __restrict__ b,
+                                          const double* __restrict__ gh,
+                                          const double* __restrict__ gb, double& FH, double& FB) {
+  const int64_t nvp = v.nvp;
+  const int kind = m.fbc[f];
+  const int L = m.fL[f];
+  double uk[3] = {0, 0, 0};
+  double un = 0.0;
+  for (int d = 0; d < D; ++d) {
+    uk[d] = v.u[d * nvp + k];
+    un += uk[d] * m.fnorm[f * 3 + d];
+  }
+  const double dt = g.dt;
+  constexpr int KXI = 3 - D;
+  double ih = 0.0, ib = 0.0;
+  if (kind == UGKS_BC_WALL) {
+    if (un > 0.0) {
+      double hf = ld(h, (int64_t)L * nvp + k), bf = (D == 2) ? ld(b, (int64_t)L * nvp + k) : 0.0;
+      double ugh = 0.0, ugb = 0.0;
+      for (int d = 0; d < D; ++d) {
+        double gd = gh[((int64_t)L * 3 + d) * nvp + k];
+        hf += m.fdxL[f * 3 + d] * gd;
+        ugh += uk[d] * gd;
+        if (D == 2) {
+          double gbd = gb[((int64_t)L * 3 + d) * nvp + k];
+          bf += m.fdxL[f * 3 + d] * gbd;
+          ugb += uk[d] * gbd;
+        }
+      }
+      ih = dt * hf - 0.5 * dt * dt * ugh;
+      ib = dt * bf - 0.5 * dt * dt * ugb;
+    } else if (un < 0.0) {
+      double c2 = 0.0;
+      for (int d = 0; d < D; ++d) {
+        double c = uk[d] - R[FR_U + d];
+        c2 += c * c;
+      }
+      double Hw = R[FR_C0] * exp(-R[FR_LAM] * c2);
+      ih = dt * R[FR_RHOW] * Hw;
+      ib = dt * R[FR_RHOW] * KXI / (2.0 * R[FR_LAM]) * Hw;
+    }
+    FH = un * ih;
+    FB = un * ib;
+    return;
+  }
+  const bool ghost = kind != UGKS_BC_INTERIOR;
+  double hf, bf = 0.0, ugh = 0.0, ugb = 0.0;
+  if (un <= 0.0 && ghost) {
+    double c2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      double c = uk[d] - R[FR_GU + d];
+      c2 += c * c;
+    }
+    hf = R[FR_GC] * exp(-R[FR_GLAM] * c2);
+    bf = KXI / (2.0 * R[FR_GLAM]) * hf;
+  } else {
+    const bool left = un > 0.0;
+    const int64_t up = left ? L : m.fR[f];
+    const double* dx = left ? &m.fdxL[f * 3] : &m.fdxR[f * 3];
+    hf = ld(h, up * nvp + k);
+    if (D == 2) bf = ld(b, up * nvp + k);
+    for (int d = 0; d < D; ++d) {
+      double gd = gh[(up * 3 + d) * nvp + k];
+      hf += dx[d] * gd;
+      ugh += uk[d] * gd;
+      if (D == 2) {
+        double gbd = gb[(up * 3 + d) * nvp + k];
+        bf += dx[d] * gbd;
+        ugb += uk[d] * gbd;
+      }
+    }
+  }
+  // interface equilibrium, its Shakhov correction and derivative terms
+  const double lam0 = R[FR_LAM];
+  double c2 = 0.0, cq = 0.0, u2 = v.u2[k];
+  for (int d = 0; d < D; ++d) {
+    double c = uk[d] - R[FR_U + d];
+    c2 += c * c;
+    cq += c * R[FR_Q + d];
+  }
+  const double H0 = R[FR_C0] * exp(-lam0 * c2);
+  const double B0 = KXI / (2.0 * lam0) * H0;
+  const double sh = R[FR_SH] * cq;
+  const double H0p = sh * (2.0 * lam0 * c2 - 2.0 - D) * H0;
+  const double B0p = sh * (2.0 * lam0 * c2 - D) * KXI / (2.0 * lam0) * H0;
+  const double xi4 = KXI * (KXI + 2.0) / (4.0 * lam0 * lam0);
+  double uH = 0.0, uB = 0.0;
+  for (int d = 0; d < D; ++d) {
+    const double* ad = &R[FR_A + d * 5];
+    double Pd = ad[0] + 0.5 * ad[D + 1] * u2;
+    for (int c = 0; c < D; ++c) Pd += ad[1 + c] * uk[c];
+    uH += uk[d] * (Pd * H0 + 0.5 * ad[D + 1] * B0);
+    uB += uk[d] * (Pd * B0 + 0.5 * ad[D + 1] * xi4 * H0);
+  }
+  const double* At = &R[FR_AT];
+  double PA = At[0] + 0.5 * At[D + 1] * u2;
+  for (int c = 0; c < D; ++c) PA += At[1 + c] * uk[c];
+  const double tH = PA * H0 + 0.5 * At[D + 1] * B0;
+  const double tB = PA * B0 + 0.5 * At[D + 1] * xi4 * H0;
+  const double* G = &R[FR_G];
+  ih = G[0] * hf + G[1] * ugh + G[2] * (H0 + H0p) + G[3] * uH + G[4] * tH;
+  ib = G[0] * bf + G[1] * ugb + G[2] * (B0 + B0p) + G[3] * uB + G[4] * tB;
+  FH = un * ih;
+  FB = un * ib;
+}
+
+// Microscopic fluxes of one face for every velocity, and the face's
+// macroscopic flux F = sum_k w_k (H, u H, (|u|^2 H + B)/2) (Eq. macro_flux).
+template <int D, typename T>
+__global__ __launch_bounds__(TPB) void k_flux(DevMesh m, DevVel v, GasP g,
+                                              const double* __restrict__ frec,
+                                              const T* __restrict__ h, const T* __restrict__ b,
+                                              const double* __restrict__ gh,
+                                              const double* __restrict__ gb,
+                                              double* __restrict__ fh, double* __restrict__ fb,
+                                              double* __restrict__ F, const int32_t* flag) {
+  __shared__ double lds[5 * 16];
+  if (*flag) return;
+  const int64_t f = blockIdx.x;
+  const double* R = &frec[f * FREC];
+  const int64_t nvp = v.nvp;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t k = threadIdx.x; k < nvp; k += TPB) {
+    double FH, FB;
+    face_flux<D, T>(m, v, g, R, f, k, h, b, gh, gb, FH, FB);
+    fh[f * nvp + k] = FH;
+    if (D == 2) fb[f * nvp + k] = FB;
+    const double wk = v.w[k];
+    acc[0] += wk * FH;
+    for (int d = 0; d < D; ++d) acc[1 + d] += wk * v.u[d * nvp + k] * FH;
+    acc[D + 1] += wk * 0.5 * (v.u2[k] * FH + FB);
+  }
+  block_sum<5>(acc, lds);
+  if (threadIdx.x == 0)
+    for (int x = 0; x < 5; ++x) F[f * 5 + x] = x < D + 2 ? acc[x] : 0.0;
+}
+
+// Reduced Maxwellian and Shakhov correction of a cell at one velocity.
+template <int D>
+__device__ __forceinline__ void cell_equilibrium(const double* P, const double* qv, double Pr,
+                                                 const double* uk, double& Hs, double& Bs) {
+  constexpr int KXI = 3 - D;
+  const double rho = P[0], lam = P[4];
+  double c2 = 0.0, cq = 0.0;
+  for (int d = 0; d < D; ++d) {
+    double c = uk[d] - P[1 + d];
+    c2 += c * c;
+    cq += c * qv[d];
+  }
+  const double H = rho * maxw_norm<D>(lam) * exp(-lam * c2);
+  const double pre = 4.0 * (1.0 - Pr) * lam * lam / (5.0 * rho) * cq;
+  const double Hp = pre * (2.0 * lam * c2 - 2.0 - D) * H;
+  const double Bp = pre * (2.0 * lam * c2 - D) * KXI / (2.0 * lam) * H;
+  Hs = H + Hp;
+  Bs = KXI / (2.0 * lam) * H + Bp;
+}
+
+// First stage (Eq. f_tilde).
+template <int D, typename T>
+__global__ __launch_bounds__(TPB) void k_stage1(DevMesh m, DevVel v, GasP g,
+                                                const double* __restrict__ prim,
+                                                const double* __restrict__ q,
+                                                const T* __restrict__ h, const T* __restrict__ b,
+                                                const double* __restrict__ fh,
+                                                const double* __restrict__ fb, T* __restrict__ ht,
+                                                T* __restrict__ bt, const int32_t* flag) {
+  const int64_t nch = (v.nvp + TPB - 1) / TPB;
+  const int64_t i = blockIdx.x / nch;
+  const int64_t k = (blockIdx.x % nch) * TPB + threadIdx.x;
+  if (k >= v.nvp || *flag) return;
+  const int64_t nvp = v.nvp;
+  double sh = 0.0, sb = 0.0;
+  const int nfc = m.nfc[i];
+  for (int p = 0; p < nfc; ++p) {
+    const int64_t f = m.cface[i * MAXF + p];
+    const double s = m.csign[i * MAXF + p] * m.farea[f];
+    sh += s * fh[f * nvp + k];
+    if (D == 2) sb += s * fb[f * nvp + k];
+  }
+  const double* P = &prim[i * NPRIM];
+  double uk[3] = {0, 0, 0};
+  for (int d = 0; d < D; ++d) uk[d] = v.u[d * nvp + k];
+  double Hs, Bs;
+  cell_equilibrium<D>(P, &q[i * 3], g.Pr, uk, Hs, Bs);
+  const double c = g.dt / (2.0 * P[5]);
+  const double iv = 1.0 / m.vol[i];
+  const double hv = ld(h, i * nvp + k);
+  st(ht, i * nvp + k, hv - sh * iv + c * (Hs - hv));
+  if (D == 2) {
+    const double bv = ld(b, i * nvp + k);
+    st(bt, i * nvp + k, bv - sb * iv + c * (Bs - bv));
+  }
+}
+
+// Conservative update (Eq. macro_update) and per-cell residual parts.
+template <int D>
+__global__ void k_macro_update(DevMesh m, const double* __restrict__ W, const double* __restrict__ F,
+                               double* __restrict__ Wn, double* __restrict__ cellred,
+                               const int32_t* flag) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m.nc || *flag) return;
+  double acc[5] = {0, 0, 0, 0, 0};
+  const int nfc = m.nfc[i];
+  for (int p = 0; p < nfc; ++p) {
+    const int64_t f = m.cface[i * MAXF + p];
+    const double s = m.csign[i * MAXF + p] * m.farea[f];
+    for (int x = 0; x < D + 2; ++x) acc[x] += s * F[f * 5 + x];
+  }
+  const double V = m.vol[i];
+  for (int x = 0; x < D + 2; ++x) Wn[i * (D + 2) + x] = W[i * (D + 2) + x] - acc[x] / V;
+  const double dr = Wn[i * (D + 2)] - W[i * (D + 2)];
+  cellred[i * 3 + 0] = V * dr * dr;
+  cellred[i * 3 + 1] = V;
+  cellred[i * 3 + 2] = V * W[i * (D + 2)] * W[i * (D + 2)];
+}
+
+// Second stage (Eq. f_final) with the equilibrium of W^{n+1} and q^n.
+template <int D, typename T>
+__global__ __launch_bounds__(TPB) void k_stage2(DevVel v, GasP g, const double* __restrict__ primn,
+                                                const double* __restrict__ q,
+                                                const T* __restrict__ ht, const T* __restrict__ bt,
+                                                T* __restrict__ h, T* __restrict__ b,
+                                                const int32_t* flag) {
+  const int64_t nch = (v.nvp + TPB - 1) / TPB;
+  const int64_t i = blockIdx.x / nch;
+  const int64_t k = (blockIdx.x % nch) * TPB + threadIdx.x;
+  if (k >= v.nvp || *flag) return;
+  const int64_t nvp = v.nvp;
+  const double* P = &primn[i * NPRIM];
+  double uk[3] = {0, 0, 0};
+  for (int d = 0; d < D; ++d) uk[d] = v.u[d * nvp + k];
+  double Hs, Bs;
+  cell_equilibrium<D>(P, &q[i * 3], g.Pr, uk, Hs, Bs);
+  const double a = g.dt / (2.0 * P[5]);
+  const double inv = 1.0 / (1.0 + a);
+  st(h, i * nvp + k, (ld(ht, i * nvp + k) + a * Hs) * inv);
+  if (D == 2) st(b, i * nvp + k, (ld(bt, i * nvp + k) + a * Bs) * inv);
+}
+
+// Residual of the density: one block, fixed summation order.
+__global__ __launch_bounds__(1024) void k_residual(int64_t nc, const double* __restrict__ cellred,
+                                                   double* __restrict__ resid, const int32_t* flag) {
+  __shared__ double lds[3 * 16];
+  if (*flag) return;
+  double acc[3] = {0, 0, 0};
+  for (int64_t i = threadIdx.x; i < nc; i += blockDim.x)
+    for (int x = 0; x < 3; ++x) acc[x] += cellred[i * 3 + x];
+  block_sum<3>(acc, lds);
+  if (threadIdx.x == 0) {
+    double nrm = sqrt(acc[0] / acc[1]);
+    if (resid[3] == 0.0) resid[3] = nrm;
+    resid[0] = resid[3] > 0.0 ? nrm / resid[3] : 0.0;
+    resid[1] = nrm / sqrt(acc[2] / acc[1]);
+  }
+}
+
+template <int D>
+__global__ void k_commit_W(int64_t nc, const double* __restrict__ Wn, double* __restrict__ W,
+                           const int32_t* flag) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nc * (D + 2) || *flag) return;
+  W[i] = Wn[i];
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(TPB) void k_init_maxwellian(DevVel v, const double* __restrict__ prim,
+                                                         T* __restrict__ h, T* __restrict__ b) {
+  const int64_t nch = (v.nvp + TPB - 1) / TPB;
+  const int64_t i = blockIdx.x / nch;
+  const int64_t k = (blockIdx.x % nch) * TPB + threadIdx.x;
+  if (k >= v.nvp) return;
+  const double* P = &prim[i * NPRIM];
+  double c2 = 0.0;
+  for (int d = 0; d < D; ++d) {
+    double c = v.u[d * v.nvp + k] - P[1 + d];
+    c2 += c * c;
+  }
+  const double H = P[0] * maxw_norm<D>(P[4]) * exp(-P[4] * c2);
+  st(h, i * v.nvp + k, H);
+  if (D == 2) st(b, i * v.nvp + k, (3 - D) / (2.0 * P[4]) * H);
+}
+
+// Discrete moments sum_k w_k psi_k (h, b) per cell.
+template <int D, typename T>
+__global__ __launch_bounds__(TPB) void k_moments(DevVel v, const T* __restrict__ h,
+                                                 const T* __restrict__ b, double* __restrict__ out) {
+  __shared__ double lds[5 * 16];
+  const int64_t i = blockIdx.x;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t k = threadIdx.x; k < v.nvp; k += TPB) {
+    double wh = v.w[k] * ld(h, i * v.nvp + k);
+    double wb = (D == 2) ? v.w[k] * ld(b, i * v.nvp + k) : 0.0;
+    acc[0] += wh;
+    for (int d = 0; d < D; ++d) acc[1 + d] += wh * v.u[d * v.nvp + k];
+    acc[D + 1] += 0.5 * (wh * v.u2[k] + wb);
+  }
+  block_sum<5>(acc, lds);
+  if (threadIdx.x == 0)
+    for (int x = 0; x < D + 2; ++x) out[i * (D + 2) + x] = acc[x];
+}
+
+// Per-cell CFL bound 2 V_i / max_k sum_j S_j |u_k . n_j|.
+template <int D>
+__global__ __launch_bounds__(TPB) void k_dt_cells(DevMesh m, DevVel v, double* __restrict__ out) {
+  __shared__ double lds[16];
+  const int64_t i = blockIdx.x;
+  const int nfc = m.nfc[i];
+  double mx = 0.0;
+  for (int64_t k = threadIdx.x; k < v.nvp; k += TPB) {
+    if (k >= v.nv) break;
+    double s = 0.0;
+    for (int p = 0; p < nfc; ++p) {
+      const int64_t f = m.cface[i * MAXF + p];
+      double un = 0.0;
+      for (int d = 0; d < D; ++d) un += v.u[d * v.nvp + k] * m.fnorm[f * 3 + d];
+      s += m.farea[f] * fabs(un);
+    }
+    mx = fmax(mx, s);
+  }
+  mx = block_max(mx, lds);
+  if (threadIdx.x == 0) out[i] = 2.0 * m.vol[i] / mx;
+}
+
+inline unsigned blocks_for(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
+
+}  // namespace
+
+#define UGKS_DISPATCH_D(D_, ...)          \
+  do {                                    \
+    if ((D_) == 2) {                      \
+      constexpr int DD = 2;               \
+      __VA_ARGS__;                        \
+    } else {                              \
+      constexpr int DD = 3;               \
+      __VA_ARGS__;                        \
+    }                                     \
+  } while (0)
+
+#define UGKS_DISPATCH_DT(D_, P_, ...)                  \
+  do {                                                 \
+    if ((P_) == UGKS_FP32) {                           \
+      using TT = float;                                \
+      UGKS_DISPATCH_D(D_, __VA_ARGS__);                \
+    } else {                                           \
+      using TT = double;                               \
+      UGKS_DISPATCH_D(D_, __VA_ARGS__);                \
+    }                                                  \
+  } while (0)
+
+hipError_t launch_prims(int D, const DevMesh& m, const GasP& g, const double* W, double* prim,
+                        int32_t* flag, int checkflag, hipStream_t s) {
+  UGKS_DISPATCH_D(D, k_prims<DD><<<blocks_for(m.nc, 256), 256, 0, s>>>(m.nc, g, W, prim, flag, checkflag));
+  return hipGetLastError();
+}
+
+hipError_t launch_heatflux(int D, int prec, const DevMesh& m, const DevVel& v, const void* h,
+                           const void* b, const double* prim, double* q, const int32_t* flag,
+                           hipStream_t s) {
+  UGKS_DISPATCH_DT(D, prec, k_heatflux<DD, TT><<<(unsigned)m.nc, TPB, 0, s>>>(
+      v, (const TT*)h, (const TT*)b, prim, q, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_gradW(int D, const DevMesh& m, const DevBC* bcs, const GasP& g, const double* W,
+                        double* gW, const int32_t* flag, hipStream_t s) {
+  UGKS_DISPATCH_D(D, k_gradW<DD><<<blocks_for(m.nc, 128), 128, 0, s>>>(m, bcs, g, W, gW, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_face_eq(int D, const DevMesh& m, const DevBC* bcs, const GasP& g,
+                          const double* W, const double* gW, const double* q, double* frec,
+                          int32_t* flag, hipStream_t s) {
+  UGKS_DISPATCH_D(D, k_face_eq<DD><<<blocks_for(m.nf, 64), 64, 0, s>>>(m, bcs, g, W, gW, q, frec, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_micro(int D, int prec, const DevMesh& m, const DevVel& v,
+                             const double* frec, const void* h, const void* b, double* gh,
+                             double* gb, const int32_t* flag, hipStream_t s) {
+  const unsigned grid = blocks_for(v.nvp, TPB) * (unsigned)m.nc;
+  UGKS_DISPATCH_DT(D, prec, k_grad_micro<DD, TT><<<grid, TPB, 0, s>>>(
+      m, v, frec, (const TT*)h, (const TT*)b, gh, gb, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_flux(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
+                       const double* frec, const void* h, const void* b, const double* gh,
+                       const double* gb, double* fh, double* fb, double* F, const int32_t* flag,
+                       hipStream_t s) {
+  UGKS_DISPATCH_DT(D, prec, k_flux<DD, TT><<<(unsigned)m.nf, TPB, 0, s>>>(
+      m, v, g, frec, (const TT*)h, (const TT*)b, gh, gb, fh, fb, F, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_stage1(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
+                         const double* prim, const double* q, const void* h, const void* b,
+                         const double* fh, const double* fb, void* ht, void* bt,
+                         const int32_t* flag, hipStream_t s) {
+  const unsigned grid = blocks_for(v.nvp, TPB) * (unsigned)m.nc;
+  UGKS_DISPATCH_DT(D, prec, k_stage1<DD, TT><<<grid, TPB, 0, s>>>(
+      m, v, g, prim, q, (const TT*)h, (const TT*)b, fh, fb, (TT*)ht, (TT*)bt, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_macro_update(int D, const DevMesh& m, const double* W, const double* F,
+                               double* Wn, double* cellred, const int32_t* flag, hipStream_t s) {
+  UGKS_DISPATCH_D(D, k_macro_update<DD><<<blocks_for(m.nc, 256), 256, 0, s>>>(m, W, F, Wn, cellred, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_stage2(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
+                         const double* primn, const double* q, const void* ht, const void* bt,
+                         void* h, void* b, const int32_t* flag, hipStream_t s) {
+  const unsigned grid = blocks_for(v.nvp, TPB) * (unsigned)m.nc;
+  UGKS_DISPATCH_DT(D, prec, k_stage2<DD, TT><<<grid, TPB, 0, s>>>(
+      v, g, primn, q, (const TT*)ht, (const TT*)bt, (TT*)h, (TT*)b, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const DevMesh& m, const double* cellred, double* resid,
+                           const int32_t* flag, hipStream_t s) {
+  k_residual<<<1, 1024, 0, s>>>(m.nc, cellred, resid, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit_W(int D, const DevMesh& m, const double* Wn, double* W,
+                           const int32_t* flag, hipStream_t s) {
+  UGKS_DISPATCH_D(D, k_commit_W<DD><<<blocks_for(m.nc * (DD + 2), 256), 256, 0, s>>>(m.nc, Wn, W, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_init_maxwellian(int D, int prec, const DevMesh& m, const DevVel& v,
+                                  const double* prim, void* h, void* b, hipStream_t s) {
+  const unsigned grid = blocks_for(v.nvp, TPB) * (unsigned)m.nc;
+  UGKS_DISPATCH_DT(D, prec, k_init_maxwellian<DD, TT><<<grid, TPB, 0, s>>>(v, prim, (TT*)h, (TT*)b));
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int D, int prec, const DevMesh& m, const DevVel& v, const void* h,
+                          const void* b, double* out, hipStream_t s) {
+  UGKS_DISPATCH_DT(D, prec, k_moments<DD, TT><<<(unsigned)m.nc, TPB, 0, s>>>(v, (const TT*)h, (const TT*)b, out));
+  return hipGetLastError();
+}
+
+hipError_t launch_dt_cells(int D, const DevMesh& m, const DevVel& v, double* cellval,
+                           hipStream_t s) {
+  UGKS_DISPATCH_D(D, k_dt_cells<DD><<<(unsigned)m.nc, TPB, 0, s>>>(m, v, cellval));
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_rho(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
+                           const void* h, const double* gh, double* frec, const int32_t* flag,
+                           hipStream_t s) {
+  if (m.nwall == 0) return hipSuccess;
+  UGKS_DISPATCH_DT(D, prec, k_wall_rho<DD, TT><<<(unsigned)m.nwall, TPB, 0, s>>>(
+      m, v, g, (const TT*)h, gh, frec, flag));
+  return hipGetLastError();
+}
+
+}  // namespace ugks

@@ -1,0 +1,242 @@
+"""Thin ctypes binding of libugks.so (the C ABI in include/ugks.h).
+
+The functions carry the C names and only marshal arguments: every step of the
+method runs in the library's HIP kernels.  If the shared library has not been
+built, loading raises instead of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libugks.so")
+
+UGKS_OK, UGKS_EINVAL, UGKS_ENOMEM, UGKS_EHIP, UGKS_ENUMERIC, UGKS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+UGKS_BC_INTERIOR, UGKS_BC_WALL, UGKS_BC_FARFIELD, UGKS_BC_OUTFLOW = 0, 1, 2, 3
+UGKS_FP64, UGKS_FP32 = 64, 32
+
+# every entry point include/ugks.h declares
+EXPORTED = [
+    "ugks_create", "ugks_step", "ugks_moments", "ugks_get_state", "ugks_set_state",
+    "ugks_face_data", "ugks_info", "ugks_destroy", "ugks_last_error",
+]
+
+
+class ugks_mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
+                ("cell_volume", C.c_void_p), ("cell_centroid", C.c_void_p),
+                ("face_cells", C.c_void_p), ("face_area", C.c_void_p),
+                ("face_normal", C.c_void_p), ("face_centroid", C.c_void_p),
+                ("face_shift", C.c_void_p), ("face_bc", C.c_void_p), ("face_bc_id", C.c_void_p)]
+
+
+class ugks_velocity(C.Structure):
+    _fields_ = [("nv", C.c_int64), ("u", C.c_void_p), ("w", C.c_void_p)]
+
+
+class ugks_gas(C.Structure):
+    _fields_ = [("K", C.c_int32), ("Pr", C.c_double), ("R", C.c_double), ("T_ref", C.c_double),
+                ("mu_ref", C.c_double), ("omega", C.c_double), ("cfl", C.c_double),
+                ("dt", C.c_double)]
+
+
+class ugks_bc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("rho", C.c_double), ("U", C.c_double * 3), ("T", C.c_double)]
+
+
+class ugks_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("block_v", C.c_int32), ("flags", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class ugks_info_t(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_r", C.c_int32), ("precision", C.c_int32),
+                ("block_v", C.c_int32), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
+                ("nv", C.c_int64), ("nv_padded", C.c_int64), ("dt", C.c_double),
+                ("steps_done", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libugks.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run __graft_entry__.build() (hipcc for gfx950) first")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.ugks_create.restype = C.c_int
+    lib.ugks_create.argtypes = [C.POINTER(ugks_mesh), C.POINTER(ugks_velocity), C.POINTER(ugks_gas),
+                                P, C.c_int32, P, C.POINTER(ugks_options), C.POINTER(C.c_void_p)]
+    lib.ugks_step.restype = C.c_int
+    lib.ugks_step.argtypes = [P, C.c_int32, P]
+    lib.ugks_moments.restype = C.c_int
+    lib.ugks_moments.argtypes = [P, C.c_int32, P, C.c_int32]
+    lib.ugks_get_state.restype = C.c_int
+    lib.ugks_get_state.argtypes = [P, P, P, P]
+    lib.ugks_set_state.restype = C.c_int
+    lib.ugks_set_state.argtypes = [P, P, P, P]
+    lib.ugks_face_data.restype = C.c_int
+    lib.ugks_face_data.argtypes = [P, P, P]
+    lib.ugks_info.restype = C.c_int
+    lib.ugks_info.argtypes = [P, C.POINTER(ugks_info_t)]
+    lib.ugks_destroy.restype = None
+    lib.ugks_destroy.argtypes = [P]
+    lib.ugks_last_error.restype = C.c_char_p
+    lib.ugks_last_error.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+class UGKSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"UGKS error {code}: {msg}")
+        self.code = code
+
+
+def _p(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _f8(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, ctx=None):
+    if rc != UGKS_OK:
+        lib = load_library()
+        msg = lib.ugks_last_error(ctx)
+        raise UGKSError(rc, msg.decode() if msg else "")
+
+
+def ugks_create(mesh, vel, gas, bcs, W0, precision=UGKS_FP64, block_v=0, flags=0, stream=None):
+    """Create a context from a ``ugks_cases`` mesh / velocity / gas / BC list.
+
+    Returns ``(handle, keepalive)``; the arrays are copied by the library, so
+    keepalive only needs to live for the call.
+    """
+    lib = load_library()
+    m = mesh.contiguous()
+    keep = dict(mesh=m, u=_f8(vel.u), w=_f8(vel.w), W0=_f8(W0))
+    cm = ugks_mesh(m.dim, m.n_cells, m.n_faces, _p(m.cell_volume), _p(m.cell_centroid),
+                   _p(m.face_cells), _p(m.face_area), _p(m.face_normal), _p(m.face_centroid),
+                   _p(m.face_shift), _p(m.face_bc), _p(m.face_bc_id))
+    cv = ugks_velocity(vel.nv, _p(keep["u"]), _p(keep["w"]))
+    cg = ugks_gas(gas.K, gas.Pr, gas.R, gas.T_ref, gas.mu_ref, gas.omega, gas.cfl, gas.dt)
+    nb = len(bcs)
+    arr = (ugks_bc * max(nb, 1))()
+    for i, b in enumerate(bcs):
+        U = list(b.U) + [0.0] * (3 - len(b.U))
+        arr[i] = ugks_bc(b.kind, b.rho, (C.c_double * 3)(*U[:3]), b.T)
+    opt = ugks_options(precision, block_v, flags, C.c_void_p(stream) if stream else None)
+    h = C.c_void_p()
+    rc = lib.ugks_create(C.byref(cm), C.byref(cv), C.byref(cg), C.cast(arr, C.c_void_p), nb,
+                         _p(keep["W0"]), C.byref(opt), C.byref(h))
+    _check(rc, None)
+    return h, keep
+
+
+def ugks_step(h, n_steps: int):
+    res = np.zeros(2)
+    _check(load_library().ugks_step(h, int(n_steps), _p(res)), h)
+    return res
+
+
+def ugks_moments(h, which: int, out, on_device: bool = False):
+    ptr = C.c_void_p(out.data_ptr()) if on_device else _p(out)
+    _check(load_library().ugks_moments(h, int(which), ptr, 1 if on_device else 0), h)
+    return out
+
+
+def ugks_get_state(h, W, hdist, bdist):
+    _check(load_library().ugks_get_state(h, _p(W), _p(hdist), _p(bdist)), h)
+
+
+def ugks_set_state(h, W, hdist, bdist):
+    W = None if W is None else _f8(W)
+    hdist = None if hdist is None else _f8(hdist)
+    bdist = None if bdist is None else _f8(bdist)
+    _check(load_library().ugks_set_state(h, _p(W), _p(hdist), _p(bdist)), h)
+
+
+def ugks_face_data(h, F, rho_w):
+    _check(load_library().ugks_face_data(h, _p(F), _p(rho_w)), h)
+
+
+def ugks_info(h) -> dict:
+    info = ugks_info_t()
+    _check(load_library().ugks_info(h, C.byref(info)), h)
+    return {f: getattr(info, f) for f, _ in ugks_info_t._fields_}
+
+
+def ugks_destroy(h):
+    if h:
+        load_library().ugks_destroy(h)
+
+
+def ugks_last_error(h=None) -> str:
+    s = load_library().ugks_last_error(h)
+    return s.decode() if s else ""
+
+
+class Solver:
+    """Owning wrapper around one library context for a ``ugks_cases.Case``."""
+
+    def __init__(self, case, precision=UGKS_FP64, block_v=0, flags=0, stream=None):
+        self.case = case
+        self.dim = case.mesh.dim
+        self.nc, self.nf, self.nv = case.mesh.n_cells, case.mesh.n_faces, case.vel.nv
+        self.h, _ = ugks_create(case.mesh, case.vel, case.gas, case.bcs, case.W0,
+                                precision=precision, block_v=block_v, flags=flags, stream=stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            ugks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def info(self) -> dict:
+        return ugks_info(self.h)
+
+    @property
+    def dt(self) -> float:
+        return self.info["dt"]
+
+    def step(self, n: int = 1):
+        r = ugks_step(self.h, n)
+        return float(r[0]), float(r[1])
+
+    def W(self):
+        out = np.zeros((self.nc, self.dim + 2))
+        return ugks_moments(self.h, 0, out)
+
+    def moments(self, which: int):
+        ncol = self.dim if which == 2 else self.dim + 2
+        out = np.zeros((self.nc, ncol))
+        return ugks_moments(self.h, which, out)
+
+    def state(self, with_h: bool = True):
+        W = np.zeros((self.nc, self.dim + 2))
+        hd = np.zeros((self.nc, self.nv)) if with_h else None
+        bd = np.zeros((self.nc, self.nv)) if with_h else None
+        ugks_get_state(self.h, W, hd, bd)
+        return W, hd, bd
+
+    def set_state(self, W=None, h=None, b=None):
+        ugks_set_state(self.h, W, h, b)
+
+    def faces(self):
+        F = np.zeros((self.nf, self.dim + 2))
+        rw = np.zeros(self.nf)
+        ugks_face_data(self.h, F, rw)
+        return F, rw

@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports what include/ugks.h declares, and rejects bad input.
+
+These run without a GPU: only validation paths that fail before any HIP call
+are exercised.
+"""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import ugks_cases as uc
+from paper_2606_15720_amd import ugks
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ugks.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ugks_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_what_the_binding_lists():
+    assert _declared() == sorted(ugks.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ugks.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = os.popen(f"nm -D --defined-only {ugks.LIB_PATH}").read()
+    for name in _declared():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_library_is_built_for_gfx950():
+    blob = open(ugks.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob
+
+
+def _create(case, **kw):
+    return ugks.ugks_create(case.mesh, case.vel, case.gas, case.bcs, case.W0, **kw)
+
+
+def test_rejects_polyatomic_gas():
+    case = uc.cavity2d(n=4, nv=4)
+    case.gas.K = 2
+    with pytest.raises(ugks.UGKSError) as e:
+        _create(case)
+    assert e.value.code == ugks.UGKS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("what", ["volume", "normal", "weight", "bcid", "state", "precision", "open"])
+def test_rejects_invalid_input(what):
+    case = uc.cavity2d(n=4, nv=4)
+    m = case.mesh
+    kw = {}
+    if what == "volume":
+        m.cell_volume[3] = -1.0
+    elif what == "normal":
+        m.face_normal[5] *= 2.0
+    elif what == "weight":
+        case.vel.w[0] = 0.0
+    elif what == "bcid":
+        m.face_bc_id[m.face_bc == 1] = 9
+    elif what == "state":
+        case.W0[2, 3] = 0.0
+    elif what == "precision":
+        kw["precision"] = 16
+    elif what == "open":
+        m.face_area[7] *= 1.5
+    with pytest.raises(ugks.UGKSError) as e:
+        _create(case, **kw)
+    assert e.value.code == ugks.UGKS_EINVAL
+    assert ugks.ugks_last_error(None)

@@ -1,0 +1,139 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Both sides start from the same seeded inputs (``ugks_cases``) and compute
+everything else independently.  Tolerances (FP64): the oracle sums in a fixed
+sequential order with FP contraction off, the GPU sums with wave trees and
+fuses multiply-adds, so each step differs by a few ulps.  The bound is
+max_i |W_gpu - W_cpu| <= tol * scale_c per conserved component c, with
+tol = 1e-12 and scale_c the component's natural magnitude: max_i rho_i for
+rho, max_i rho_i sqrt(2 E_i) (density times a speed that includes the
+thermal speed) for each momentum component, max_i rho_i E_i for energy.  A
+momentum component that is zero up to round-off is thus not divided by its
+own noise.
+"""
+
+import numpy as np
+import pytest
+
+import ugks_cases as uc
+from oracle import Oracle
+from paper_2606_15720_amd.ugks import UGKS_FP32, Solver, UGKSError, UGKS_ENUMERIC
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _scales(W):
+    D = W.shape[1] - 2
+    rho, rE = W[:, 0], W[:, D + 1]
+    mom = np.max(np.sqrt(2.0 * rho * rE))
+    return np.array([rho.max()] + [mom] * D + [np.abs(rE).max()])
+
+
+def _normwise(a, b):
+    """max_i |a - b| / scale_c per conserved component c (see module docstring)."""
+    return np.abs(a - b).max(axis=0) / _scales(b)
+
+
+def _normwise_F(a, b):
+    """Face fluxes: relative to the largest flux magnitude over all components."""
+    return np.abs(a - b).max(axis=0) / max(np.abs(b).max(), 1e-300)
+
+
+def _compare_step(case, steps, check_h_every=None, tol=TOL):
+    o = Oracle(case)
+    s = Solver(case)
+    assert s.dt == pytest.approx(o.dt, rel=1e-14)
+    done = 0
+    while done < steps:
+        n = 1 if done == 0 else (steps - done)
+        o.step(n)
+        s.step(n)
+        done += n
+        Wo, ho, bo, qo = o.state()
+        Wg, hg, bg = s.state()
+        err = _normwise(Wg, Wo)
+        print(f"{case.name} step {done}: W normwise err {err}", flush=True)
+        assert np.all(err <= tol), err
+        herr = np.abs(hg - ho).max() / np.abs(ho).max()
+        assert herr <= tol, herr
+        if case.mesh.dim == 2:
+            berr = np.abs(bg - bo).max() / np.abs(bo).max()
+            assert berr <= tol, berr
+        if done == 1:
+            Fo, rwo, _, _ = o.faces()
+            Fg, rwg = s.faces()
+            ferr = _normwise_F(Fg, Fo)
+            assert np.all(ferr <= 1e-13), ferr
+            wall = case.mesh.face_bc == 1
+            np.testing.assert_allclose(rwg[wall], rwo[wall], rtol=1e-13, atol=1e-15)
+            qg = s.moments(2)
+            # heat flux scale: rho E times a speed of order one
+            np.testing.assert_allclose(qg, qo, rtol=0, atol=1e-13 * np.abs(Wo[:, -1]).max())
+    s.close()
+
+
+def test_cavity2d_config1_parity_100_steps():
+    # the full 2-D lid-driven cavity: 32x32 quads, 28^2 velocities, 100 steps
+    _compare_step(uc.cavity2d(), 100)
+
+
+def test_sod3d_small_parity():
+    _compare_step(uc.sod3d_tets(n=4, nv=8, jitter=0.15, seed=3), 10)
+
+
+def test_couette_periodic_parity():
+    _compare_step(uc.couette2d(n=12, nv=16, kn=0.05), 20)
+
+
+def test_ragged_velocity_tail_and_tiny_mesh():
+    # 7^2 = 49 velocities: one partly padded block; 3x3 cells
+    _compare_step(uc.cavity2d(n=3, nv=7, kn=1.0), 5)
+
+
+@pytest.mark.parametrize("kn", [1e-3, 10.0])
+def test_kn_extremes_parity(kn):
+    # continuum-like (dt/tau >> 1) and free-molecular-like (dt/tau << 1)
+    _compare_step(uc.cavity2d(n=8, nv=12, kn=kn), 10)
+
+
+def test_block_size_and_padding_invariance():
+    case = uc.cavity2d(n=8, nv=28)
+    Ws = []
+    for bv in (64, 128, 256):
+        s = Solver(case, block_v=bv)
+        assert s.info["nv_padded"] % bv == 0
+        s.step(5)
+        Ws.append(s.W())
+        s.close()
+    for W in Ws[1:]:
+        np.testing.assert_allclose(W, Ws[0], rtol=0, atol=1e-15)
+
+
+def test_fp32_form_error_against_fp64_oracle():
+    case = uc.cavity2d(n=16, nv=20)
+    o = Oracle(case)
+    s = Solver(case, precision=UGKS_FP32)
+    o.step(50)
+    s.step(50)
+    err = _normwise(s.W(), o.state(with_h=False)[0])
+    print("FP32 form normwise error after 50 steps:", err, flush=True)
+    assert np.all(err < 1e-5)
+
+
+def test_numeric_failure_is_reported_and_state_kept():
+    case = uc.cavity2d(n=4, nv=8)
+    s = Solver(case)
+    s.step(2)
+    W, h, b = s.state()
+    bad = W.copy()
+    bad[1, 3] = -1.0  # negative energy
+    s.set_state(bad, h, b)
+    with pytest.raises(UGKSError) as e:
+        s.step(3)
+    assert e.value.code == UGKS_ENUMERIC
+    W2, h2, _ = s.state()
+    np.testing.assert_array_equal(W2, bad)
+    np.testing.assert_array_equal(h2, h)
+    s.close()
