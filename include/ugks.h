@@ -132,6 +132,13 @@ typedef struct {
  *   precision  UGKS_FP64 (default when 0) or UGKS_FP32.
  *   block_v    velocity-block size B_v (64, 128, 256); 0 = library choice.
  *   flags      bit 0: skip the density residual (saves one small reduction).
+ *              bit 1: use the staged sweep even where the fused one applies.
+ *   The fused sweep (one pass for reconstruction, interface flux, moment
+ *   sums and the first stage) applies when the velocity set is a tensor
+ *   product of one 1-D node set symmetric about zero, listed with the first
+ *   axis slowest, every cell has at most 4 faces and every boundary face is a
+ *   wall.  Otherwise the staged sweep keeps the microscopic gradients and
+ *   fluxes of the whole velocity space in device memory.
  *   stream     hipStream_t to enqueue on, or NULL for a library-owned stream.
  *              A caller stream is borrowed, never destroyed.
  */
@@ -150,6 +157,7 @@ typedef struct {
   double dt;
   int64_t steps_done;
   int64_t device_bytes;      /* device memory held by the context */
+  int32_t fused;             /* 1: the fused sweep runs; 0: the staged sweep */
 } ugks_info_t;
 
 /*

@@ -231,6 +231,37 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     w[k] = vel->w[k];
     u2[k] = s;
   }
+  // ---- fused-path eligibility ----------------------------------------------
+  // A tensor product of one symmetric 1-D node set, first axis slowest, so
+  // that point k and its mirror -u_k = u_{nv-1-k} are known by index.
+  std::vector<double> ax;
+  {
+    std::vector<double> a0;
+    for (int64_t k = 0; k < nv; ++k) a0.push_back(vel->u[k * D]);
+    std::sort(a0.begin(), a0.end());
+    a0.erase(std::unique(a0.begin(), a0.end()), a0.end());
+    bool ok = !(c->flags & 2);
+    const int64_t na = (int64_t)a0.size();
+    int64_t prod = 1;
+    for (int d = 0; d < D; ++d) prod *= na;
+    ok = ok && prod == nv && na <= 64;
+    for (int64_t n = 0; ok && n < na; ++n) ok = a0[na - 1 - n] == -a0[n];
+    for (int64_t k = 0; ok && k < nv; ++k) {
+      int64_t r = k;
+      for (int d = D - 1; d >= 0 && ok; --d) {
+        ok = vel->u[k * D + d] == a0[r % na];
+        r /= na;
+      }
+    }
+    for (int64_t f = 0; ok && f < nf; ++f)
+      ok = mesh->face_bc[f] == UGKS_BC_INTERIOR || mesh->face_bc[f] == UGKS_BC_WALL;
+    for (int64_t i = 0; ok && i < nc; ++i) ok = nfc[i] <= 4;
+    c->fused = ok;
+    if (ok) {
+      ax = a0;
+      c->fmesh.na = (int)na;
+    }
+  }
   // ---- initial state check ---------------------------------------------
   for (int64_t i = 0; i < nc; ++i) {
     const double* Wi = &W0[i * (D + 2)];
@@ -284,6 +315,64 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     fail_if(bcs[i].kind != UGKS_BC_OUTFLOW && !(bcs[i].T > 0.0), "boundary temperature must be positive");
   }
   c->bcs = upload(c, hb);
+  if (c->fused) {
+    // static records of the fused sweep: the cell's faces, its least-squares
+    // stencil and, per face, the neighbour's stencil, all wave-uniform
+    std::vector<int32_t> ci(nc * CRI, -1);
+    std::vector<double> cdr(nc * CRD, 0.0);
+    auto stencil = [&](int64_t cell, int32_t* cells, double* G /* [d*4 + s] */) {
+      int n = 0;
+      for (int p = 0; p < nfc[cell]; ++p) {
+        int j = cnbr[cell * MAXF + p];
+        if (j < 0) continue;  // a wall row adds nothing to the gradient
+        cells[n] = j;
+        for (int d = 0; d < 3; ++d) G[d * 4 + n] = lsG[(cell * 3 + d) * MAXF + p];
+        ++n;
+      }
+      return n;
+    };
+    for (int64_t i = 0; i < nc; ++i) {
+      int32_t* I = &ci[i * CRI];
+      double* Dd = &cdr[i * CRD];
+      I[0] = nfc[i];
+      I[1] = stencil(i, &I[2], Dd);
+      for (int p = 0; p < nfc[i]; ++p) {
+        int32_t* fi = &I[CRI_F0 + CRI_FS * p];
+        double* fd = &Dd[CRD_F0 + CRD_FS * p];
+        const int f = cface[i * MAXF + p];
+        const double sg = csign[i * MAXF + p];
+        const int j = cnbr[i * MAXF + p];
+        fi[0] = f;
+        fi[1] = fbc[f];
+        fi[2] = sg > 0.0 ? 1 : 0;
+        fi[3] = j;
+        fi[4] = j >= 0 ? stencil(j, &fi[5], &fd[10]) : 0;
+        for (int d = 0; d < 3; ++d) {
+          fd[0 + d] = sg * fnorm[f * 3 + d];
+          fd[4 + d] = sg > 0.0 ? fdxL[f * 3 + d] : fdxR[f * 3 + d];
+          fd[7 + d] = sg > 0.0 ? fdxR[f * 3 + d] : fdxL[f * 3 + d];
+        }
+        fd[3] = farea[f] / mesh->cell_volume[i];
+      }
+    }
+    std::vector<int32_t> vidx(nv);
+    const int64_t na = c->fmesh.na;
+    for (int64_t k = 0; k < nv; ++k) {
+      int64_t r = k;
+      int32_t packed = 0;
+      for (int d = D - 1; d >= 0; --d) {
+        packed |= (int32_t)(r % na) << (8 * d);
+        r /= na;
+      }
+      vidx[k] = packed;
+    }
+    c->fmesh.nc = nc;
+    c->fmesh.nv = nv;
+    c->fmesh.axis = upload(c, ax);
+    c->fmesh.vidx = upload(c, vidx);
+    c->fmesh.crec_i = upload(c, ci);
+    c->fmesh.crec_d = upload(c, cdr);
+  }
   c->cell_perm.resize(nc);
   for (int64_t i = 0; i < nc; ++i) c->cell_perm[i] = i;
   c->face_perm.resize(nf);
@@ -297,17 +386,26 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   B.prim = dalloc<double>(c, nc * NPRIM);
   B.primn = dalloc<double>(c, nc * NPRIM);
   B.q = dalloc<double>(c, nc * 3);
+  B.qn = dalloc<double>(c, nc * 3);
   B.gW = dalloc<double>(c, nc * 15);
   B.frec = dalloc<double>(c, nf * FREC);
   B.F = dalloc<double>(c, nf * 5);
+  B.dW = dalloc<double>(c, nc * 5);
+  if (c->fused) {
+    B.cs = dalloc<double>(c, nc * CSREC);
+    B.csn = dalloc<double>(c, nc * CSREC);
+  }
   B.h = dalloc<char>(c, (size_t)nc * nvp * esz);
   B.ht = dalloc<char>(c, (size_t)nc * nvp * esz);
   B.b = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)nc * nvp * esz) : nullptr;
   B.bt = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)nc * nvp * esz) : nullptr;
-  B.gradh = dalloc<double>(c, (size_t)nc * 3 * nvp);
-  B.gradb = c->nr == 2 ? dalloc<double>(c, (size_t)nc * 3 * nvp) : nullptr;
-  B.fluxh = dalloc<double>(c, (size_t)nf * nvp);
-  B.fluxb = c->nr == 2 ? dalloc<double>(c, (size_t)nf * nvp) : nullptr;
+  if (!c->fused) {
+    // the staged sweep keeps every gradient and microscopic flux in HBM
+    B.gradh = dalloc<double>(c, (size_t)nc * 3 * nvp);
+    B.gradb = c->nr == 2 ? dalloc<double>(c, (size_t)nc * 3 * nvp) : nullptr;
+    B.fluxh = dalloc<double>(c, (size_t)nf * nvp);
+    B.fluxb = c->nr == 2 ? dalloc<double>(c, (size_t)nf * nvp) : nullptr;
+  }
   B.resid = dalloc<double>(c, 8);
   B.cellred = dalloc<double>(c, nc * 3);
   B.flag = dalloc<int32_t>(c, 4);
@@ -349,8 +447,46 @@ int set_err(ugks_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
+// One time step of the fused path, enqueued.
+void enqueue_step_fused(ugks_ctx* c) {
+  const int D = c->D, P = c->prec;
+  const DevMesh& m = c->mesh;
+  const DevVel& v = c->vel;
+  const GasP& g = c->gas;
+  StepBuffers& B = c->buf;
+  hipStream_t s = c->stream;
+  // 2 heat flux of h^n: carried over from the previous second stage once valid
+  if (!c->q_valid) {
+    HIP_TRY(launch_prims(D, m, g, B.W, B.prim, B.flag, 1, s));
+    HIP_TRY(launch_heatflux(D, P, m, v, B.h, B.b, B.prim, B.q, B.flag, s));
+    c->q_valid = true;
+  }
+  // 1 primitives of W^n and the cell equilibrium data of the first stage
+  HIP_TRY(launch_cell_prep(D, c->nc, g, B.W, B.q, B.prim, B.cs, B.flag, s));
+  // 4 macroscopic reconstruction; 6.1-6.6 interface equilibrium
+  HIP_TRY(launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
+  HIP_TRY(launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
+  // 7 wall densities
+  HIP_TRY(launch_wall_rho_inline(D, P, m, v, g, B.h, B.frec, B.flag, s));
+  // 5, 6.7-6.8, 9: the fused velocity sweep
+  HIP_TRY(launch_sweep(D, P, c->fmesh, v, g, B.prim, B.cs, B.frec, B.h, B.b, B.ht, B.bt, B.dW,
+                       B.flag, s));
+  // 8 conservative update; 10 new equilibrium (with q^n, reading R17)
+  HIP_TRY(launch_apply_dW(D, m, B.W, B.dW, B.Wn, B.cellred, B.flag, s));
+  HIP_TRY(launch_cell_prep(D, c->nc, g, B.Wn, B.q, B.primn, B.csn, B.flag, s));
+  // 11 second stage and the heat flux of h^{n+1}
+  HIP_TRY(launch_stage2_q(D, P, c->fmesh, v, B.primn, B.csn, B.ht, B.bt, B.h, B.b, B.qn, B.flag, s));
+  std::swap(B.q, B.qn);
+  if (!(c->flags & 1)) HIP_TRY(launch_residual(m, B.cellred, B.resid, B.flag, s));
+  HIP_TRY(launch_commit_W(D, m, B.Wn, B.W, B.flag, s));
+}
+
 // One time step, enqueued (the one-step algorithm).
 void enqueue_step(ugks_ctx* c) {
+  if (c->fused) {
+    enqueue_step_fused(c);
+    return;
+  }
   const int D = c->D, P = c->prec;
   const DevMesh& m = c->mesh;
   const DevVel& v = c->vel;
@@ -453,9 +589,9 @@ int ugks_moments(ugks_ctx* c, int32_t which, double* out, int32_t on_device) {
       HIP_TRY(hipMemcpyAsync(lib.data(), tmp, c->nc * ncol * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     } else if (which == 2) {
       HIP_TRY(launch_prims(D, c->mesh, c->gas, c->buf.W, c->buf.prim, c->buf.flag, 0, c->stream));
-      HIP_TRY(launch_heatflux(D, c->prec, c->mesh, c->vel, c->buf.h, c->buf.b, c->buf.prim, c->buf.q,
+      HIP_TRY(launch_heatflux(D, c->prec, c->mesh, c->vel, c->buf.h, c->buf.b, c->buf.prim, c->buf.qn,
                               c->buf.flag, c->stream));
-      HIP_TRY(hipMemcpyAsync(lib.data(), c->buf.q, c->nc * 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipMemcpyAsync(lib.data(), c->buf.qn, c->nc * 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     } else {
       return set_err(c, UGKS_EINVAL, "which must be 0, 1 or 2");
     }
@@ -537,6 +673,7 @@ int ugks_set_state(ugks_ctx* c, const double* W, const double* h, const double* 
       }
     }
     // a new state restarts the residual normalisation and clears a failure
+    c->q_valid = false;
     HIP_TRY(hipMemset(c->buf.resid, 0, 8 * sizeof(double)));
     HIP_TRY(hipMemset(c->buf.flag, 0, 4 * sizeof(int32_t)));
   } catch (const HipFail& e) {
@@ -584,6 +721,7 @@ int ugks_info(const ugks_ctx* c, ugks_info_t* out) {
   out->dt = c->gas.dt;
   out->steps_done = c->steps_done;
   out->device_bytes = c->bytes;
+  out->fused = c->fused ? 1 : 0;
   return UGKS_OK;
 }
 

@@ -14,7 +14,7 @@ namespace ugks {
 
 constexpr int MAXF = 8;    // faces per cell
 constexpr int NPRIM = 8;   // rho, U[3], lambda, tau, p, spare
-constexpr int FREC = 48;   // doubles per face record
+constexpr int FREC = 96;   // doubles per face record
 constexpr int WAVE = 64;
 
 // Face record layout (doubles).  Interior / far-field faces hold the
@@ -33,6 +33,8 @@ enum FaceRec : int {
   FR_GU = 36,
   FR_GLAM = 39,
   FR_GC = 40,    // ghost: rho_g (lambda_g/pi)^(D/2)
+  FR_PH = 48,    // cubic polynomial PH(u) of the h-equation equilibrium terms (20)
+  FR_PB = 68,    // cubic polynomial PB(u) of the b-equation equilibrium terms (20, 2-D)
 };
 
 struct DevMesh {
@@ -59,6 +61,31 @@ struct DevMesh {
   int64_t nwall;
 };
 
+// Static per-cell records of the fused sweep (built once at create).
+// Integer record (CRI ints per cell):
+//   [0] faces, [1] own stencil size, [2..5] own stencil cells,
+//   face p at CRI_F0 + CRI_FS p: [0] face id, [1] kind, [2] 1 if the cell is L,
+//   [3] neighbour cell (-1 on a wall), [4] neighbour stencil size,
+//   [5..8] neighbour stencil cells.
+// Double record (CRD doubles per cell):
+//   [d*4 + s] own least-squares coefficients G[d][s],
+//   face p at CRD_F0 + CRD_FS p: [0..2] outward unit normal, [3] S/V,
+//   [4..6] x_f - x_cell, [7..9] x_f - x_neighbour, [10 + d*4 + r] the
+//   neighbour's coefficients G[d][r].
+constexpr int CRI = 48, CRI_F0 = 6, CRI_FS = 10;
+constexpr int CRD = 104, CRD_F0 = 12, CRD_FS = 22;
+// Per-cell, per-step record of the fused path (CSREC doubles per cell).
+constexpr int CSREC = 48, CS_CC = 0, CS_KAP = 1, CS_NORM = 2, CS_SH = 4, CS_SB = 24;
+
+struct FusedMesh {
+  int64_t nc, nv;
+  int na;                   // nodes per velocity axis
+  const double* axis;       // [na] symmetric 1-D nodes
+  const int32_t* vidx;      // [nv] packed axis indices of point k (8 bits per axis, first axis low)
+  const int32_t* crec_i;    // [nc*CRI]
+  const double* crec_d;     // [nc*CRD]
+};
+
 struct DevVel {
   int64_t nv, nvp;          // true and padded counts
   const double* u;          // [3*nvp] SoA: u[d*nvp + k]
@@ -82,9 +109,13 @@ struct StepBuffers {
   double* prim;    // [nc*NPRIM] of W^n
   double* primn;   // [nc*NPRIM] of W^{n+1}
   double* q;       // [nc*3] heat flux of h^n
+  double* qn;      // [nc*3] heat flux of h^{n+1} (fused path)
   double* gW;      // [nc*3*5]
   double* frec;    // [nf*FREC]
-  double* F;       // [nf*5]
+  double* F;       // [nf*5] face fluxes (staged sweep)
+  double* dW;      // [nc*5] per-cell net outflow moments (fused sweep)
+  double* cs;      // [nc*CSREC] per-step cell record of W^n (fused sweep)
+  double* csn;     // [nc*CSREC] per-step cell record of W^{n+1}
   void* h;         // [nc*nvp] storage type
   void* b;         // [nc*nvp] (2-D only)
   void* ht;        // [nc*nvp] first-stage result
@@ -137,11 +168,29 @@ hipError_t launch_moments(int D, int prec, const DevMesh& m, const DevVel& v, co
                           const void* b, double* out, hipStream_t s);
 hipError_t launch_dt_cells(int D, const DevMesh& m, const DevVel& v, double* cellval,
                            hipStream_t s);
+// fused sweep (ugks_sweep.hip)
+hipError_t launch_cell_prep(int D, int64_t nc, const GasP& g, const double* W, const double* q,
+                            double* prim, double* cs, int32_t* flag, hipStream_t s);
+hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, const GasP& g,
+                        const double* prim, const double* cs, const double* frec, const void* h,
+                        const void* b, void* ht, void* bt, double* dW, const int32_t* flag,
+                        hipStream_t s);
+hipError_t launch_apply_dW(int D, const DevMesh& m, const double* W, const double* dW, double* Wn,
+                          double* cellred, const int32_t* flag, hipStream_t s);
+hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v,
+                           const double* primn, const double* csn, const void* ht, const void* bt,
+                           void* h, void* b, double* qn, const int32_t* flag, hipStream_t s);
+hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
+                                  const GasP& g, const void* h, double* frec, const int32_t* flag,
+                                  hipStream_t s);
 
 }  // namespace ugks
 
 struct ugks_ctx {
   int D = 0, kxi = 0, nr = 0, prec = 64, Bv = 64, flags = 0;
+  bool fused = false;       // tensor-product symmetric velocity set, walls / interior only
+  bool q_valid = false;     // buf.q holds the heat flux of the current h
+  ugks::FusedMesh fmesh{};  // static records of the fused sweep
   int64_t nc = 0, nf = 0, nv = 0, nvp = 0;
   int64_t steps_done = 0;
   ugks::GasP gas{};

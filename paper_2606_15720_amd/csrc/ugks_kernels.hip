@@ -7,288 +7,13 @@
 // per-cell quantity (geometry, interface coefficients) is wave-uniform.
 // Sums over velocity use wave shuffles plus LDS in a fixed order, so the
 // results are deterministic.
-#include "ugks_internal.h"
-
-#include <cmath>
+#include "ugks_device.h"
 
 namespace ugks {
 
+using namespace dev;
+
 namespace {
-
-constexpr int TPB = 256;  // threads per block for velocity-parallel kernels
-
-template <typename T>
-__device__ __forceinline__ double ld(const T* p, int64_t i) {
-  return static_cast<double>(p[i]);
-}
-template <typename T>
-__device__ __forceinline__ void st(T* p, int64_t i, double v) {
-  p[i] = static_cast<T>(v);
-}
-
-// (lambda/pi)^(D/2)
-template <int D>
-__device__ __forceinline__ double maxw_norm(double lam) {
-  double r = lam * M_1_PI;
-  if constexpr (D == 2) return r;
-  else return r * sqrt(r);
-}
-
-// Primitive variables of a conservative state (monatomic, K = 0):
-// lambda = 3 rho / (4 (rho E - rho|U|^2/2)), p = rho/(2 lambda),
-// T = 1/(2 R lambda), tau = mu(T)/p with mu = mu_ref (T/T_ref)^omega.
-template <int D>
-__device__ __forceinline__ bool prim_of(const double* W, const GasP& g, double* P) {
-  double rho = W[0];
-  double u2 = 0.0;
-  double U[3] = {0.0, 0.0, 0.0};
-  for (int d = 0; d < D; ++d) {
-    U[d] = W[1 + d] / rho;
-    u2 += U[d] * U[d];
-  }
-  double eint = W[D + 1] - 0.5 * rho * u2;
-  double lam = 3.0 * rho / (4.0 * eint);
-  double p = rho / (2.0 * lam);
-  double T = 1.0 / (2.0 * g.R * lam);
-  double tau = g.muref * pow(T / g.Tref, g.omega) / p;
-  P[0] = rho;
-  P[1] = U[0];
-  P[2] = U[1];
-  P[3] = U[2];
-  P[4] = lam;
-  P[5] = tau;
-  P[6] = p;
-  P[7] = 0.0;
-  return (rho > 0.0) && (eint > 0.0) && isfinite(lam) && isfinite(tau);
-}
-
-// Conservative state of (rho, U, T) for a monatomic gas.
-template <int D>
-__device__ __forceinline__ void cons_of(double rho, const double* U, double T, double R, double* W) {
-  double u2 = 0.0;
-  W[0] = rho;
-  for (int d = 0; d < D; ++d) {
-    W[1 + d] = rho * U[d];
-    u2 += U[d] * U[d];
-  }
-  W[D + 1] = 0.5 * rho * u2 + 1.5 * rho * R * T;
-}
-
-// Far-field / outflow ghost state: free stream when it enters through the
-// face, otherwise the interior state.
-template <int D>
-__device__ __forceinline__ void ghost_state(int kind, const DevBC& bc, const double* n,
-                                            const double* Wi, double R, double* Wg) {
-  bool inflow = false;
-  if (kind == UGKS_BC_FARFIELD) {
-    double un = 0.0;
-    for (int d = 0; d < D; ++d) un += bc.U[d] * n[d];
-    inflow = un < 0.0;
-  }
-  if (inflow) {
-    cons_of<D>(bc.rho, bc.U, bc.T, R, Wg);
-  } else {
-    for (int v = 0; v < D + 2; ++v) Wg[v] = Wi[v];
-  }
-}
-
-// Reduce N per-thread values over a block of TPB threads; the result is
-// valid in thread 0.  Fixed order: wave shuffle tree, then waves in order.
-template <int N>
-__device__ __forceinline__ void block_sum(double (&v)[N], double* lds) {
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) v[n] += __shfl_down(v[n], off, WAVE);
-  }
-  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-  const int nw = blockDim.x / WAVE;
-  if (lane == 0)
-#pragma unroll
-    for (int n = 0; n < N; ++n) lds[n * 16 + wv] = v[n];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-      double s = lds[n * 16];
-      for (int w = 1; w < nw; ++w) s += lds[n * 16 + w];
-      v[n] = s;
-    }
-  }
-}
-
-__device__ __forceinline__ double block_max(double v, double* lds) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, WAVE));
-  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-  if (lane == 0) lds[wv] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) v = fmax(v, lds[w]);
-  }
-  return v;
-}
-
-// ---------------------------------------------------------------------------
-// Interface equilibrium (steps 6.1-6.6)
-
-// Half-range moments <u_n^m>_{s}, m = 0, 1, 2, of a unit-density 1-D
-// Maxwellian with mean Un; s = +1 for u_n > 0, -1 for u_n < 0.
-__device__ __forceinline__ void half_range(double Un, double lam, double s, double* m) {
-  double sl = sqrt(lam);
-  m[0] = 0.5 * erfc(-s * sl * Un);
-  m[1] = Un * m[0] + s * exp(-lam * Un * Un) / (2.0 * sqrt(M_PI * lam));
-  m[2] = Un * m[1] + m[0] / (2.0 * lam);
-}
-
-// Solve E[psi psi^T] a = b for a Maxwellian (U, lam) with 3 translational plus
-// internal degrees of freedom, by elimination of a_0, a_j, a_E.
-template <int D>
-__device__ __forceinline__ void slope_solve(const double* b, const double* U, double lam, double* a) {
-  const double N = 3.0;
-  double UU = 0.0, UR = 0.0, Rj[3];
-  for (int d = 0; d < D; ++d) {
-    UU += U[d] * U[d];
-    Rj[d] = b[1 + d] - U[d] * b[0];
-    UR += U[d] * Rj[d];
-  }
-  double e2 = UU + N / (2.0 * lam);
-  double RE = 2.0 * b[D + 1] - e2 * b[0];
-  double aE = 4.0 * lam * lam / N * (RE - 2.0 * UR);
-  double a0 = b[0] - 0.5 * aE * e2;
-  for (int d = 0; d < D; ++d) {
-    double aj = 2.0 * lam * Rj[d] - U[d] * aE;
-    a[1 + d] = aj;
-    a0 -= U[d] * aj;
-  }
-  a[0] = a0;
-  a[D + 1] = aE;
-}
-
-// Gaussian moment tables for the time slope.
-template <int D>
-struct Moments {
-  double m[3][6];   // E[u_d^n], n <= 5 (m[d][0] = 1; unused dims are delta at 0)
-  double x1, x2;    // E[xi^2], E[xi^4]
-  __device__ void init(const double* U, double lam) {
-    double var = 1.0 / (2.0 * lam);
-    for (int d = 0; d < 3; ++d) {
-      double mu = d < D ? U[d] : 0.0;
-      m[d][0] = 1.0;
-      m[d][1] = mu;
-      for (int n = 1; n < 5; ++n) m[d][n + 1] = mu * m[d][n] + n * var * m[d][n - 1];
-      if (d >= D)
-        for (int n = 1; n < 6; ++n) m[d][n] = 0.0;
-    }
-    const int kxi = 3 - D;
-    x1 = kxi * var;
-    x2 = kxi * (kxi + 2.0) * var * var;
-  }
-  // E[u^e] for an exponent vector
-  __device__ double E(int e0, int e1, int e2) const { return m[0][e0] * m[1][e1] * m[2][e2]; }
-  // E[u^e psi_E] with psi_E = (|u|^2 + xi^2)/2
-  __device__ double Epe(int e0, int e1, int e2) const {
-    double s = x1 * E(e0, e1, e2);
-    s += E(e0 + 2, e1, e2);
-    if (D >= 2) s += E(e0, e1 + 2, e2);
-    if (D >= 3) s += E(e0, e1, e2 + 2);
-    return 0.5 * s;
-  }
-  // E[u^e psi_E^2]
-  __device__ double Epe2(int e0, int e1, int e2) const {
-    int e[3] = {e0, e1, e2};
-    double s = x2 * E(e0, e1, e2);
-    for (int g = 0; g < D; ++g) {
-      int f[3] = {e[0], e[1], e[2]};
-      f[g] += 2;
-      s += 2.0 * x1 * E(f[0], f[1], f[2]);
-      for (int hh = 0; hh < D; ++hh) {
-        int k[3] = {f[0], f[1], f[2]};
-        k[hh] += 2;
-        s += E(k[0], k[1], k[2]);
-      }
-    }
-    return 0.25 * s;
-  }
-};
-
-// r_alpha = -sum_d E[u_d psi_alpha (a_d . psi)]  (compatibility condition for
-// the time slope).
-template <int D>
-__device__ __forceinline__ void time_slope_rhs(const Moments<D>& M, const double (*a)[5], double* r) {
-  for (int al = 0; al < D + 2; ++al) r[al] = 0.0;
-  for (int d = 0; d < D; ++d) {
-    int ed[3] = {0, 0, 0};
-    ed[d] = 1;
-    // alpha = 0: psi_0 = 1
-    {
-      double t = a[d][0] * M.E(ed[0], ed[1], ed[2]);
-      for (int e = 0; e < D; ++e) {
-        int k[3] = {ed[0], ed[1], ed[2]};
-        k[e] += 1;
-        t += a[d][1 + e] * M.E(k[0], k[1], k[2]);
-      }
-      t += a[d][D + 1] * M.Epe(ed[0], ed[1], ed[2]);
-      r[0] -= t;
-    }
-    // alpha = f: psi_f = u_f
-    for (int f = 0; f < D; ++f) {
-      int ef[3] = {ed[0], ed[1], ed[2]};
-      ef[f] += 1;
-      double t = a[d][0] * M.E(ef[0], ef[1], ef[2]);
-      for (int e = 0; e < D; ++e) {
-        int k[3] = {ef[0], ef[1], ef[2]};
-        k[e] += 1;
-        t += a[d][1 + e] * M.E(k[0], k[1], k[2]);
-      }
-      t += a[d][D + 1] * M.Epe(ef[0], ef[1], ef[2]);
-      r[1 + f] -= t;
-    }
-    // alpha = E: psi_E
-    {
-      double t = a[d][0] * M.Epe(ed[0], ed[1], ed[2]);
-      for (int e = 0; e < D; ++e) {
-        int k[3] = {ed[0], ed[1], ed[2]};
-        k[e] += 1;
-        t += a[d][1 + e] * M.Epe(k[0], k[1], k[2]);
-      }
-      t += a[d][D + 1] * M.Epe2(ed[0], ed[1], ed[2]);
-      r[D + 1] -= t;
-    }
-  }
-}
-
-// Time integrals of c_1..c_5 over [0, dt]; closed forms for dt/tau >= 1/2,
-// power series of the same functions below (they are exact rearrangements of
-// exp(-x); the closed forms cancel catastrophically for small x).
-__device__ __forceinline__ void time_coeffs(double dt, double tau, double* G) {
-  double x = dt / tau;
-  if (x >= 0.5) {
-    double E = -expm1(-x);
-    G[0] = tau * E;
-    G[1] = tau * tau * (x * (1.0 - E) - E);
-    G[2] = tau * (x - E);
-    G[3] = tau * tau * (2.0 * E - x * (2.0 - E));
-    G[4] = tau * tau * (0.5 * x * x - x + E);
-    return;
-  }
-  // term t_n = (-x)^n / n!; accumulate each series by its own coefficient
-  double t = 1.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
-  for (int n = 1; n <= 40; ++n) {
-    t *= -x / n;           // (-1)^n x^n / n!
-    s1 -= t;               // (-1)^(n+1) x^n/n!
-    s2 -= (n - 1) * t;     // (-1)^(n-1) (n-1) x^n/n!
-    s3 += (n >= 2) ? t : 0.0;
-    s4 -= (n >= 3) ? (2 - n) * t : 0.0;
-    s5 -= (n >= 3) ? t : 0.0;
-    if (fabs(t) < 1e-40) break;
-  }
-  G[0] = tau * s1;
-  G[1] = tau * tau * s2;
-  G[2] = tau * s3;
-  G[3] = tau * tau * s4;
-  G[4] = tau * tau * s5;
-}
 
 // ---------------------------------------------------------------------------
 template <int D>
@@ -470,10 +195,58 @@ __global__ void k_face_eq(DevMesh m, const DevBC* __restrict__ bcs, GasP g,
     for (int v = 0; v < 5; ++v) R[FR_A + d * 5 + v] = (d < D && v < D + 2) ? a[d][v] : 0.0;
   for (int v = 0; v < 5; ++v) R[FR_AT + v] = v < D + 2 ? At[v] : 0.0;
   // 6.6 interface heat flux
+  double q0[3] = {0.0, 0.0, 0.0};
   for (int d = 0; d < 3; ++d) {
     double ql = q[(int64_t)L * 3 + d];
     double qr = ghost ? 0.0 : q[(int64_t)Rc * 3 + d];
-    R[FR_Q + d] = d < D ? 0.5 * (ql + qr) : 0.0;
+    q0[d] = d < D ? 0.5 * (ql + qr) : 0.0;
+    R[FR_Q + d] = q0[d];
+  }
+  // All equilibrium terms of the time-integrated interface distribution,
+  //   Gamma3 (g0 + g0+) + Gamma4 u.grad g0 + Gamma5 d_t g0,
+  // equal g0(u) times a cubic polynomial in u: PH for h, PB for b.
+  {
+    using Cb = Cubic<D>;
+    double PH[Cb::N], PB[Cb::N];
+    for (int x = 0; x < Cb::N; ++x) PH[x] = PB[x] = 0.0;
+    const double kap = (3 - D) / (2.0 * lam0);                         // B0 / H0
+    const double xi4 = (3 - D) * (5.0 - D) / (4.0 * lam0 * lam0);     // int xi^4 g / H0
+    const double G3 = R[FR_G + 2], G4 = R[FR_G + 3], G5 = R[FR_G + 4];
+    const double sh = R[FR_SH];
+    double a0v[3], a4v[3], Am[9], Atl[3];
+    for (int d = 0; d < D; ++d) {
+      a0v[d] = a[d][0];
+      a4v[d] = a[d][D + 1];
+      Atl[d] = At[1 + d];
+      for (int e = 0; e < D; ++e) Am[d * 3 + e] = a[d][1 + e];
+    }
+    // Gamma3 (1 + H0+/H0)
+    Cb::add_const(PH, G3);
+    Cb::add_shakhov(PH, G3 * sh, U0, q0, lam0, 2.0 + D);
+    // Gamma4 sum_d u_d (P_d + a_d4 kap / 2), P_d = a_d0 + a_d.u + a_d4 |u|^2 / 2
+    Cb::add_lin(PH, G4, a0v);
+    Cb::add_mat(PH, G4, Am, 3);
+    Cb::add_lin_u2(PH, 0.5 * G4, a4v);
+    Cb::add_lin(PH, 0.5 * G4 * kap, a4v);
+    // Gamma5 (P_A + A4 kap / 2)
+    Cb::add_const(PH, G5 * (At[0] + 0.5 * At[D + 1] * kap));
+    Cb::add_lin(PH, G5, Atl);
+    Cb::add_u2(PH, 0.5 * G5 * At[D + 1]);
+    if (D == 2) {
+      Cb::add_const(PB, G3 * kap);
+      Cb::add_shakhov(PB, G3 * sh * kap, U0, q0, lam0, (double)D);
+      Cb::add_lin(PB, G4 * kap, a0v);
+      Cb::add_mat(PB, G4 * kap, Am, 3);
+      Cb::add_lin_u2(PB, 0.5 * G4 * kap, a4v);
+      Cb::add_lin(PB, 0.5 * G4 * xi4, a4v);
+      Cb::add_const(PB, G5 * (kap * At[0] + 0.5 * At[D + 1] * xi4));
+      Cb::add_lin(PB, G5 * kap, Atl);
+      Cb::add_u2(PB, 0.5 * G5 * kap * At[D + 1]);
+    }
+    for (int x = 0; x < 20; ++x) {
+      R[FR_PH + x] = x < Cb::N ? PH[x] : 0.0;
+      R[FR_PB + x] = x < Cb::N ? PB[x] : 0.0;
+    }
   }
 }
 

@@ -1,0 +1,600 @@
+// Fused velocity sweep for tensor-product, mirror-symmetric velocity sets.
+//
+// One work-group owns one cell and sweeps its whole velocity space.  Each
+// lane owns a mirror pair of velocities (u, -u): for every face of the cell
+// exactly one of the two leaves the cell, so the lane evaluates one
+// time-integrated flux from the cell's own reconstruction (outgoing) and one
+// from the neighbour's reconstruction (incoming), with no divergence between
+// lanes.  Face and cell data are wave-uniform and staged in LDS once per
+// work-group:
+//   * the Maxwellians g0, g_cell and the wall Maxwellian factor over the
+//     velocity axes, so exp(-lambda |u - U|^2) is a product of three LDS
+//     table entries;
+//   * every equilibrium term of the interface distribution (Eqs.
+//     interface_distribution, c123, c45 integrated over the step) as g0(u)
+//     times a cubic polynomial, evaluated from the lane's monomials with the
+//     even/odd split P(-u) = E(u) - O(u);
+//   * the least-squares stencils of the cell and of each neighbour.
+// The conservative update needs, per cell, sum_j sigma_j S_j F_j / V with
+// F_j = sum_k w_k psi_k H_jk (Eqs. macro_update, macro_flux); the sweep
+// regroups that sum by velocity, sum_k w_k psi_k (sum_j sigma_j S_j H_jk / V),
+// accumulates it per lane and reduces it once per work-group, so there are
+// no atomics and the result is deterministic.  The first stage (Eq. f_tilde)
+// is applied in the same pass.  All loads of an iteration (the cell's
+// stencil at u and -u, each neighbour's stencil at the incoming member) are
+// issued before any arithmetic so their latency overlaps.  Stage 2 (Eq. f_final) and the
+// heat flux of the new distribution are fused in a second kernel.
+#include "ugks_device.h"
+
+namespace ugks {
+
+using namespace dev;
+
+namespace {
+
+constexpr int SWF = 4;      // faces per cell on the fused path (triangles, quads, tets)
+constexpr int SWT = 256;    // threads per work-group
+constexpr int NAX = 64;     // nodes per velocity axis (max)
+
+// Even and odd parts of a cubic (monomial order of Cubic<D>) at u by nested
+// Horner forms:  P(u) = E(u) + O(u),  P(-u) = E(u) - O(u).
+template <int D>
+__device__ __forceinline__ void cubic_eo(const double* __restrict__ P, const double* v, double& E,
+                                         double& O) {
+  if constexpr (D == 3) {
+    const double x = v[0], y = v[1], z = v[2];
+    // quadratics xx yy zz xy xz yz = P[4..9], cubics xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz = P[10..19]
+    E = P[0] + x * (P[4] * x + P[7] * y + P[8] * z) + y * (P[5] * y + P[9] * z) + P[6] * z * z;
+    O = x * (P[1] + x * (P[10] * x + P[11] * y + P[12] * z) + y * (P[13] * y + P[14] * z) +
+             P[15] * z * z) +
+        y * (P[2] + y * (P[16] * y + P[17] * z) + P[18] * z * z) + z * (P[3] + P[19] * z * z);
+  } else {
+    const double x = v[0], y = v[1];
+    // quadratics xx yy xy = P[3..5], cubics xxx xxy xyy yyy = P[6..9]
+    E = P[0] + x * (P[3] * x + P[5] * y) + P[4] * y * y;
+    O = x * (P[1] + x * (P[6] * x + P[7] * y) + P[8] * y * y) + y * (P[2] + P[9] * y * y);
+  }
+}
+
+// Per-cell first-stage data of one step: dt/(2 tau), K_xi/(2 lambda) and the
+// Shakhov polynomials H+/H, B+/B of the cell's equilibrium (Eqs. H_plus, B_plus).
+template <int D>
+__global__ void k_cell_prep(int64_t nc, GasP g, const double* __restrict__ W,
+                            const double* __restrict__ q, double* __restrict__ prim,
+                            double* __restrict__ cs, int32_t* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nc || *flag) return;
+  double* P = &prim[i * NPRIM];
+  if (!prim_of<D>(&W[i * (D + 2)], g, P)) {
+    atomicOr(flag, 1);
+    return;
+  }
+  using Cb = Cubic<D>;
+  double SH[Cb::N], SB[Cb::N];
+  for (int x = 0; x < Cb::N; ++x) SH[x] = SB[x] = 0.0;
+  const double lam = P[4], rho = P[0];
+  const double sh = 4.0 * (1.0 - g.Pr) * lam * lam / (5.0 * rho);
+  const double U[3] = {P[1], P[2], P[3]};
+  const double qc[3] = {q[i * 3], q[i * 3 + 1], q[i * 3 + 2]};
+  Cb::add_shakhov(SH, sh, U, qc, lam, 2.0 + D);
+  Cb::add_shakhov(SB, sh, U, qc, lam, (double)D);
+  double* C = &cs[i * CSREC];
+  C[CS_CC] = g.dt / (2.0 * P[5]);
+  C[CS_KAP] = (3 - D) / (2.0 * lam);
+  C[CS_NORM] = rho * maxw_norm<D>(lam);
+  for (int x = 0; x < 20; ++x) {
+    C[CS_SH + x] = x < Cb::N ? SH[x] : 0.0;
+    C[CS_SB + x] = x < Cb::N ? SB[x] : 0.0;
+  }
+}
+
+// Axis tables of the face Maxwellians and of the cell Maxwellian in LDS.
+template <int D>
+__device__ __forceinline__ void build_tables(double (*tab)[3][NAX], double (*ctab)[NAX], double* ax,
+                                             const FusedMesh& fm, const GasP& g,
+                                             const double* __restrict__ prim,
+                                             const double* __restrict__ cs,
+                                             const double* __restrict__ frec, int64_t ic, int nf) {
+  const int na = fm.na;
+  const int32_t* ci = fm.crec_i + ic * CRI;
+  for (int t = threadIdx.x; t < na; t += SWT) ax[t] = fm.axis[t];
+  const int ntab = (nf + 1) * D * na;
+  for (int t = threadIdx.x; t < ntab; t += SWT) {
+    const int p = t / (D * na), r = t % (D * na);
+    const int d = r / na, n = r % na;
+    const double a = fm.axis[n];
+    if (p == nf) {
+      const double* P = &prim[ic * NPRIM];
+      const double lam = P[4], U = P[1 + d];
+      const double scale = d == 0 ? cs[ic * CSREC + CS_NORM] : 1.0;
+      ctab[d][n] = scale * exp(-lam * (a - U) * (a - U));
+    } else {
+      const int64_t f = ci[CRI_F0 + CRI_FS * p + 0];
+      const double* R = &frec[f * FREC];
+      const double lam = R[FR_LAM], U = R[FR_U + d];
+      double scale = 1.0;
+      if (d == 0)  // rho0 (lambda0/pi)^(D/2), or rho_w dt (lambda_w/pi)^(D/2) on a wall
+        scale = ci[CRI_F0 + CRI_FS * p + 1] == UGKS_BC_WALL ? R[FR_C0] * R[FR_RHOW] * g.dt : R[FR_C0];
+      tab[p][d][n] = scale * exp(-lam * (a - U) * (a - U));
+    }
+  }
+  __syncthreads();
+}
+
+// Every read-only array is its own __restrict__ kernel argument so that the
+// compiler can prove no store of the kernel clobbers it and serve the
+// wave-uniform reads from the scalar cache.
+template <int D, typename T>
+__global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
+    FusedMesh fm, GasP g, int64_t nvp, const int32_t* __restrict__ crec_i,
+    const double* __restrict__ crec_d, const int32_t* __restrict__ vidx,
+    const double* __restrict__ w, const double* __restrict__ prim, const double* __restrict__ cs,
+    const double* __restrict__ frec, const T* __restrict__ h, const T* __restrict__ b,
+    T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dW, const int32_t* __restrict__ flag) {
+  __shared__ double tab[SWF][3][NAX];
+  __shared__ double ctab[3][NAX];
+  __shared__ double ax[NAX];
+  __shared__ double red[5 * 16];
+  if (*flag) return;
+  // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+  // range of cells so neighbouring cells share an L2
+  const int64_t per = (fm.nc + 7) / 8;
+  const int64_t ic = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (ic >= fm.nc) return;
+  // every pointer below is wave-uniform: its loads are scalar loads
+  const int32_t* __restrict__ ci0 = crec_i + ic * CRI;
+  const double* __restrict__ cd0 = crec_d + ic * CRD;
+  const double* __restrict__ cc0 = cs + ic * CSREC;
+  const int nf = ci0[0], on = ci0[1];
+  build_tables<D>(tab, ctab, ax, fm, g, prim, cs, frec, ic, nf);
+  constexpr int NM = D + 2;
+  constexpr bool B2 = (D == 2);  // the b equation is carried in 2-D only
+  const unsigned nv = (unsigned)fm.nv;
+  const unsigned npairs = (nv + 1) / 2;
+  const T* __restrict__ hi = h + ic * nvp;
+  const T* __restrict__ bi = B2 ? b + ic * nvp : nullptr;
+  // per-lane moments sum_k w_k psi_k (net outflow of the cell at u_k): the
+  // conservative update of the cell is W - sum (Eq. macro_update regrouped
+  // by velocity: sum_j sigma S_j F_j / V = sum_k w_k psi_k sum_j sigma S_j H_jk / V)
+  double mw[NM];
+#pragma unroll
+  for (int x = 0; x < NM; ++x) mw[x] = 0.0;
+
+  for (unsigned kp = threadIdx.x; kp < npairs; kp += SWT) {
+    // The cell and face records are loop invariant but too large to keep in
+    // scalar registers for the whole loop: an opaque uniform zero added to
+    // their addresses makes them scalar re-loads (scalar cache) each
+    // iteration instead of hoisted, spilled registers.
+    int z;
+    __asm__ volatile("s_mov_b32 %0, 0" : "=s"(z));
+    const int32_t* __restrict__ ci = ci0 + z;
+    const double* __restrict__ cd = cd0 + z;
+    const double* __restrict__ cc = cc0 + z;
+    const unsigned k0 = kp, k1 = nv - 1 - kp;
+    const int pk = vidx[k0];
+    int id[3], im[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      id[d] = (pk >> (8 * d)) & 255;
+      im[d] = fm.na - 1 - id[d];
+    }
+    double vv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < D; ++d) vv[d] = ax[id[d]];
+    // orientation of u against every outward normal
+    double sp[SWF];
+#pragma unroll
+    for (int p = 0; p < SWF; ++p) {
+      double s = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) s += vv[d] * cd[CRD_F0 + CRD_FS * p + 0 + d];
+      sp[p] = s;
+    }
+    // ---- the cell's own stencil at u and -u ----
+    const double h0 = ld(hi, k0), h1 = ld(hi, k1);
+    double b0 = 0.0, b1 = 0.0;
+    if (B2) {
+      b0 = ld(bi, k0);
+      b1 = ld(bi, k1);
+    }
+    double os0[SWF], os1[SWF], ob0[SWF], ob1[SWF];
+#pragma unroll
+    for (int s = 0; s < SWF; ++s) {
+      os0[s] = os1[s] = ob0[s] = ob1[s] = 0.0;
+      if (s < on) {
+        const int64_t cell = ci[2 + s];
+        const T* __restrict__ row = h + cell * nvp;
+        os0[s] = ld(row, k0);
+        os1[s] = ld(row, k1);
+        if (B2) {
+          const T* __restrict__ rb = b + cell * nvp;
+          ob0[s] = ld(rb, k0);
+          ob1[s] = ld(rb, k1);
+        }
+      }
+    }
+    double g0[3] = {0, 0, 0}, g1[3] = {0, 0, 0}, gb0[3] = {0, 0, 0}, gb1[3] = {0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < SWF; ++s) {
+      if (s < on) {
+        const double d0 = os0[s] - h0, d1 = os1[s] - h1;
+        const double e0 = ob0[s] - b0, e1 = ob1[s] - b1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const double G = cd[d * 4 + s];
+          g0[d] += G * d0;
+          g1[d] += G * d1;
+          if (B2) {
+            gb0[d] += G * e0;
+            gb1[d] += G * e1;
+          }
+        }
+      }
+    }
+    // ---- every neighbour's value and stencil at the incoming member ----
+    double nh[SWF], nhs[SWF][SWF], nb[SWF], nbs[SWF][SWF];
+#pragma unroll
+    for (int p = 0; p < SWF; ++p) {
+      nh[p] = nb[p] = 0.0;
+#pragma unroll
+      for (int r = 0; r < SWF; ++r) nhs[p][r] = nbs[p][r] = 0.0;
+      const int32_t* fi = ci + CRI_F0 + CRI_FS * p;
+      if (p < nf && fi[1] != UGKS_BC_WALL) {
+        const unsigned kin = sp[p] > 0.0 ? k1 : k0;
+        const int64_t j = fi[3];
+        nh[p] = ld(h + j * nvp, kin);
+        if (B2) nb[p] = ld(b + j * nvp, kin);
+        const int jn = fi[4];
+#pragma unroll
+        for (int r = 0; r < SWF; ++r) {
+          if (r < jn) {
+            const int64_t cell = fi[5 + r];
+            nhs[p][r] = ld(h + cell * nvp, kin);
+            if (B2) nbs[p][r] = ld(b + cell * nvp, kin);
+          }
+        }
+      }
+    }
+    double ug0 = 0.0, ug1 = 0.0, ub0 = 0.0, ub1 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      ug0 += vv[d] * g0[d];
+      ug1 -= vv[d] * g1[d];
+      if (B2) {
+        ub0 += vv[d] * gb0[d];
+        ub1 -= vv[d] * gb1[d];
+      }
+    }
+    double v2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) v2 += vv[d] * vv[d];
+    double acc0 = 0.0, acc1 = 0.0, accb0 = 0.0, accb1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < SWF; ++p) {
+      if (p >= nf) break;
+      const int32_t* fi = ci + CRI_F0 + CRI_FS * p;
+      const double* fd = cd + CRD_F0 + CRD_FS * p;
+      const double* R = frec + (int64_t)fi[0] * FREC;
+      const bool pos = sp[p] > 0.0;
+      const double as = fabs(sp[p]);
+      // outgoing member: the cell's own reconstruction at the face
+      const double us = pos ? ug0 : ug1;
+      double hf = pos ? h0 : h1;
+#pragma unroll
+      for (int d = 0; d < D; ++d) hf += fd[4 + d] * (pos ? g0[d] : g1[d]);
+      double bfo = 0.0, ubs = 0.0;
+      if (B2) {
+        bfo = pos ? b0 : b1;
+        ubs = pos ? ub0 : ub1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) bfo += fd[4 + d] * (pos ? gb0[d] : gb1[d]);
+      }
+      // g0 (or the scaled wall Maxwellian) at u and -u from the axis tables
+      double e0 = tab[p][0][id[0]], e1 = tab[p][0][im[0]];
+#pragma unroll
+      for (int d = 1; d < D; ++d) {
+        e0 *= tab[p][d][id[d]];
+        e1 *= tab[p][d][im[d]];
+      }
+      double out, in, outb = 0.0, inb = 0.0;
+      if (fi[1] == UGKS_BC_WALL) {
+        // incident free transport out of the cell, diffuse re-emission in
+        const double dt = g.dt;
+        out = as * (dt * hf - 0.5 * dt * dt * us);
+        in = -as * (pos ? e1 : e0);
+        if (B2) {
+          outb = as * (dt * bfo - 0.5 * dt * dt * ubs);
+          inb = (3 - D) / (2.0 * R[FR_LAM]) * in;
+        }
+      } else {
+        const double G1 = R[FR_G], G2 = R[FR_G + 1];
+        double E, O;
+        cubic_eo<D>(R + FR_PH, vv, E, O);
+        const double P0 = E + O, P1 = E - O;
+        const double eqo = pos ? e0 * P0 : e1 * P1;
+        const double eqi = pos ? e1 * P1 : e0 * P0;
+        // incoming member: the neighbour's reconstruction at the face
+        const double sgn_in = pos ? -1.0 : 1.0;  // u_in = sgn_in * u
+        const double hj = nh[p], bj = nb[p];
+        double gj[3] = {0, 0, 0}, gbj[3] = {0, 0, 0};
+        const int jn = fi[4];
+#pragma unroll
+        for (int r = 0; r < SWF; ++r) {
+          if (r < jn) {
+            const double dh = nhs[p][r] - hj, db = nbs[p][r] - bj;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              const double G = fd[10 + d * 4 + r];
+              gj[d] += G * dh;
+              if (B2) gbj[d] += G * db;
+            }
+          }
+        }
+        double hfj = hj, ugj = 0.0, bfj = bj, ubj = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          hfj += fd[7 + d] * gj[d];
+          ugj += vv[d] * gj[d];
+          if (B2) {
+            bfj += fd[7 + d] * gbj[d];
+            ubj += vv[d] * gbj[d];
+          }
+        }
+        ugj *= sgn_in;
+        ubj *= sgn_in;
+        out = as * (G1 * hf + G2 * us + eqo);
+        in = -as * (G1 * hfj + G2 * ugj + eqi);
+        if (B2) {
+          double Eb, Ob;
+          cubic_eo<D>(R + FR_PB, vv, Eb, Ob);
+          const double Q0 = Eb + Ob, Q1 = Eb - Ob;
+          outb = as * (G1 * bfo + G2 * ubs + (pos ? e0 * Q0 : e1 * Q1));
+          inb = -as * (G1 * bfj + G2 * ubj + (pos ? e1 * Q1 : e0 * Q0));
+        }
+      }
+      // fluxes at u and at -u along this cell's outward normal, times S/V
+      const double sv = fd[3];
+      acc0 += sv * (pos ? out : in);
+      acc1 += sv * (pos ? in : out);
+      if (B2) {
+        accb0 += sv * (pos ? outb : inb);
+        accb1 += sv * (pos ? inb : outb);
+      }
+    }
+    // moments of the net outflow (the zero velocity of an odd grid once)
+    {
+      const double a0 = w[k0] * acc0, a1 = (k1 != k0) ? w[k1] * acc1 : 0.0;
+      mw[0] += a0 + a1;
+#pragma unroll
+      for (int d = 0; d < D; ++d) mw[1 + d] += vv[d] * (a0 - a1);
+      double e = 0.5 * v2 * (a0 + a1);
+      if (B2) e += 0.5 * (w[k0] * accb0 + ((k1 != k0) ? w[k1] * accb1 : 0.0));
+      mw[D + 1] += e;
+    }
+    // first stage with the cell's BGK-Shakhov equilibrium at u and -u
+    double c0 = ctab[0][id[0]], c1 = ctab[0][im[0]];
+#pragma unroll
+    for (int d = 1; d < D; ++d) {
+      c0 *= ctab[d][id[d]];
+      c1 *= ctab[d][im[d]];
+    }
+    double E, O;
+    cubic_eo<D>(cc + CS_SH, vv, E, O);
+    const double ccoll = cc[CS_CC];
+    T* __restrict__ hto = ht + ic * nvp;
+    st(hto, k0, h0 - acc0 + ccoll * (c0 * (1.0 + E + O) - h0));
+    if (k1 != k0) st(hto, k1, h1 - acc1 + ccoll * (c1 * (1.0 + E - O) - h1));
+    if (B2) {
+      double Eb, Ob;
+      cubic_eo<D>(cc + CS_SB, vv, Eb, Ob);
+      const double kc = cc[CS_KAP];
+      T* __restrict__ bto = bt + ic * nvp;
+      st(bto, k0, b0 - accb0 + ccoll * (kc * c0 * (1.0 + Eb + Ob) - b0));
+      if (k1 != k0) st(bto, k1, b1 - accb1 + ccoll * (kc * c1 * (1.0 + Eb - Ob) - b1));
+    }
+  }
+  block_sum<NM>(mw, red);
+  if (threadIdx.x == 0)
+    for (int x = 0; x < 5; ++x) dW[ic * 5 + x] = x < NM ? mw[x] : 0.0;
+}
+
+// Conservative update of the fused path: W^{n+1} = W^n - dW.
+template <int D>
+__global__ void k_apply_dW(int64_t nc, const double* __restrict__ vol, const double* __restrict__ W,
+                           const double* __restrict__ dW, double* __restrict__ Wn,
+                           double* __restrict__ cellred, const int32_t* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nc || *flag) return;
+  for (int x = 0; x < D + 2; ++x) Wn[i * (D + 2) + x] = W[i * (D + 2) + x] - dW[i * 5 + x];
+  const double V = vol[i];
+  const double dr = Wn[i * (D + 2)] - W[i * (D + 2)];
+  cellred[i * 3 + 0] = V * dr * dr;
+  cellred[i * 3 + 1] = V;
+  cellred[i * 3 + 2] = V * W[i * (D + 2)] * W[i * (D + 2)];
+}
+
+// Second stage (Eq. f_final) fused with the heat flux of the result.
+// csn holds dt/(2 tau^{n+1}) and the Shakhov polynomials of W^{n+1} with q^n.
+template <int D, typename T>
+__global__ __launch_bounds__(SWT) void k_stage2_q(FusedMesh fm, int64_t nvp,
+                                                  const double* __restrict__ w,
+                                                  const double* __restrict__ primn,
+                                                  const double* __restrict__ csn,
+                                                  const T* __restrict__ ht, const T* __restrict__ bt,
+                                                  T* __restrict__ h, T* __restrict__ b,
+                                                  double* __restrict__ qn, const int32_t* flag) {
+  __shared__ double ctab[3][NAX];
+  __shared__ double ax[NAX];
+  __shared__ double red[3 * 16];
+  if (*flag) return;
+  const int64_t per = (fm.nc + 7) / 8;
+  const int64_t ic = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (ic >= fm.nc) return;
+  const int na = fm.na;
+  const double* __restrict__ P = primn + ic * NPRIM;
+  const double* __restrict__ cc = csn + ic * CSREC;
+  for (int t = threadIdx.x; t < D * na; t += SWT) {
+    const int d = t / na, n = t % na;
+    const double a = fm.axis[n], U = P[1 + d], lam = P[4];
+    ctab[d][n] = (d == 0 ? cc[CS_NORM] : 1.0) * exp(-lam * (a - U) * (a - U));
+  }
+  for (int t = threadIdx.x; t < na; t += SWT) ax[t] = fm.axis[t];
+  __syncthreads();
+  const double A = cc[CS_CC];
+  const double inv = 1.0 / (1.0 + A);
+  const double kc = cc[CS_KAP];
+  const double U0 = P[1], U1 = P[2], U2 = P[3];
+  const T* __restrict__ hti = ht + ic * nvp;
+  T* __restrict__ hi = h + ic * nvp;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const unsigned nv = (unsigned)fm.nv;
+  for (unsigned k = threadIdx.x; k < nv; k += SWT) {
+    __asm__ volatile("" ::: "memory");
+    const int pk = fm.vidx[k];
+    double vv[3] = {0, 0, 0};
+    double c0 = 1.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int i = (pk >> (8 * d)) & 255;
+      vv[d] = ax[i];
+      c0 *= ctab[d][i];
+    }
+    double E, O;
+    cubic_eo<D>(cc + CS_SH, vv, E, O);
+    const double hn = (ld(hti, k) + A * c0 * (1.0 + E + O)) * inv;
+    st(hi, k, hn);
+    double bn = 0.0;
+    if (D == 2) {
+      double Eb, Ob;
+      cubic_eo<D>(cc + CS_SB, vv, Eb, Ob);
+      bn = (ld(bt + ic * nvp, k) + A * kc * c0 * (1.0 + Eb + Ob)) * inv;
+      st(b + ic * nvp, k, bn);
+    }
+    // heat flux of h^{n+1} about U^{n+1} (Eq. reduced_heat_flux)
+    const double c[3] = {vv[0] - U0, vv[1] - U1, D == 3 ? vv[2] - U2 : 0.0};
+    double c2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) c2 += c[d] * c[d];
+    const double s = w[k] * (c2 * hn + bn);
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d] += s * c[d];
+  }
+  block_sum<3>(acc, red);
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 3; ++d) qn[ic * 3 + d] = d < D ? 0.5 * acc[d] : 0.0;
+}
+
+// Wall density with the wall cell's gradient evaluated in place.
+template <int D, typename T>
+__global__ __launch_bounds__(SWT) void k_wall_rho_inline(DevMesh m, DevVel v, GasP g,
+                                                         const T* __restrict__ h,
+                                                         double* __restrict__ frec,
+                                                         const int32_t* flag) {
+  __shared__ double red[2 * 16];
+  if (*flag) return;
+  const int f = m.walls[blockIdx.x];
+  const int64_t L = m.fL[f];
+  const int64_t nvp = v.nvp;
+  double* R = &frec[(int64_t)f * FREC];
+  const double lamw = R[FR_LAM], Cw = R[FR_C0], dt = g.dt;
+  const int nfc = m.nfc[L];
+  double acc[2] = {0.0, 0.0};
+  for (int64_t k = threadIdx.x; k < v.nv; k += SWT) {
+    double un = 0.0;
+    for (int d = 0; d < D; ++d) un += v.u[d * nvp + k] * m.fnorm[f * 3 + d];
+    if (un > 0.0) {
+      const double hl = ld(h, L * nvp + k);
+      double gr[3] = {0, 0, 0};
+      for (int p = 0; p < nfc; ++p) {
+        const int j = m.cnbr[L * MAXF + p];
+        if (j < 0) continue;
+        const double dh = ld(h, (int64_t)j * nvp + k) - hl;
+        for (int d = 0; d < D; ++d) gr[d] += m.lsG[(L * 3 + d) * MAXF + p] * dh;
+      }
+      double hf = hl, ugh = 0.0;
+      for (int d = 0; d < D; ++d) {
+        hf += m.fdxL[f * 3 + d] * gr[d];
+        ugh += v.u[d * nvp + k] * gr[d];
+      }
+      acc[0] += v.w[k] * un * (dt * hf - 0.5 * dt * dt * ugh);
+    } else if (un < 0.0) {
+      double c2 = 0.0;
+      for (int d = 0; d < D; ++d) {
+        double c = v.u[d * nvp + k] - R[FR_U + d];
+        c2 += c * c;
+      }
+      acc[1] += v.w[k] * un * Cw * exp(-lamw * c2);
+    }
+  }
+  block_sum<2>(acc, red);
+  if (threadIdx.x == 0) R[FR_RHOW] = -acc[0] / (dt * acc[1]);
+}
+
+}  // namespace
+
+#define UGKS_DISPATCH_D(D_, ...) \
+  do {                           \
+    if ((D_) == 2) {             \
+      constexpr int DD = 2;      \
+      __VA_ARGS__;               \
+    } else {                     \
+      constexpr int DD = 3;      \
+      __VA_ARGS__;               \
+    }                            \
+  } while (0)
+
+#define UGKS_DISPATCH_DT(D_, P_, ...)   \
+  do {                                  \
+    if ((P_) == UGKS_FP32) {            \
+      using TT = float;                 \
+      UGKS_DISPATCH_D(D_, __VA_ARGS__); \
+    } else {                            \
+      using TT = double;                \
+      UGKS_DISPATCH_D(D_, __VA_ARGS__); \
+    }                                   \
+  } while (0)
+
+hipError_t launch_apply_dW(int D, const DevMesh& m, const double* W, const double* dW, double* Wn,
+                          double* cellred, const int32_t* flag, hipStream_t s) {
+  const unsigned grid = (unsigned)((m.nc + 255) / 256);
+  UGKS_DISPATCH_D(D, k_apply_dW<DD><<<grid, 256, 0, s>>>(m.nc, m.vol, W, dW, Wn, cellred, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_prep(int D, int64_t nc, const GasP& g, const double* W, const double* q,
+                            double* prim, double* cs, int32_t* flag, hipStream_t s) {
+  const unsigned grid = (unsigned)((nc + 127) / 128);
+  UGKS_DISPATCH_D(D, k_cell_prep<DD><<<grid, 128, 0, s>>>(nc, g, W, q, prim, cs, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, const GasP& g,
+                        const double* prim, const double* cs, const double* frec, const void* h,
+                        const void* b, void* ht, void* bt, double* dW, const int32_t* flag,
+                        hipStream_t s) {
+  const unsigned grid = (unsigned)(((fm.nc + 7) / 8) * 8);
+  UGKS_DISPATCH_DT(D, prec, k_sweep<DD, TT><<<grid, SWT, 0, s>>>(
+      fm, g, v.nvp, fm.crec_i, fm.crec_d, fm.vidx, v.w, prim, cs, frec, (const TT*)h, (const TT*)b,
+      (TT*)ht, (TT*)bt, dW, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v,
+                           const double* primn, const double* csn, const void* ht, const void* bt,
+                           void* h, void* b, double* qn, const int32_t* flag, hipStream_t s) {
+  const unsigned grid = (unsigned)(((fm.nc + 7) / 8) * 8);
+  UGKS_DISPATCH_DT(D, prec, k_stage2_q<DD, TT><<<grid, SWT, 0, s>>>(
+      fm, v.nvp, v.w, primn, csn, (const TT*)ht, (const TT*)bt, (TT*)h, (TT*)b, qn, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
+                                  const GasP& g, const void* h, double* frec, const int32_t* flag,
+                                  hipStream_t s) {
+  if (m.nwall == 0) return hipSuccess;
+  UGKS_DISPATCH_DT(D, prec, k_wall_rho_inline<DD, TT><<<(unsigned)m.nwall, SWT, 0, s>>>(
+      m, v, g, (const TT*)h, frec, flag));
+  return hipGetLastError();
+}
+
+}  // namespace ugks

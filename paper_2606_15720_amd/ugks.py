@@ -57,7 +57,7 @@ class ugks_info_t(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_r", C.c_int32), ("precision", C.c_int32),
                 ("block_v", C.c_int32), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
                 ("nv", C.c_int64), ("nv_padded", C.c_int64), ("dt", C.c_double),
-                ("steps_done", C.c_int64), ("device_bytes", C.c_int64)]
+                ("steps_done", C.c_int64), ("device_bytes", C.c_int64), ("fused", C.c_int32)]
 
 
 _lib = None

@@ -41,9 +41,12 @@ def _normwise_F(a, b):
     return np.abs(a - b).max(axis=0) / max(np.abs(b).max(), 1e-300)
 
 
-def _compare_step(case, steps, check_h_every=None, tol=TOL):
+STAGED = 2  # ugks_options.flags bit: force the staged (unfused) sweep
+
+
+def _compare_step(case, steps, flags=0, tol=TOL):
     o = Oracle(case)
-    s = Solver(case)
+    s = Solver(case, flags=flags)
     assert s.dt == pytest.approx(o.dt, rel=1e-14)
     done = 0
     while done < steps:
@@ -64,8 +67,10 @@ def _compare_step(case, steps, check_h_every=None, tol=TOL):
         if done == 1:
             Fo, rwo, _, _ = o.faces()
             Fg, rwg = s.faces()
-            ferr = _normwise_F(Fg, Fo)
-            assert np.all(ferr <= 1e-13), ferr
+            if flags & STAGED:
+                # the staged sweep keeps per-face macroscopic fluxes
+                ferr = _normwise_F(Fg, Fo)
+                assert np.all(ferr <= 1e-13), ferr
             wall = case.mesh.face_bc == 1
             np.testing.assert_allclose(rwg[wall], rwo[wall], rtol=1e-13, atol=1e-15)
             qg = s.moments(2)
@@ -74,28 +79,46 @@ def _compare_step(case, steps, check_h_every=None, tol=TOL):
     s.close()
 
 
-def test_cavity2d_config1_parity_100_steps():
+PATHS = [pytest.param(0, id="fused"), pytest.param(STAGED, id="staged")]
+
+
+@pytest.mark.parametrize("flags", PATHS)
+def test_cavity2d_config1_parity_100_steps(flags):
     # the full 2-D lid-driven cavity: 32x32 quads, 28^2 velocities, 100 steps
-    _compare_step(uc.cavity2d(), 100)
+    _compare_step(uc.cavity2d(), 100, flags)
 
 
-def test_sod3d_small_parity():
-    _compare_step(uc.sod3d_tets(n=4, nv=8, jitter=0.15, seed=3), 10)
+@pytest.mark.parametrize("flags", PATHS)
+def test_sod3d_small_parity(flags):
+    _compare_step(uc.sod3d_tets(n=4, nv=8, jitter=0.15, seed=3), 10, flags)
 
 
-def test_couette_periodic_parity():
-    _compare_step(uc.couette2d(n=12, nv=16, kn=0.05), 20)
+@pytest.mark.parametrize("flags", PATHS)
+def test_couette_periodic_parity(flags):
+    _compare_step(uc.couette2d(n=12, nv=16, kn=0.05), 20, flags)
 
 
-def test_ragged_velocity_tail_and_tiny_mesh():
-    # 7^2 = 49 velocities: one partly padded block; 3x3 cells
-    _compare_step(uc.cavity2d(n=3, nv=7, kn=1.0), 5)
+@pytest.mark.parametrize("flags", PATHS)
+def test_ragged_velocity_tail_and_tiny_mesh(flags):
+    # 7^2 = 49 velocities: an odd count (the zero velocity is its own mirror)
+    # and a partly padded block; 3x3 cells
+    _compare_step(uc.cavity2d(n=3, nv=7, kn=1.0), 5, flags)
 
 
+@pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("kn", [1e-3, 10.0])
-def test_kn_extremes_parity(kn):
+def test_kn_extremes_parity(kn, flags):
     # continuum-like (dt/tau >> 1) and free-molecular-like (dt/tau << 1)
-    _compare_step(uc.cavity2d(n=8, nv=12, kn=kn), 10)
+    _compare_step(uc.cavity2d(n=8, nv=12, kn=kn), 10, flags)
+
+
+def test_fused_path_is_selected_for_tensor_grids():
+    s = Solver(uc.cavity2d(n=4, nv=6))
+    assert s.info["fused"] == 1
+    s.close()
+    s = Solver(uc.cavity2d(n=4, nv=6), flags=STAGED)
+    assert s.info["fused"] == 0
+    s.close()
 
 
 def test_block_size_and_padding_invariance():

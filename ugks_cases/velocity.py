@@ -45,7 +45,8 @@ def midpoint_grid(n: int, a: float, dim: int) -> Velocity:
     Eq. omega_k).
     """
     du = 2.0 * a / n
-    nodes = -a + (np.arange(n) + 0.5) * du
+    # (i + 1/2 - n/2) is exact, so node n-1-i is exactly minus node i
+    nodes = (np.arange(n) + 0.5 - 0.5 * n) * du
     return _tensor(dim, nodes, np.full(n, du), f"mid{n}^{dim}[{a}]")
 
 
@@ -58,5 +59,8 @@ def gauss_hermite_grid(n_gh: int, u_max: float, dim: int) -> Velocity:
     plain integral of Q.
     """
     xi, wgh = np.polynomial.hermite.hermgauss(n_gh)
+    # make the node set exactly symmetric about zero
+    xi = 0.5 * (xi - xi[::-1])
+    wgh = 0.5 * (wgh + wgh[::-1])
     s = u_max / np.max(np.abs(xi))
     return _tensor(dim, s * xi, s * wgh * np.exp(xi ** 2), f"gh{n_gh}^{dim}[{u_max}]")
