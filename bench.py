@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the UGKS phase-space step on one MI355X.
+
+Workload: the 3-D Sod-type jump in the unit cube meshed by 20^3 hexes split
+into 48,000 jittered Kuhn tetrahedra (seed 0), 24^3 = 13,824 midpoint
+velocities on [-4, 4]^3, Kn = 0.01, diffuse walls; synthetic inputs from
+``ugks_cases.sod3d_tets``.  A step is one pass of the whole step (heat flux,
+macroscopic reconstruction, interface equilibrium, wall densities, the fused
+velocity sweep, conservative update, second stage, residual).  The metric is
+cell-velocity updates per second, N_c * N_v * steps / wall time, with every
+input resident in HBM before the timed region.
+
+The printed JSON line also carries
+  * ``roofline``: the dominant kernel (the sweep) against the HBM roofline,
+    from HIP events recorded by the library on its own stream over the timed
+    steps; algorithmic bytes per launch = 2 N_r P N_c N_v (read h^n, write
+    the first-stage result), and the HBM traffic measured by rocprofv3
+    counters when the committed summary matches the current kernel source;
+  * ``fp32``: the same step in the FP32 storage form;
+  * ``cpu_baseline``: the FP64 CPU oracle timed on a bounded sample (one step
+    of the same workload family on a smaller mesh).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "cell-velocity updates/s on 1 GPU, % HBM peak; time to 1e-6 residual"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_sod3d_48k_24cube_traffic.json")
+SWEEP_SRC = os.path.join(ROOT, "paper_2606_15720_amd", "csrc", "ugks_sweep.hip")
+
+
+def _source_hash() -> str:
+    with open(SWEEP_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(precision: int):
+    """HBM bytes per sweep launch from the committed counter summary, or None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sweep_source_sha256_16") != _source_hash():
+        return None  # the kernel changed since the counters were taken
+    rec = t.get(f"fp{precision}")
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def run_gpu(case, precision: int, steps: int, warmup: int):
+    import torch
+    from paper_2606_15720_amd.ugks import Solver, ugks_profile_enable, ugks_profile_read
+
+    stream = torch.cuda.current_stream()
+    s = Solver(case, precision=precision, stream=stream.cuda_stream)
+    info = s.info
+    if warmup:
+        s.step(warmup)
+    ugks_profile_enable(s.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = s.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ugks_profile_read(s.h)
+    ugks_profile_enable(s.h, False)
+    W = s.W()
+    s.close()
+    ups = case.updates_per_step * steps / wall
+    n_r = info["n_r"]
+    pbytes = 8 if precision == 64 else 4
+    launches, tot_ms = prof.get("sweep", (0, 0.0))
+    avg_s = tot_ms / max(launches, 1) / 1e3
+    alg_bytes = 2.0 * n_r * pbytes * case.mesh.n_cells * case.vel.nv
+    achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
+    return dict(value=ups, ms_per_step=wall / steps * 1e3, info=info, prof=prof, residual=res,
+                sweep_ms=avg_s * 1e3, alg_bytes=alg_bytes, achieved=achieved,
+                mass=float(W[:, 0] @ case.mesh.cell_volume))
+
+
+def run_cpu_baseline(n: int):
+    """One oracle step of the same workload family on an n^3-hex mesh."""
+    import ugks_cases as uc
+    from oracle import Oracle, threads
+
+    case = uc.sod3d_tets(n=n)
+    o = Oracle(case)
+    t0 = time.perf_counter()
+    o.step(1)
+    t = time.perf_counter() - t0
+    return dict(value=case.updates_per_step / t, unit="cell-velocity updates/s",
+                cores=threads(), kind="oracle",
+                sample=f"one FP64 oracle step of the 3-D Sod tet cube at {n}^3 hexes "
+                       f"({case.mesh.n_cells} tets) x 24^3 velocities, {t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=14)
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="instead of the step, copy this many GiB device-to-device with a plain "
+                         "copy kernel (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_probe > 0:
+        import torch
+        n = int(args.copy_probe * 2**30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_launch": n * 8, "launches": 3}), flush=True)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the step holds one physical subdomain with all of its "
+              "velocity blocks on a single MI355X; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import ugks_cases as uc
+
+    case = uc.sod3d_tets()
+    r64 = run_gpu(case, 64, args.steps, args.warmup)
+    out = {
+        "metric": METRIC,
+        "value": r64["value"],
+        "unit": "cell-velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sod3d_tets_48000x24^3", "n_cells": case.mesh.n_cells,
+                   "n_faces": case.mesh.n_faces, "nv": case.vel.nv, "kn": 0.01,
+                   "fused_sweep": bool(r64["info"]["fused"]), "parallelism": "none"},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "sweep",
+            "achieved": r64["achieved"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": r64["achieved"] / HBM_PEAK_GBS,
+            "traffic": _traffic(64),
+            "avg_ms": r64["sweep_ms"],
+            "algorithmic_bytes_per_launch": r64["alg_bytes"],
+        },
+        "kernels_ms_per_step": {k: v[1] / max(args.steps, 1) for k, v in r64["prof"].items()},
+    }
+    if not args.no_fp32:
+        r32 = run_gpu(case, 32, args.steps, args.warmup)
+        out["fp32"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
+                       "roofline_frac": r32["achieved"] / HBM_PEAK_GBS,
+                       "achieved_GBs": r32["achieved"], "sweep_ms": r32["sweep_ms"],
+                       "traffic": _traffic(32)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

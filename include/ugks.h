@@ -133,6 +133,9 @@ typedef struct {
  *   block_v    velocity-block size B_v (64, 128, 256); 0 = library choice.
  *   flags      bit 0: skip the density residual (saves one small reduction).
  *              bit 1: use the staged sweep even where the fused one applies.
+ *              bit 2: keep the caller's cell order internally (by default
+ *                     cells are renumbered along a Z-order curve of their
+ *                     centroids; inputs and outputs always use the caller's order).
  *   The fused sweep (one pass for reconstruction, interface flux, moment
  *   sums and the first stage) applies when the velocity set is a tensor
  *   product of one 1-D node set symmetric about zero, listed with the first
@@ -222,6 +225,24 @@ int ugks_set_state(ugks_ctx* ctx, const double* W, const double* h, const double
 int ugks_face_data(ugks_ctx* ctx, double* F, double* rho_w);
 
 int ugks_info(const ugks_ctx* ctx, ugks_info_t* out);
+
+/*
+ * Kernel timing with HIP events recorded on the context's stream around
+ * every kernel a step enqueues (measurement support, not part of the method).
+ *   ugks_profile_enable(ctx, 1) starts recording, 0 stops; either call
+ *     discards what was recorded.
+ *   ugks_profile_read fills out[0..max-1] with one row per kernel kind
+ *     (launch count, summed duration) and sets *n_out to the number of kinds;
+ *     it synchronises the stream.  Recording costs two event records per launch.
+ */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} ugks_kernel_time;
+
+int ugks_profile_enable(ugks_ctx* ctx, int32_t on);
+int ugks_profile_read(ugks_ctx* ctx, ugks_kernel_time* out, int32_t max, int32_t* n_out);
 
 /* Releases every device buffer; accepts NULL. */
 void ugks_destroy(ugks_ctx* ctx);

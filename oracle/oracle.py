@@ -68,6 +68,8 @@ def _load():
     lib.oracle_last_error.argtypes = [P]
     lib.oracle_steps_done.restype = i64
     lib.oracle_steps_done.argtypes = [P]
+    lib.oracle_threads.restype = i32
+    lib.oracle_threads.argtypes = []
     _lib = lib
     return lib
 
@@ -159,6 +161,11 @@ class Oracle:
     @property
     def steps_done(self) -> int:
         return int(self.lib.oracle_steps_done(self.h_))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_load().oracle_threads())
 
 
 def gamma(dt: float, tau: float) -> np.ndarray:

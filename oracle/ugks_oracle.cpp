@@ -981,3 +981,12 @@ int oracle_ctx::step_once() {
 
 extern "C" const char* oracle_last_error(const oracle_ctx* o) { return o->err.c_str(); }
 extern "C" int64_t oracle_steps_done(const oracle_ctx* o) { return o->steps_done; }
+
+// Threads the oracle's parallel loops use.
+extern "C" int oracle_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

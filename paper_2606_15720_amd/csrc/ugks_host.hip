@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <memory>
 
 using namespace ugks;
@@ -126,9 +127,38 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   std::vector<int32_t> fL(nf), fR(nf), fbc(nf), fbcid(nf), walls;
   std::vector<double> farea(nf), fnorm(nf * 3, 0.0), fdxL(nf * 3, 0.0), fdxR(nf * 3, 0.0),
       fmir(nf * 3, 0.0);
-  std::vector<double> cen(nc * 3, 0.0);
-  for (int64_t i = 0; i < nc; ++i)
-    for (int d = 0; d < D; ++d) cen[i * 3 + d] = mesh->cell_centroid[i * D + d];
+  // ---- cell renumbering: Z-order (Morton) of the centroids, so that cells
+  // with nearby indices are spatial neighbours (they run together and share
+  // stencil rows in cache); the caller never sees this order
+  std::vector<int64_t> perm(nc), inv(nc);
+  {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < nc; ++i)
+      for (int d = 0; d < D; ++d) {
+        lo[d] = std::min(lo[d], mesh->cell_centroid[i * D + d]);
+        hi[d] = std::max(hi[d], mesh->cell_centroid[i * D + d]);
+      }
+    std::vector<std::pair<uint64_t, int64_t>> key(nc);
+    for (int64_t i = 0; i < nc; ++i) {
+      uint64_t code = 0;
+      for (int d = 0; d < D; ++d) {
+        const double span = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0;
+        uint64_t qd = (uint64_t)std::min(1048575.0, std::floor((mesh->cell_centroid[i * D + d] - lo[d]) / span * 1048576.0));
+        for (int bit = 0; bit < 20; ++bit) code |= ((qd >> bit) & 1ull) << (bit * D + d);
+      }
+      key[i] = {(c->flags & 4) ? (uint64_t)i : code, i};
+    }
+    std::stable_sort(key.begin(), key.end());
+    for (int64_t i = 0; i < nc; ++i) {
+      perm[i] = key[i].second;
+      inv[key[i].second] = i;
+    }
+  }
+  std::vector<double> cen(nc * 3, 0.0), vol(nc);
+  for (int64_t i = 0; i < nc; ++i) {
+    vol[i] = mesh->cell_volume[perm[i]];
+    for (int d = 0; d < D; ++d) cen[i * 3 + d] = mesh->cell_centroid[perm[i] * D + d];
+  }
   std::vector<double> closure(nc * 3, 0.0), asum(nc, 0.0);
   for (int64_t f = 0; f < nf; ++f) {
     int64_t L = mesh->face_cells[2 * f], R = mesh->face_cells[2 * f + 1];
@@ -137,6 +167,8 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     fail_if(kind < 0 || kind > 3, "unknown face_bc");
     fail_if(kind == UGKS_BC_INTERIOR && (R < 0 || R >= nc || R == L), "interior face needs a distinct R");
     fail_if(kind != UGKS_BC_INTERIOR && R != -1, "boundary face must have R = -1");
+    L = inv[L];
+    if (R >= 0) R = inv[R];
     fail_if(!(mesh->face_area[f] > 0.0), "non-positive face area");
     double nn = 0.0;
     for (int d = 0; d < D; ++d) nn += mesh->face_normal[f * D + d] * mesh->face_normal[f * D + d];
@@ -282,7 +314,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   DevMesh& m = c->mesh;
   m.nc = nc;
   m.nf = nf;
-  m.vol = upload(c, std::vector<double>(mesh->cell_volume, mesh->cell_volume + nc));
+  m.vol = upload(c, vol);
   m.cen = upload(c, cen);
   m.nfc = upload(c, nfc);
   m.cface = upload(c, cface);
@@ -352,7 +384,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
           fd[4 + d] = sg > 0.0 ? fdxL[f * 3 + d] : fdxR[f * 3 + d];
           fd[7 + d] = sg > 0.0 ? fdxR[f * 3 + d] : fdxL[f * 3 + d];
         }
-        fd[3] = farea[f] / mesh->cell_volume[i];
+        fd[3] = farea[f] / vol[i];
       }
     }
     std::vector<int32_t> vidx(nv);
@@ -373,8 +405,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     c->fmesh.crec_i = upload(c, ci);
     c->fmesh.crec_d = upload(c, cdr);
   }
-  c->cell_perm.resize(nc);
-  for (int64_t i = 0; i < nc; ++i) c->cell_perm[i] = i;
+  c->cell_perm = perm;
   c->face_perm.resize(nf);
   for (int64_t f = 0; f < nf; ++f) c->face_perm[f] = f;
 
@@ -413,7 +444,10 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   HIP_TRY(hipMemsetAsync(B.resid, 0, 8 * sizeof(double), c->stream));
   HIP_TRY(hipMemsetAsync(B.flag, 0, 4 * sizeof(int32_t), c->stream));
   HIP_TRY(hipMemsetAsync(B.q, 0, nc * 3 * sizeof(double), c->stream));
-  HIP_TRY(hipMemcpyAsync(B.W, W0, nc * NW * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  std::vector<double> W0p(nc * NW);
+  for (int64_t i = 0; i < nc; ++i)
+    for (int x = 0; x < NW; ++x) W0p[i * NW + x] = W0[perm[i] * NW + x];
+  HIP_TRY(hipMemcpy(B.W, W0p.data(), nc * NW * sizeof(double), hipMemcpyHostToDevice));
 
   // ---- time step ----------------------------------------------------------
   c->gas.Pr = gas->Pr;
@@ -447,6 +481,53 @@ int set_err(ugks_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
+// Kernel kinds timed by ugks_profile_enable.
+enum KernelKind {
+  KK_PRIMS, KK_HEATFLUX, KK_GRADW, KK_FACE_EQ, KK_WALL, KK_SWEEP, KK_STAGE1, KK_GRAD_MICRO,
+  KK_FLUX, KK_MACRO, KK_STAGE2, KK_RESID, KK_COMMIT, KK_COUNT
+};
+const char* const kKernelNames[KK_COUNT] = {
+    "cell_prims", "heat_flux", "macro_gradient", "face_equilibrium", "wall_density",
+    "sweep", "stage1", "micro_gradient", "face_flux", "macro_update", "stage2", "residual",
+    "commit"};
+
+hipEvent_t take_event(ugks_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_TRY(hipEventCreate(&e));
+  return e;
+}
+
+// Records an event pair around one launch when profiling is on.
+struct Timed {
+  ugks_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr;
+  Timed(ugks_ctx* c_, int k) : c(c_), kind(k) {
+    if (c->profiling) {
+      a = take_event(c);
+      HIP_TRY(hipEventRecord(a, c->stream));
+    }
+  }
+  ~Timed() noexcept(false) {
+    // no second record while a failed launch is unwinding
+    if (c->profiling && a && std::uncaught_exceptions() == 0) {
+      hipEvent_t b = take_event(c);
+      HIP_TRY(hipEventRecord(b, c->stream));
+      c->prof_events.push_back({kind, {a, b}});
+    }
+  }
+};
+#define TIMED(kind, call)        \
+  do {                           \
+    Timed _t(c, kind);           \
+    HIP_TRY(call);               \
+  } while (0)
+
 // One time step of the fused path, enqueued.
 void enqueue_step_fused(ugks_ctx* c) {
   const int D = c->D, P = c->prec;
@@ -457,28 +538,29 @@ void enqueue_step_fused(ugks_ctx* c) {
   hipStream_t s = c->stream;
   // 2 heat flux of h^n: carried over from the previous second stage once valid
   if (!c->q_valid) {
-    HIP_TRY(launch_prims(D, m, g, B.W, B.prim, B.flag, 1, s));
-    HIP_TRY(launch_heatflux(D, P, m, v, B.h, B.b, B.prim, B.q, B.flag, s));
+    TIMED(KK_PRIMS, launch_prims(D, m, g, B.W, B.prim, B.flag, 1, s));
+    TIMED(KK_HEATFLUX, launch_heatflux(D, P, m, v, B.h, B.b, B.prim, B.q, B.flag, s));
     c->q_valid = true;
   }
   // 1 primitives of W^n and the cell equilibrium data of the first stage
-  HIP_TRY(launch_cell_prep(D, c->nc, g, B.W, B.q, B.prim, B.cs, B.flag, s));
+  TIMED(KK_PRIMS, launch_cell_prep(D, c->nc, g, B.W, B.q, B.prim, B.cs, B.flag, s));
   // 4 macroscopic reconstruction; 6.1-6.6 interface equilibrium
-  HIP_TRY(launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
-  HIP_TRY(launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
+  TIMED(KK_GRADW, launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
+  TIMED(KK_FACE_EQ, launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
   // 7 wall densities
-  HIP_TRY(launch_wall_rho_inline(D, P, m, v, g, B.h, B.frec, B.flag, s));
+  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, g, B.h, B.frec, B.flag, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep
-  HIP_TRY(launch_sweep(D, P, c->fmesh, v, g, B.prim, B.cs, B.frec, B.h, B.b, B.ht, B.bt, B.dW,
-                       B.flag, s));
+  TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, B.prim, B.cs, B.frec, B.h, B.b, B.ht, B.bt,
+                                 B.dW, B.flag, s));
   // 8 conservative update; 10 new equilibrium (with q^n, reading R17)
-  HIP_TRY(launch_apply_dW(D, m, B.W, B.dW, B.Wn, B.cellred, B.flag, s));
-  HIP_TRY(launch_cell_prep(D, c->nc, g, B.Wn, B.q, B.primn, B.csn, B.flag, s));
+  TIMED(KK_MACRO, launch_apply_dW(D, m, B.W, B.dW, B.Wn, B.cellred, B.flag, s));
+  TIMED(KK_PRIMS, launch_cell_prep(D, c->nc, g, B.Wn, B.q, B.primn, B.csn, B.flag, s));
   // 11 second stage and the heat flux of h^{n+1}
-  HIP_TRY(launch_stage2_q(D, P, c->fmesh, v, B.primn, B.csn, B.ht, B.bt, B.h, B.b, B.qn, B.flag, s));
+  TIMED(KK_STAGE2, launch_stage2_q(D, P, c->fmesh, v, B.primn, B.csn, B.ht, B.bt, B.h, B.b, B.qn,
+                                    B.flag, s));
   std::swap(B.q, B.qn);
-  if (!(c->flags & 1)) HIP_TRY(launch_residual(m, B.cellred, B.resid, B.flag, s));
-  HIP_TRY(launch_commit_W(D, m, B.Wn, B.W, B.flag, s));
+  if (!(c->flags & 1)) TIMED(KK_RESID, launch_residual(m, B.cellred, B.resid, B.flag, s));
+  TIMED(KK_COMMIT, launch_commit_W(D, m, B.Wn, B.W, B.flag, s));
 }
 
 // One time step, enqueued (the one-step algorithm).
@@ -494,30 +576,30 @@ void enqueue_step(ugks_ctx* c) {
   StepBuffers& B = c->buf;
   hipStream_t s = c->stream;
   // 1-2 primitives and heat flux of the current state
-  HIP_TRY(launch_prims(D, m, g, B.W, B.prim, B.flag, 1, s));
-  HIP_TRY(launch_heatflux(D, P, m, v, B.h, B.b, B.prim, B.q, B.flag, s));
+  TIMED(KK_PRIMS, launch_prims(D, m, g, B.W, B.prim, B.flag, 1, s));
+  TIMED(KK_HEATFLUX, launch_heatflux(D, P, m, v, B.h, B.b, B.prim, B.q, B.flag, s));
   // 3-4 ghost states and macroscopic reconstruction
-  HIP_TRY(launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
+  TIMED(KK_GRADW, launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
   // 6.1-6.6 interface equilibrium data
-  HIP_TRY(launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
+  TIMED(KK_FACE_EQ, launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
   // 5 microscopic reconstruction
-  HIP_TRY(launch_grad_micro(D, P, m, v, B.frec, B.h, B.b, B.gradh, B.gradb, B.flag, s));
+  TIMED(KK_GRAD_MICRO, launch_grad_micro(D, P, m, v, B.frec, B.h, B.b, B.gradh, B.gradb, B.flag, s));
   // 7 wall densities
-  HIP_TRY(launch_wall_rho(D, P, m, v, g, B.h, B.gradh, B.frec, B.flag, s));
+  TIMED(KK_WALL, launch_wall_rho(D, P, m, v, g, B.h, B.gradh, B.frec, B.flag, s));
   // 6.7-6.8 microscopic fluxes and their moments
-  HIP_TRY(launch_flux(D, P, m, v, g, B.frec, B.h, B.b, B.gradh, B.gradb, B.fluxh, B.fluxb, B.F,
-                      B.flag, s));
+  TIMED(KK_FLUX, launch_flux(D, P, m, v, g, B.frec, B.h, B.b, B.gradh, B.gradb, B.fluxh, B.fluxb,
+                              B.F, B.flag, s));
   // 9 first stage
-  HIP_TRY(launch_stage1(D, P, m, v, g, B.prim, B.q, B.h, B.b, B.fluxh, B.fluxb, B.ht, B.bt,
-                        B.flag, s));
+  TIMED(KK_STAGE1, launch_stage1(D, P, m, v, g, B.prim, B.q, B.h, B.b, B.fluxh, B.fluxb, B.ht,
+                                B.bt, B.flag, s));
   // 8 conservative update, 10 new equilibrium
-  HIP_TRY(launch_macro_update(D, m, B.W, B.F, B.Wn, B.cellred, B.flag, s));
-  HIP_TRY(launch_prims(D, m, g, B.Wn, B.primn, B.flag, 1, s));
+  TIMED(KK_MACRO, launch_macro_update(D, m, B.W, B.F, B.Wn, B.cellred, B.flag, s));
+  TIMED(KK_PRIMS, launch_prims(D, m, g, B.Wn, B.primn, B.flag, 1, s));
   // 11 second stage
-  HIP_TRY(launch_stage2(D, P, m, v, g, B.primn, B.q, B.ht, B.bt, B.h, B.b, B.flag, s));
+  TIMED(KK_STAGE2, launch_stage2(D, P, m, v, g, B.primn, B.q, B.ht, B.bt, B.h, B.b, B.flag, s));
   // 12 residual, commit W^{n+1}
-  if (!(c->flags & 1)) HIP_TRY(launch_residual(m, B.cellred, B.resid, B.flag, s));
-  HIP_TRY(launch_commit_W(D, m, B.Wn, B.W, B.flag, s));
+  if (!(c->flags & 1)) TIMED(KK_RESID, launch_residual(m, B.cellred, B.resid, B.flag, s));
+  TIMED(KK_COMMIT, launch_commit_W(D, m, B.Wn, B.W, B.flag, s));
 }
 
 }  // namespace
@@ -725,9 +807,60 @@ int ugks_info(const ugks_ctx* c, ugks_info_t* out) {
   return UGKS_OK;
 }
 
+int ugks_profile_enable(ugks_ctx* c, int32_t on) {
+  if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
+  try {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto& e : c->prof_events) {
+      c->event_pool.push_back(e.second.first);
+      c->event_pool.push_back(e.second.second);
+    }
+    c->prof_events.clear();
+    c->profiling = on != 0;
+  } catch (const HipFail& e) {
+    return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return UGKS_OK;
+}
+
+int ugks_profile_read(ugks_ctx* c, ugks_kernel_time* out, int32_t max, int32_t* n_out) {
+  if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
+  try {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double tot[KK_COUNT] = {0};
+    int64_t cnt[KK_COUNT] = {0};
+    for (auto& e : c->prof_events) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+      tot[e.first] += ms;
+      cnt[e.first] += 1;
+    }
+    int n = 0;
+    for (int k = 0; k < KK_COUNT; ++k) {
+      if (!cnt[k]) continue;
+      if (out && n < max) {
+        std::memset(out[n].name, 0, sizeof(out[n].name));
+        std::strncpy(out[n].name, kKernelNames[k], sizeof(out[n].name) - 1);
+        out[n].launches = cnt[k];
+        out[n].total_ms = tot[k];
+      }
+      ++n;
+    }
+    if (n_out) *n_out = n;
+  } catch (const HipFail& e) {
+    return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return UGKS_OK;
+}
+
 void ugks_destroy(ugks_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->prof_events) {
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   for (void* p : c->allocations) (void)hipFree(p);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;

@@ -205,5 +205,9 @@ struct ugks_ctx {
   int64_t bytes = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // kernel timing (ugks_profile_enable): event pairs per launch, in order
+  bool profiling = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;
+  std::vector<hipEvent_t> event_pool;
   std::string err;
 };

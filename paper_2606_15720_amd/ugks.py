@@ -22,7 +22,8 @@ UGKS_FP64, UGKS_FP32 = 64, 32
 # every entry point include/ugks.h declares
 EXPORTED = [
     "ugks_create", "ugks_step", "ugks_moments", "ugks_get_state", "ugks_set_state",
-    "ugks_face_data", "ugks_info", "ugks_destroy", "ugks_last_error",
+    "ugks_face_data", "ugks_info", "ugks_destroy", "ugks_last_error", "ugks_profile_enable",
+    "ugks_profile_read",
 ]
 
 
@@ -60,6 +61,10 @@ class ugks_info_t(C.Structure):
                 ("steps_done", C.c_int64), ("device_bytes", C.c_int64), ("fused", C.c_int32)]
 
 
+class ugks_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -91,6 +96,10 @@ def load_library(path: str = LIB_PATH):
     lib.ugks_destroy.argtypes = [P]
     lib.ugks_last_error.restype = C.c_char_p
     lib.ugks_last_error.argtypes = [P]
+    lib.ugks_profile_enable.restype = C.c_int
+    lib.ugks_profile_enable.argtypes = [P, C.c_int32]
+    lib.ugks_profile_read.restype = C.c_int
+    lib.ugks_profile_read.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
     _lib = lib
     return lib
 
@@ -174,6 +183,19 @@ def ugks_info(h) -> dict:
     info = ugks_info_t()
     _check(load_library().ugks_info(h, C.byref(info)), h)
     return {f: getattr(info, f) for f, _ in ugks_info_t._fields_}
+
+
+def ugks_profile_enable(h, on: bool = True):
+    _check(load_library().ugks_profile_enable(h, 1 if on else 0), h)
+
+
+def ugks_profile_read(h) -> dict:
+    """{kernel kind: (launches, total_ms)} recorded since ugks_profile_enable."""
+    arr = (ugks_kernel_time * 32)()
+    n = C.c_int32(0)
+    _check(load_library().ugks_profile_read(h, C.cast(arr, C.c_void_p), 32, C.byref(n)), h)
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
+            for i in range(min(n.value, 32))}
 
 
 def ugks_destroy(h):
