@@ -130,7 +130,11 @@ typedef struct {
 /*
  * Options.
  *   precision  UGKS_FP64 (default when 0) or UGKS_FP32.
- *   block_v    velocity-block size B_v (64, 128, 256); 0 = library choice.
+ *   block_v    velocity-block size B_v of the fused sweep: velocities per
+ *              work item (a multiple of 64, at least 128; 0 = 2048), the
+ *              paper's B_v (Eq. velocity_block_partition) as a scheduling unit.
+ *   tile_cells cells per tile of the fused sweep's schedule (0 = 256); each
+ *              XCD runs one tile through one velocity block at a time.
  *   flags      bit 0: skip the density residual (saves one small reduction).
  *              bit 1: use the staged sweep even where the fused one applies.
  *              bit 2: keep the caller's cell order internally (by default
@@ -149,6 +153,7 @@ typedef struct {
   int32_t precision;
   int32_t block_v;
   int32_t flags;
+  int32_t tile_cells;
   void* stream;
 } ugks_options;
 
@@ -161,6 +166,7 @@ typedef struct {
   int64_t steps_done;
   int64_t device_bytes;      /* device memory held by the context */
   int32_t fused;             /* 1: the fused sweep runs; 0: the staged sweep */
+  int32_t tile_cells;        /* fused sweep: cells per tile */
 } ugks_info_t;
 
 /*

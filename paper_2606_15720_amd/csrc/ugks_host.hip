@@ -106,8 +106,10 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
           "gas constants must be positive");
   int prec = opt && opt->precision ? opt->precision : UGKS_FP64;
   fail_if(prec != UGKS_FP64 && prec != UGKS_FP32, "precision must be 64 or 32");
-  int Bv = opt && opt->block_v ? opt->block_v : 64;
-  fail_if(Bv % WAVE != 0 || Bv < WAVE || Bv > 1024, "block_v must be a multiple of 64 in [64, 1024]");
+  int Bv = opt && opt->block_v ? opt->block_v : 0;
+  fail_if(Bv < 0 || Bv % WAVE != 0, "block_v must be 0 or a positive multiple of 64");
+  const int tile = opt && opt->tile_cells ? opt->tile_cells : 0;
+  fail_if(tile < 0, "tile_cells must be >= 0");
   c->D = D;
   c->kxi = 3 - D;
   c->nr = D == 2 ? 2 : 1;
@@ -117,7 +119,9 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   c->nc = nc;
   c->nf = nf;
   c->nv = nv;
-  c->nvp = (nv + Bv - 1) / Bv * Bv;
+  // rows are padded to whole waves; the velocity block of the sweep is a
+  // scheduling unit and needs no padding
+  c->nvp = (nv + WAVE - 1) / WAVE * WAVE;
 
   // ---- mesh validation and cell -> face tables --------------------------
   for (int64_t i = 0; i < nc; ++i)
@@ -348,11 +352,21 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   }
   c->bcs = upload(c, hb);
   if (c->fused) {
-    // static records of the fused sweep: the cell's faces, its least-squares
-    // stencil and, per face, the neighbour's stencil, all wave-uniform
-    std::vector<int32_t> ci(nc * CRI, -1);
+    // Static records of the fused sweep: the cell's faces, its least-squares
+    // stencil and, per face, the neighbour's stencil, all wave-uniform.
+    // Every cell is padded to the same shape (4 faces, 4-row stencils) so the
+    // sweep runs one straight-line body:
+    //   * a missing stencil row points at a real row with coefficient 0;
+    //   * a wall face's "neighbour" rows point at the all-zero row nc (so the
+    //     incoming free transport vanishes) and its equilibrium polynomial is
+    //     the constant 1 (or K_xi/(2 lambda_w) for b), so the incoming flux
+    //     is the re-emitted wall Maxwellian; the outgoing member's
+    //     equilibrium term is switched off by the multiplier 0;
+    //   * a missing face (cells with 3 faces) repeats face 0 with S/V = 0.
+    const int32_t zero_row = (int32_t)nc;
+    std::vector<int32_t> ci(nc * CRI, 0);
     std::vector<double> cdr(nc * CRD, 0.0);
-    auto stencil = [&](int64_t cell, int32_t* cells, double* G /* [d*4 + s] */) {
+    auto stencil = [&](int64_t cell, int32_t pad_row, int32_t* cells, double* G /* [d*4 + s] */) {
       int n = 0;
       for (int p = 0; p < nfc[cell]; ++p) {
         int j = cnbr[cell * MAXF + p];
@@ -361,30 +375,41 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
         for (int d = 0; d < 3; ++d) G[d * 4 + n] = lsG[(cell * 3 + d) * MAXF + p];
         ++n;
       }
+      for (int r = n; r < 4; ++r) {
+        cells[r] = pad_row;
+        for (int d = 0; d < 3; ++d) G[d * 4 + r] = 0.0;
+      }
       return n;
     };
     for (int64_t i = 0; i < nc; ++i) {
       int32_t* I = &ci[i * CRI];
       double* Dd = &cdr[i * CRD];
       I[0] = nfc[i];
-      I[1] = stencil(i, &I[2], Dd);
-      for (int p = 0; p < nfc[i]; ++p) {
+      I[1] = stencil(i, (int32_t)i, &I[2], Dd);
+      for (int p = 0; p < 4; ++p) {
+        const int pp = p < nfc[i] ? p : 0;
         int32_t* fi = &I[CRI_F0 + CRI_FS * p];
         double* fd = &Dd[CRD_F0 + CRD_FS * p];
-        const int f = cface[i * MAXF + p];
-        const double sg = csign[i * MAXF + p];
-        const int j = cnbr[i * MAXF + p];
+        const int f = cface[i * MAXF + pp];
+        const double sg = csign[i * MAXF + pp];
+        const int j = cnbr[i * MAXF + pp];
         fi[0] = f;
         fi[1] = fbc[f];
-        fi[2] = sg > 0.0 ? 1 : 0;
-        fi[3] = j;
-        fi[4] = j >= 0 ? stencil(j, &fi[5], &fd[10]) : 0;
+        fi[2] = (p < nfc[i] && sg > 0.0) ? 1 : 0;
+        fi[3] = j >= 0 ? j : zero_row;
+        fi[4] = j >= 0 ? stencil(j, j, &fi[5], &fd[10]) : 0;
+        if (j < 0)
+          for (int r = 0; r < 4; ++r) {
+            fi[5 + r] = zero_row;
+            for (int d = 0; d < 3; ++d) fd[10 + d * 4 + r] = 0.0;
+          }
         for (int d = 0; d < 3; ++d) {
           fd[0 + d] = sg * fnorm[f * 3 + d];
           fd[4 + d] = sg > 0.0 ? fdxL[f * 3 + d] : fdxR[f * 3 + d];
           fd[7 + d] = sg > 0.0 ? fdxR[f * 3 + d] : fdxL[f * 3 + d];
         }
-        fd[3] = farea[f] / vol[i];
+        fd[3] = p < nfc[i] ? farea[f] / vol[i] : 0.0;
+        fd[22] = j >= 0 ? 1.0 : 0.0;  // equilibrium term of the outgoing member
       }
     }
     std::vector<int32_t> vidx(nv);
@@ -421,15 +446,30 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   B.gW = dalloc<double>(c, nc * 15);
   B.frec = dalloc<double>(c, nf * FREC);
   B.F = dalloc<double>(c, nf * 5);
-  B.dW = dalloc<double>(c, nc * 5);
   if (c->fused) {
+    // velocity block: B_v velocities = B_v/2 mirror pairs per work item
+    const int64_t npairs = (nv + 1) / 2;
+    int64_t cp = Bv ? Bv / 2 : 1024;
+    cp = std::max<int64_t>(64, std::min<int64_t>(cp, npairs));
+    c->sched.nf = nf;
+    c->sched.chunk_pairs = cp;
+    c->sched.nchunk = (npairs + cp - 1) / cp;
+    c->sched.tile = tile ? tile : 256;
+    c->Bv = (int)(2 * cp);
+    B.dW = dalloc<double>(c, nc * c->sched.nchunk * 5);
+    B.tabs = dalloc<double>(c, (nf + nc) * (int64_t)D * c->fmesh.na);
     B.cs = dalloc<double>(c, nc * CSREC);
     B.csn = dalloc<double>(c, nc * CSREC);
+  } else {
+    B.dW = dalloc<double>(c, nc * 5);
   }
-  B.h = dalloc<char>(c, (size_t)nc * nvp * esz);
+  // row nc of h and b stays zero: the fused sweep's wall faces read it
+  B.h = dalloc<char>(c, (size_t)(nc + 1) * nvp * esz);
   B.ht = dalloc<char>(c, (size_t)nc * nvp * esz);
-  B.b = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)nc * nvp * esz) : nullptr;
+  B.b = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)(nc + 1) * nvp * esz) : nullptr;
   B.bt = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)nc * nvp * esz) : nullptr;
+  HIP_TRY(hipMemset(B.h, 0, (size_t)(nc + 1) * nvp * esz));
+  if (B.b) HIP_TRY(hipMemset(B.b, 0, (size_t)(nc + 1) * nvp * esz));
   if (!c->fused) {
     // the staged sweep keeps every gradient and microscopic flux in HBM
     B.gradh = dalloc<double>(c, (size_t)nc * 3 * nvp);
@@ -484,12 +524,12 @@ int set_err(ugks_ctx* c, int code, const std::string& msg) {
 // Kernel kinds timed by ugks_profile_enable.
 enum KernelKind {
   KK_PRIMS, KK_HEATFLUX, KK_GRADW, KK_FACE_EQ, KK_WALL, KK_SWEEP, KK_STAGE1, KK_GRAD_MICRO,
-  KK_FLUX, KK_MACRO, KK_STAGE2, KK_RESID, KK_COMMIT, KK_COUNT
+  KK_FLUX, KK_MACRO, KK_STAGE2, KK_RESID, KK_COMMIT, KK_TABLES, KK_COUNT
 };
 const char* const kKernelNames[KK_COUNT] = {
     "cell_prims", "heat_flux", "macro_gradient", "face_equilibrium", "wall_density",
     "sweep", "stage1", "micro_gradient", "face_flux", "macro_update", "stage2", "residual",
-    "commit"};
+    "commit", "maxwell_tables"};
 
 hipEvent_t take_event(ugks_ctx* c) {
   if (!c->event_pool.empty()) {
@@ -549,11 +589,13 @@ void enqueue_step_fused(ugks_ctx* c) {
   TIMED(KK_FACE_EQ, launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
   // 7 wall densities
   TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, g, B.h, B.frec, B.flag, s));
+  // Maxwellian axis tables of every face and cell of this step
+  TIMED(KK_TABLES, launch_tables(D, m, c->fmesh, g, B.frec, B.prim, B.cs, B.tabs, B.flag, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep
-  TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, B.prim, B.cs, B.frec, B.h, B.b, B.ht, B.bt,
-                                 B.dW, B.flag, s));
+  TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, c->sched, B.cs, B.frec, B.tabs, B.h, B.b,
+                               B.ht, B.bt, B.dW, B.flag, s));
   // 8 conservative update; 10 new equilibrium (with q^n, reading R17)
-  TIMED(KK_MACRO, launch_apply_dW(D, m, B.W, B.dW, B.Wn, B.cellred, B.flag, s));
+  TIMED(KK_MACRO, launch_apply_dW(D, m, c->sched.nchunk, B.W, B.dW, B.Wn, B.cellred, B.flag, s));
   TIMED(KK_PRIMS, launch_cell_prep(D, c->nc, g, B.Wn, B.q, B.primn, B.csn, B.flag, s));
   // 11 second stage and the heat flux of h^{n+1}
   TIMED(KK_STAGE2, launch_stage2_q(D, P, c->fmesh, v, B.primn, B.csn, B.ht, B.bt, B.h, B.b, B.qn,
@@ -804,6 +846,7 @@ int ugks_info(const ugks_ctx* c, ugks_info_t* out) {
   out->steps_done = c->steps_done;
   out->device_bytes = c->bytes;
   out->fused = c->fused ? 1 : 0;
+  out->tile_cells = c->fused ? (int32_t)c->sched.tile : 0;
   return UGKS_OK;
 }
 

@@ -71,9 +71,10 @@ struct DevMesh {
 //   [d*4 + s] own least-squares coefficients G[d][s],
 //   face p at CRD_F0 + CRD_FS p: [0..2] outward unit normal, [3] S/V,
 //   [4..6] x_f - x_cell, [7..9] x_f - x_neighbour, [10 + d*4 + r] the
-//   neighbour's coefficients G[d][r].
+//   neighbour's coefficients G[d][r], [22] 1 (0 on a wall: the outgoing
+//   member has no equilibrium term).
 constexpr int CRI = 48, CRI_F0 = 6, CRI_FS = 10;
-constexpr int CRD = 104, CRD_F0 = 12, CRD_FS = 22;
+constexpr int CRD = 112, CRD_F0 = 12, CRD_FS = 24;
 // Per-cell, per-step record of the fused path (CSREC doubles per cell).
 constexpr int CSREC = 48, CS_CC = 0, CS_KAP = 1, CS_NORM = 2, CS_SH = 4, CS_SB = 24;
 
@@ -84,6 +85,15 @@ struct FusedMesh {
   const int32_t* vidx;      // [nv] packed axis indices of point k (8 bits per axis, first axis low)
   const int32_t* crec_i;    // [nc*CRI]
   const double* crec_d;     // [nc*CRD]
+};
+
+// Schedule of the fused sweep: work item = (cell, velocity block of
+// chunk_pairs mirror pairs); tiles of `tile` consecutive cells per XCD.
+struct SweepSched {
+  int64_t nf;             // face count (cell tables follow the face tables)
+  int64_t tile;           // cells per tile
+  int64_t nchunk;         // velocity blocks
+  int64_t chunk_pairs;    // mirror pairs per velocity block
 };
 
 struct DevVel {
@@ -113,7 +123,8 @@ struct StepBuffers {
   double* gW;      // [nc*3*5]
   double* frec;    // [nf*FREC]
   double* F;       // [nf*5] face fluxes (staged sweep)
-  double* dW;      // [nc*5] per-cell net outflow moments (fused sweep)
+  double* dW;      // [nc*nchunk*5] per-(cell, velocity block) net outflow moments (fused sweep)
+  double* tabs;    // [(nf+nc)*D*na] Maxwellian axis tables of the step (fused sweep)
   double* cs;      // [nc*CSREC] per-step cell record of W^n (fused sweep)
   double* csn;     // [nc*CSREC] per-step cell record of W^{n+1}
   void* h;         // [nc*nvp] storage type
@@ -172,11 +183,15 @@ hipError_t launch_dt_cells(int D, const DevMesh& m, const DevVel& v, double* cel
 hipError_t launch_cell_prep(int D, int64_t nc, const GasP& g, const double* W, const double* q,
                             double* prim, double* cs, int32_t* flag, hipStream_t s);
 hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, const GasP& g,
-                        const double* prim, const double* cs, const double* frec, const void* h,
-                        const void* b, void* ht, void* bt, double* dW, const int32_t* flag,
-                        hipStream_t s);
-hipError_t launch_apply_dW(int D, const DevMesh& m, const double* W, const double* dW, double* Wn,
-                          double* cellred, const int32_t* flag, hipStream_t s);
+                        const SweepSched& sc, const double* cs, const double* frec,
+                        const double* tabs, const void* h, const void* b, void* ht, void* bt,
+                        double* dWp, const int32_t* flag, hipStream_t s);
+hipError_t launch_tables(int D, const DevMesh& m, const FusedMesh& fm, const GasP& g,
+                         const double* frec, const double* prim, const double* cs, double* tabs,
+                         const int32_t* flag, hipStream_t s);
+hipError_t launch_apply_dW(int D, const DevMesh& m, int64_t nchunk, const double* W,
+                          const double* dWp, double* Wn, double* cellred, const int32_t* flag,
+                          hipStream_t s);
 hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v,
                            const double* primn, const double* csn, const void* ht, const void* bt,
                            void* h, void* b, double* qn, const int32_t* flag, hipStream_t s);
@@ -191,6 +206,7 @@ struct ugks_ctx {
   bool fused = false;       // tensor-product symmetric velocity set, walls / interior only
   bool q_valid = false;     // buf.q holds the heat flux of the current h
   ugks::FusedMesh fmesh{};  // static records of the fused sweep
+  ugks::SweepSched sched{};
   int64_t nc = 0, nf = 0, nv = 0, nvp = 0;
   int64_t steps_done = 0;
   ugks::GasP gas{};

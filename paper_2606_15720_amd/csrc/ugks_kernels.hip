@@ -102,6 +102,14 @@ __global__ void k_face_eq(DevMesh m, const DevBC* __restrict__ bcs, GasP g,
     R[FR_C0] = maxw_norm<D>(lamw);
     R[FR_LAM] = lamw;
     for (int d = 0; d < 3; ++d) R[FR_U + d] = d < D ? bc.U[d] : 0.0;
+    // free transport of the incident member over the step (h_f - t u.grad h),
+    // and the re-emitted Maxwellian as g(u) times a constant polynomial
+    R[FR_G] = g.dt;
+    R[FR_G + 1] = -0.5 * g.dt * g.dt;
+    for (int x = 0; x < 20; ++x) {
+      R[FR_PH + x] = x == 0 ? 1.0 : 0.0;
+      R[FR_PB + x] = x == 0 ? (3 - D) / (2.0 * lamw) : 0.0;
+    }
     return;
   }
   const bool ghost = kind != UGKS_BC_INTERIOR;

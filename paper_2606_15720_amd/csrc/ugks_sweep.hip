@@ -88,37 +88,36 @@ __global__ void k_cell_prep(int64_t nc, GasP g, const double* __restrict__ W,
   }
 }
 
-// Axis tables of the face Maxwellians and of the cell Maxwellian in LDS.
+// Axis tables of every face Maxwellian and every cell Maxwellian of the
+// step, tab[e][d][n] = scale_d exp(-lambda (a_n - U_d)^2) with the density
+// and normalisation folded into d = 0, so that g(u) at a tensor point is a
+// product of D entries.  Entities 0..nf-1 are faces (interface g0, or on a
+// wall the re-emitted Maxwellian scaled by rho_w dt), nf..nf+nc-1 cells.
 template <int D>
-__device__ __forceinline__ void build_tables(double (*tab)[3][NAX], double (*ctab)[NAX], double* ax,
-                                             const FusedMesh& fm, const GasP& g,
-                                             const double* __restrict__ prim,
-                                             const double* __restrict__ cs,
-                                             const double* __restrict__ frec, int64_t ic, int nf) {
-  const int na = fm.na;
-  const int32_t* ci = fm.crec_i + ic * CRI;
-  for (int t = threadIdx.x; t < na; t += SWT) ax[t] = fm.axis[t];
-  const int ntab = (nf + 1) * D * na;
-  for (int t = threadIdx.x; t < ntab; t += SWT) {
-    const int p = t / (D * na), r = t % (D * na);
-    const int d = r / na, n = r % na;
-    const double a = fm.axis[n];
-    if (p == nf) {
-      const double* P = &prim[ic * NPRIM];
-      const double lam = P[4], U = P[1 + d];
-      const double scale = d == 0 ? cs[ic * CSREC + CS_NORM] : 1.0;
-      ctab[d][n] = scale * exp(-lam * (a - U) * (a - U));
-    } else {
-      const int64_t f = ci[CRI_F0 + CRI_FS * p + 0];
-      const double* R = &frec[f * FREC];
-      const double lam = R[FR_LAM], U = R[FR_U + d];
-      double scale = 1.0;
-      if (d == 0)  // rho0 (lambda0/pi)^(D/2), or rho_w dt (lambda_w/pi)^(D/2) on a wall
-        scale = ci[CRI_F0 + CRI_FS * p + 1] == UGKS_BC_WALL ? R[FR_C0] * R[FR_RHOW] * g.dt : R[FR_C0];
-      tab[p][d][n] = scale * exp(-lam * (a - U) * (a - U));
-    }
+__global__ void k_tables(int64_t nf, int64_t nc, int na, const double* __restrict__ axis,
+                         const int32_t* __restrict__ fbc, GasP g, const double* __restrict__ frec,
+                         const double* __restrict__ prim, const double* __restrict__ cs,
+                         double* __restrict__ tabs, const int32_t* __restrict__ flag) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)D * na;
+  if (t >= (nf + nc) * per || *flag) return;
+  const int64_t e = t / per;
+  const int r = (int)(t % per), d = r / na, n = r % na;
+  const double a = axis[n];
+  double lam, U, scale = 1.0;
+  if (e < nf) {
+    const double* R = &frec[e * FREC];
+    lam = R[FR_LAM];
+    U = R[FR_U + d];
+    if (d == 0)  // rho0 (lambda0/pi)^(D/2), or rho_w dt (lambda_w/pi)^(D/2) on a wall
+      scale = fbc[e] == UGKS_BC_WALL ? R[FR_C0] * R[FR_RHOW] * g.dt : R[FR_C0];
+  } else {
+    const int64_t i = e - nf;
+    lam = prim[i * NPRIM + 4];
+    U = prim[i * NPRIM + 1 + d];
+    if (d == 0) scale = cs[i * CSREC + CS_NORM];
   }
-  __syncthreads();
+  tabs[e * per + d * na + n] = scale * exp(-lam * (a - U) * (a - U));
 }
 
 // Every read-only array is its own __restrict__ kernel argument so that the
@@ -126,31 +125,52 @@ __device__ __forceinline__ void build_tables(double (*tab)[3][NAX], double (*cta
 // wave-uniform reads from the scalar cache.
 template <int D, typename T>
 __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
-    FusedMesh fm, GasP g, int64_t nvp, const int32_t* __restrict__ crec_i,
+    FusedMesh fm, GasP g, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
     const double* __restrict__ crec_d, const int32_t* __restrict__ vidx,
-    const double* __restrict__ w, const double* __restrict__ prim, const double* __restrict__ cs,
-    const double* __restrict__ frec, const T* __restrict__ h, const T* __restrict__ b,
-    T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dW, const int32_t* __restrict__ flag) {
+    const double* __restrict__ w, const double* __restrict__ cs, const double* __restrict__ frec,
+    const double* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
+    T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dWp,
+    const int32_t* __restrict__ flag) {
   __shared__ double tab[SWF][3][NAX];
   __shared__ double ctab[3][NAX];
   __shared__ double ax[NAX];
-  __shared__ double red[5 * 16];
   if (*flag) return;
-  // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-  // range of cells so neighbouring cells share an L2
-  const int64_t per = (fm.nc + 7) / 8;
-  const int64_t ic = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  // Work item = (cell, velocity block).  Blocks are dealt round-robin to the
+  // 8 XCDs; XCD x takes tiles x, x+8, ... of sc.tile consecutive (Z-order)
+  // cells and runs all of a tile's cells through velocity block 0, then 1,
+  // ..., so the stencil rows of one tile and one velocity block are what
+  // its L2 must hold.
+  const int64_t xcd = blockIdx.x % 8, local = blockIdx.x / 8;
+  const int64_t per_tile = sc.nchunk * sc.tile;
+  const int64_t tile = (local / per_tile) * 8 + xcd;
+  const int64_t rem = local % per_tile;
+  const int64_t chunk = rem / sc.tile;
+  const int64_t ic = tile * sc.tile + rem % sc.tile;
   if (ic >= fm.nc) return;
   // every pointer below is wave-uniform: its loads are scalar loads
   const int32_t* __restrict__ ci0 = crec_i + ic * CRI;
   const double* __restrict__ cd0 = crec_d + ic * CRD;
   const double* __restrict__ cc0 = cs + ic * CSREC;
-  const int nf = ci0[0], on = ci0[1];
-  build_tables<D>(tab, ctab, ax, fm, g, prim, cs, frec, ic, nf);
+  const int na = fm.na;
+  {
+    // stage this cell's face and cell tables in LDS (faces 0..3, then the cell)
+    const int per = D * na, n_all = 5 * per;
+    for (int t = threadIdx.x; t < n_all; t += SWT) {
+      const int p = t / per, r = t % per, d = r / na, n = r % na;
+      const int64_t e = p < 4 ? (int64_t)ci0[CRI_F0 + CRI_FS * p] : sc.nf + ic;
+      const double v = tabs[e * per + d * na + n];
+      if (p < 4) tab[p][d][n] = v;
+      else ctab[d][n] = v;
+    }
+    for (int t = threadIdx.x; t < na; t += SWT) ax[t] = fm.axis[t];
+    __syncthreads();
+  }
   constexpr int NM = D + 2;
   constexpr bool B2 = (D == 2);  // the b equation is carried in 2-D only
   const unsigned nv = (unsigned)fm.nv;
   const unsigned npairs = (nv + 1) / 2;
+  const unsigned kbeg = (unsigned)(chunk * sc.chunk_pairs);
+  const unsigned kend = (unsigned)min((int64_t)npairs, (chunk + 1) * sc.chunk_pairs);
   const T* __restrict__ hi = h + ic * nvp;
   const T* __restrict__ bi = B2 ? b + ic * nvp : nullptr;
   // per-lane moments sum_k w_k psi_k (net outflow of the cell at u_k): the
@@ -160,7 +180,7 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
 #pragma unroll
   for (int x = 0; x < NM; ++x) mw[x] = 0.0;
 
-  for (unsigned kp = threadIdx.x; kp < npairs; kp += SWT) {
+  for (unsigned kp = kbeg + threadIdx.x; kp < kend; kp += SWT) {
     // The cell and face records are loop invariant but too large to keep in
     // scalar registers for the whole loop: an opaque uniform zero added to
     // their addresses makes them scalar re-loads (scalar cache) each
@@ -176,82 +196,69 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       id[d] = (pk >> (8 * d)) & 255;
-      im[d] = fm.na - 1 - id[d];
+      im[d] = na - 1 - id[d];
     }
     double vv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int d = 0; d < D; ++d) vv[d] = ax[id[d]];
     // orientation of u against every outward normal
-    double sp[SWF];
+    double sp[4];
 #pragma unroll
-    for (int p = 0; p < SWF; ++p) {
+    for (int p = 0; p < 4; ++p) {
       double s = 0.0;
 #pragma unroll
       for (int d = 0; d < D; ++d) s += vv[d] * cd[CRD_F0 + CRD_FS * p + 0 + d];
       sp[p] = s;
     }
-    // ---- the cell's own stencil at u and -u ----
+    // ---- the cell's own stencil at u and -u (4 rows, padded) ----
     const double h0 = ld(hi, k0), h1 = ld(hi, k1);
     double b0 = 0.0, b1 = 0.0;
     if (B2) {
       b0 = ld(bi, k0);
       b1 = ld(bi, k1);
     }
-    double os0[SWF], os1[SWF], ob0[SWF], ob1[SWF];
+    double os0[4], os1[4], ob0[4], ob1[4];
 #pragma unroll
-    for (int s = 0; s < SWF; ++s) {
-      os0[s] = os1[s] = ob0[s] = ob1[s] = 0.0;
-      if (s < on) {
-        const int64_t cell = ci[2 + s];
-        const T* __restrict__ row = h + cell * nvp;
-        os0[s] = ld(row, k0);
-        os1[s] = ld(row, k1);
-        if (B2) {
-          const T* __restrict__ rb = b + cell * nvp;
-          ob0[s] = ld(rb, k0);
-          ob1[s] = ld(rb, k1);
-        }
-      }
-    }
-    double g0[3] = {0, 0, 0}, g1[3] = {0, 0, 0}, gb0[3] = {0, 0, 0}, gb1[3] = {0, 0, 0};
-#pragma unroll
-    for (int s = 0; s < SWF; ++s) {
-      if (s < on) {
-        const double d0 = os0[s] - h0, d1 = os1[s] - h1;
-        const double e0 = ob0[s] - b0, e1 = ob1[s] - b1;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const double G = cd[d * 4 + s];
-          g0[d] += G * d0;
-          g1[d] += G * d1;
-          if (B2) {
-            gb0[d] += G * e0;
-            gb1[d] += G * e1;
-          }
-        }
+    for (int s = 0; s < 4; ++s) {
+      const int64_t cell = ci[2 + s];
+      os0[s] = ld(h + cell * nvp, k0);
+      os1[s] = ld(h + cell * nvp, k1);
+      ob0[s] = ob1[s] = 0.0;
+      if (B2) {
+        ob0[s] = ld(b + cell * nvp, k0);
+        ob1[s] = ld(b + cell * nvp, k1);
       }
     }
     // ---- every neighbour's value and stencil at the incoming member ----
-    double nh[SWF], nhs[SWF][SWF], nb[SWF], nbs[SWF][SWF];
+    double nh[4], nhs[4][4], nb[4], nbs[4][4];
 #pragma unroll
-    for (int p = 0; p < SWF; ++p) {
-      nh[p] = nb[p] = 0.0;
-#pragma unroll
-      for (int r = 0; r < SWF; ++r) nhs[p][r] = nbs[p][r] = 0.0;
+    for (int p = 0; p < 4; ++p) {
       const int32_t* fi = ci + CRI_F0 + CRI_FS * p;
-      if (p < nf && fi[1] != UGKS_BC_WALL) {
-        const unsigned kin = sp[p] > 0.0 ? k1 : k0;
-        const int64_t j = fi[3];
-        nh[p] = ld(h + j * nvp, kin);
-        if (B2) nb[p] = ld(b + j * nvp, kin);
-        const int jn = fi[4];
+      const unsigned kin = sp[p] > 0.0 ? k1 : k0;
+      const int64_t j = fi[3];
+      nh[p] = ld(h + j * nvp, kin);
+      nb[p] = B2 ? ld(b + j * nvp, kin) : 0.0;
 #pragma unroll
-        for (int r = 0; r < SWF; ++r) {
-          if (r < jn) {
-            const int64_t cell = fi[5 + r];
-            nhs[p][r] = ld(h + cell * nvp, kin);
-            if (B2) nbs[p][r] = ld(b + cell * nvp, kin);
-          }
+      for (int r = 0; r < 4; ++r) {
+        const int64_t cell = fi[5 + r];
+        nhs[p][r] = ld(h + cell * nvp, kin);
+        nbs[p][r] = B2 ? ld(b + cell * nvp, kin) : 0.0;
+      }
+    }
+    // ---- arithmetic ----
+    double g0[3] = {0, 0, 0}, g1[3] = {0, 0, 0}, gb0[3] = {0, 0, 0}, gb1[3] = {0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double d0 = os0[s] - h0, d1 = os1[s] - h1;
+      const double e0 = ob0[s] - b0, e1 = ob1[s] - b1;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const double G = cd[d * 4 + s];
+        g0[d] += G * d0;
+        g1[d] += G * d1;
+        if (B2) {
+          gb0[d] += G * e0;
+          gb1[d] += G * e1;
         }
       }
     }
@@ -270,87 +277,73 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
     for (int d = 0; d < D; ++d) v2 += vv[d] * vv[d];
     double acc0 = 0.0, acc1 = 0.0, accb0 = 0.0, accb1 = 0.0;
 #pragma unroll
-    for (int p = 0; p < SWF; ++p) {
-      if (p >= nf) break;
-      const int32_t* fi = ci + CRI_F0 + CRI_FS * p;
+    for (int p = 0; p < 4; ++p) {
       const double* fd = cd + CRD_F0 + CRD_FS * p;
-      const double* R = frec + (int64_t)fi[0] * FREC;
+      const double* R = frec + (int64_t)ci[CRI_F0 + CRI_FS * p] * FREC;
       const bool pos = sp[p] > 0.0;
       const double as = fabs(sp[p]);
+      const double G1 = R[FR_G], G2 = R[FR_G + 1];
       // outgoing member: the cell's own reconstruction at the face
       const double us = pos ? ug0 : ug1;
       double hf = pos ? h0 : h1;
 #pragma unroll
       for (int d = 0; d < D; ++d) hf += fd[4 + d] * (pos ? g0[d] : g1[d]);
-      double bfo = 0.0, ubs = 0.0;
-      if (B2) {
-        bfo = pos ? b0 : b1;
-        ubs = pos ? ub0 : ub1;
+      // incoming member: the neighbour's reconstruction at the face (all
+      // zero rows on a wall)
+      const double sgn_in = pos ? -1.0 : 1.0;  // u_in = sgn_in * u
+      const double hj = nh[p], bj = nb[p];
+      double gj[3] = {0, 0, 0}, gbj[3] = {0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < D; ++d) bfo += fd[4 + d] * (pos ? gb0[d] : gb1[d]);
+      for (int r = 0; r < 4; ++r) {
+        const double dh = nhs[p][r] - hj, db = nbs[p][r] - bj;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const double G = fd[10 + d * 4 + r];
+          gj[d] += G * dh;
+          if (B2) gbj[d] += G * db;
+        }
       }
-      // g0 (or the scaled wall Maxwellian) at u and -u from the axis tables
+      double hfj = hj, ugj = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        hfj += fd[7 + d] * gj[d];
+        ugj += vv[d] * gj[d];
+      }
+      ugj *= sgn_in;
+      // g0 (or the scaled wall Maxwellian) at u and -u from the axis tables,
+      // times the equilibrium polynomial (constant on a wall)
       double e0 = tab[p][0][id[0]], e1 = tab[p][0][im[0]];
 #pragma unroll
       for (int d = 1; d < D; ++d) {
         e0 *= tab[p][d][id[d]];
         e1 *= tab[p][d][im[d]];
       }
-      double out, in, outb = 0.0, inb = 0.0;
-      if (fi[1] == UGKS_BC_WALL) {
-        // incident free transport out of the cell, diffuse re-emission in
-        const double dt = g.dt;
-        out = as * (dt * hf - 0.5 * dt * dt * us);
-        in = -as * (pos ? e1 : e0);
-        if (B2) {
-          outb = as * (dt * bfo - 0.5 * dt * dt * ubs);
-          inb = (3 - D) / (2.0 * R[FR_LAM]) * in;
-        }
-      } else {
-        const double G1 = R[FR_G], G2 = R[FR_G + 1];
-        double E, O;
-        cubic_eo<D>(R + FR_PH, vv, E, O);
-        const double P0 = E + O, P1 = E - O;
-        const double eqo = pos ? e0 * P0 : e1 * P1;
-        const double eqi = pos ? e1 * P1 : e0 * P0;
-        // incoming member: the neighbour's reconstruction at the face
-        const double sgn_in = pos ? -1.0 : 1.0;  // u_in = sgn_in * u
-        const double hj = nh[p], bj = nb[p];
-        double gj[3] = {0, 0, 0}, gbj[3] = {0, 0, 0};
-        const int jn = fi[4];
+      double E, O;
+      cubic_eo<D>(R + FR_PH, vv, E, O);
+      const double q0 = e0 * (E + O), q1 = e1 * (E - O);
+      const double eqm = fd[22];  // 0 on a wall: no equilibrium term going out
+      const double eqo = eqm * (pos ? q0 : q1);
+      const double eqi = pos ? q1 : q0;
+      const double out = as * (G1 * hf + G2 * us + eqo);
+      const double in = -as * (G1 * hfj + G2 * ugj + eqi);
+      double outb = 0.0, inb = 0.0;
+      if (B2) {
+        double bfo = pos ? b0 : b1;
+        const double ubs = pos ? ub0 : ub1;
 #pragma unroll
-        for (int r = 0; r < SWF; ++r) {
-          if (r < jn) {
-            const double dh = nhs[p][r] - hj, db = nbs[p][r] - bj;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-              const double G = fd[10 + d * 4 + r];
-              gj[d] += G * dh;
-              if (B2) gbj[d] += G * db;
-            }
-          }
-        }
-        double hfj = hj, ugj = 0.0, bfj = bj, ubj = 0.0;
+        for (int d = 0; d < D; ++d) bfo += fd[4 + d] * (pos ? gb0[d] : gb1[d]);
+        double bfj = bj, ubj = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          hfj += fd[7 + d] * gj[d];
-          ugj += vv[d] * gj[d];
-          if (B2) {
-            bfj += fd[7 + d] * gbj[d];
-            ubj += vv[d] * gbj[d];
-          }
+          bfj += fd[7 + d] * gbj[d];
+          ubj += vv[d] * gbj[d];
         }
-        ugj *= sgn_in;
         ubj *= sgn_in;
-        out = as * (G1 * hf + G2 * us + eqo);
-        in = -as * (G1 * hfj + G2 * ugj + eqi);
-        if (B2) {
-          double Eb, Ob;
-          cubic_eo<D>(R + FR_PB, vv, Eb, Ob);
-          const double Q0 = Eb + Ob, Q1 = Eb - Ob;
-          outb = as * (G1 * bfo + G2 * ubs + (pos ? e0 * Q0 : e1 * Q1));
-          inb = -as * (G1 * bfj + G2 * ubj + (pos ? e1 * Q1 : e0 * Q0));
-        }
+        double Eb, Ob;
+        cubic_eo<D>(R + FR_PB, vv, Eb, Ob);
+        const double r0 = e0 * (Eb + Ob), r1 = e1 * (Eb - Ob);
+        outb = as * (G1 * bfo + G2 * ubs + eqm * (pos ? r0 : r1));
+        inb = -as * (G1 * bfj + G2 * ubj + (pos ? r1 : r0));
       }
       // fluxes at u and at -u along this cell's outward normal, times S/V
       const double sv = fd[3];
@@ -393,19 +386,25 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
       if (k1 != k0) st(bto, k1, b1 - accb1 + ccoll * (kc * c1 * (1.0 + Eb - Ob) - b1));
     }
   }
+  __shared__ double red[5 * 16];
   block_sum<NM>(mw, red);
   if (threadIdx.x == 0)
-    for (int x = 0; x < 5; ++x) dW[ic * 5 + x] = x < NM ? mw[x] : 0.0;
+    for (int x = 0; x < 5; ++x) dWp[(ic * sc.nchunk + chunk) * 5 + x] = x < NM ? mw[x] : 0.0;
 }
 
 // Conservative update of the fused path: W^{n+1} = W^n - dW.
+// The partial sums of the velocity blocks are added in block order.
 template <int D>
-__global__ void k_apply_dW(int64_t nc, const double* __restrict__ vol, const double* __restrict__ W,
-                           const double* __restrict__ dW, double* __restrict__ Wn,
-                           double* __restrict__ cellred, const int32_t* flag) {
+__global__ void k_apply_dW(int64_t nc, int64_t nchunk, const double* __restrict__ vol,
+                           const double* __restrict__ W, const double* __restrict__ dWp,
+                           double* __restrict__ Wn, double* __restrict__ cellred, const int32_t* flag) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nc || *flag) return;
-  for (int x = 0; x < D + 2; ++x) Wn[i * (D + 2) + x] = W[i * (D + 2) + x] - dW[i * 5 + x];
+  for (int x = 0; x < D + 2; ++x) {
+    double s = 0.0;
+    for (int64_t c = 0; c < nchunk; ++c) s += dWp[(i * nchunk + c) * 5 + x];
+    Wn[i * (D + 2) + x] = W[i * (D + 2) + x] - s;
+  }
   const double V = vol[i];
   const double dr = Wn[i * (D + 2)] - W[i * (D + 2)];
   cellred[i * 3 + 0] = V * dr * dr;
@@ -554,10 +553,21 @@ __global__ __launch_bounds__(SWT) void k_wall_rho_inline(DevMesh m, DevVel v, Ga
     }                                   \
   } while (0)
 
-hipError_t launch_apply_dW(int D, const DevMesh& m, const double* W, const double* dW, double* Wn,
-                          double* cellred, const int32_t* flag, hipStream_t s) {
+hipError_t launch_apply_dW(int D, const DevMesh& m, int64_t nchunk, const double* W,
+                          const double* dWp, double* Wn, double* cellred, const int32_t* flag,
+                          hipStream_t s) {
   const unsigned grid = (unsigned)((m.nc + 255) / 256);
-  UGKS_DISPATCH_D(D, k_apply_dW<DD><<<grid, 256, 0, s>>>(m.nc, m.vol, W, dW, Wn, cellred, flag));
+  UGKS_DISPATCH_D(D, k_apply_dW<DD><<<grid, 256, 0, s>>>(m.nc, nchunk, m.vol, W, dWp, Wn, cellred, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_tables(int D, const DevMesh& m, const FusedMesh& fm, const GasP& g,
+                         const double* frec, const double* prim, const double* cs, double* tabs,
+                         const int32_t* flag, hipStream_t s) {
+  const int64_t n = (m.nf + m.nc) * (int64_t)D * fm.na;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  UGKS_DISPATCH_D(D, k_tables<DD><<<grid, 256, 0, s>>>(m.nf, m.nc, fm.na, fm.axis, m.fbc, g, frec,
+                                                        prim, cs, tabs, flag));
   return hipGetLastError();
 }
 
@@ -569,13 +579,14 @@ hipError_t launch_cell_prep(int D, int64_t nc, const GasP& g, const double* W, c
 }
 
 hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, const GasP& g,
-                        const double* prim, const double* cs, const double* frec, const void* h,
-                        const void* b, void* ht, void* bt, double* dW, const int32_t* flag,
-                        hipStream_t s) {
-  const unsigned grid = (unsigned)(((fm.nc + 7) / 8) * 8);
+                        const SweepSched& sc, const double* cs, const double* frec,
+                        const double* tabs, const void* h, const void* b, void* ht, void* bt,
+                        double* dWp, const int32_t* flag, hipStream_t s) {
+  const int64_t ntile = (fm.nc + sc.tile - 1) / sc.tile;
+  const unsigned grid = (unsigned)(((ntile + 7) / 8) * 8 * sc.nchunk * sc.tile);
   UGKS_DISPATCH_DT(D, prec, k_sweep<DD, TT><<<grid, SWT, 0, s>>>(
-      fm, g, v.nvp, fm.crec_i, fm.crec_d, fm.vidx, v.w, prim, cs, frec, (const TT*)h, (const TT*)b,
-      (TT*)ht, (TT*)bt, dW, flag));
+      fm, g, v.nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, v.w, cs, frec, tabs, (const TT*)h,
+      (const TT*)b, (TT*)ht, (TT*)bt, dWp, flag));
   return hipGetLastError();
 }
 

@@ -51,14 +51,15 @@ class ugks_bc(C.Structure):
 
 class ugks_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("block_v", C.c_int32), ("flags", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("tile_cells", C.c_int32), ("stream", C.c_void_p)]
 
 
 class ugks_info_t(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_r", C.c_int32), ("precision", C.c_int32),
                 ("block_v", C.c_int32), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
                 ("nv", C.c_int64), ("nv_padded", C.c_int64), ("dt", C.c_double),
-                ("steps_done", C.c_int64), ("device_bytes", C.c_int64), ("fused", C.c_int32)]
+                ("steps_done", C.c_int64), ("device_bytes", C.c_int64), ("fused", C.c_int32),
+                ("tile_cells", C.c_int32)]
 
 
 class ugks_kernel_time(C.Structure):
@@ -125,7 +126,8 @@ def _check(rc, ctx=None):
         raise UGKSError(rc, msg.decode() if msg else "")
 
 
-def ugks_create(mesh, vel, gas, bcs, W0, precision=UGKS_FP64, block_v=0, flags=0, stream=None):
+def ugks_create(mesh, vel, gas, bcs, W0, precision=UGKS_FP64, block_v=0, flags=0, stream=None,
+                tile_cells=0):
     """Create a context from a ``ugks_cases`` mesh / velocity / gas / BC list.
 
     Returns ``(handle, keepalive)``; the arrays are copied by the library, so
@@ -144,7 +146,7 @@ def ugks_create(mesh, vel, gas, bcs, W0, precision=UGKS_FP64, block_v=0, flags=0
     for i, b in enumerate(bcs):
         U = list(b.U) + [0.0] * (3 - len(b.U))
         arr[i] = ugks_bc(b.kind, b.rho, (C.c_double * 3)(*U[:3]), b.T)
-    opt = ugks_options(precision, block_v, flags, C.c_void_p(stream) if stream else None)
+    opt = ugks_options(precision, block_v, flags, tile_cells, C.c_void_p(stream) if stream else None)
     h = C.c_void_p()
     rc = lib.ugks_create(C.byref(cm), C.byref(cv), C.byref(cg), C.cast(arr, C.c_void_p), nb,
                          _p(keep["W0"]), C.byref(opt), C.byref(h))
@@ -211,12 +213,13 @@ def ugks_last_error(h=None) -> str:
 class Solver:
     """Owning wrapper around one library context for a ``ugks_cases.Case``."""
 
-    def __init__(self, case, precision=UGKS_FP64, block_v=0, flags=0, stream=None):
+    def __init__(self, case, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0):
         self.case = case
         self.dim = case.mesh.dim
         self.nc, self.nf, self.nv = case.mesh.n_cells, case.mesh.n_faces, case.vel.nv
         self.h, _ = ugks_create(case.mesh, case.vel, case.gas, case.bcs, case.W0,
-                                precision=precision, block_v=block_v, flags=flags, stream=stream)
+                                precision=precision, block_v=block_v, flags=flags, stream=stream,
+                                tile_cells=tile_cells)
 
     def close(self):
         if getattr(self, "h", None):

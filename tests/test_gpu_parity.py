@@ -121,12 +121,15 @@ def test_fused_path_is_selected_for_tensor_grids():
     s.close()
 
 
-def test_block_size_and_padding_invariance():
+@pytest.mark.parametrize("flags", PATHS)
+def test_block_size_and_tile_invariance(flags):
+    # the velocity block and the tile are scheduling units only: the result
+    # changes at most by the summation order of the per-block moment sums
+    # (the paper's algebraic equivalence of partitioned velocity moments)
     case = uc.cavity2d(n=8, nv=28)
     Ws = []
-    for bv in (64, 128, 256):
-        s = Solver(case, block_v=bv)
-        assert s.info["nv_padded"] % bv == 0
+    for bv, tile in ((128, 1), (256, 7), (1024, 64), (0, 0)):
+        s = Solver(case, block_v=bv, tile_cells=tile, flags=flags)
         s.step(5)
         Ws.append(s.W())
         s.close()
