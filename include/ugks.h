@@ -131,7 +131,7 @@ typedef struct {
  * Options.
  *   precision  UGKS_FP64 (default when 0) or UGKS_FP32.
  *   block_v    velocity-block size B_v of the fused sweep: velocities per
- *              work item (a multiple of 64, at least 128; 0 = 2048), the
+ *              work item (a multiple of 64, at least 128; 0 = 4096), the
  *              paper's B_v (Eq. velocity_block_partition) as a scheduling unit.
  *   tile_cells cells per tile of the fused sweep's schedule (0 = 256); each
  *              XCD runs one tile through one velocity block at a time.
@@ -252,6 +252,86 @@ int ugks_profile_read(ugks_ctx* ctx, ugks_kernel_time* out, int32_t max, int32_t
 
 /* Releases every device buffer; accepts NULL. */
 void ugks_destroy(ugks_ctx* ctx);
+
+/*
+ * Batched form: many independent cases (each its own mesh, velocity set, gas
+ * and boundary table, one dimension and one precision for all) advanced
+ * together, one launch per phase of the step for the whole batch.  Scheduling
+ * follows the paper's velocity-block work decomposition (Eq.
+ * velocity_block_partition, Sec. 3): the velocity sweep is one persistent
+ * launch walking a list of (case, cell, velocity block) work items, the
+ * other phases flatten the cells, faces or wall faces of every case behind
+ * case-offset tables, and the whole step is captured once into a HIP graph
+ * and replayed.  Every case must qualify for the fused sweep (a tensor
+ * product of one symmetric 1-D node set; interior, periodic and wall faces;
+ * at most four faces per cell).
+ *
+ * The velocity-block size and the cell-tile size of each case, and the
+ * lanes per work-group of the sweep, are chosen by an autotuner that times
+ * the sweep on the device at create (options.block_v = 0 and tile_cells = 0)
+ * unless the process-wide tuning cache already holds the case's shape; a
+ * nonzero block_v / tile_cells fixes them for every case instead.
+ * options.flags bit 3 runs the step eagerly (no graph); the other bits act
+ * as for ugks_create.  options.stream as for ugks_create.
+ */
+typedef struct ugks_batch ugks_batch;
+
+typedef struct {
+  const ugks_mesh* mesh;
+  const ugks_velocity* vel;
+  const ugks_gas* gas;
+  const ugks_bc* bcs;
+  int32_t n_bc;
+  const double* W0;          /* [n_cells*(dim+2)] */
+} ugks_case;
+
+typedef struct {
+  int32_t n_cases;
+  int32_t dim;
+  int32_t precision;
+  int32_t threads;           /* lanes per work-group of the batched sweep */
+  int64_t work_items;        /* (case, cell, velocity block) items of one sweep */
+  int64_t grid;              /* persistent work-groups of the sweep */
+  int32_t graph;             /* 1: steps replay a captured HIP graph */
+  int32_t tuned;             /* 1: schedule from the autotuner (timed or cached) */
+  int64_t tune_timings;      /* sweep launches the autotuner timed at create (0 on a cache hit) */
+  int64_t steps_done;
+} ugks_batch_info_t;
+
+/*
+ * ugks_batch_create - cases[0..n_cases-1] are copied; the caller keeps its
+ * arrays.  Errors: UGKS_EINVAL (any case invalid, mixed dim, n_cases < 1),
+ * UGKS_EUNSUPPORTED (a case does not qualify for the fused sweep),
+ * UGKS_ENOMEM, UGKS_EHIP.  The failing case is named in ugks_batch_last_error(NULL).
+ */
+int ugks_batch_create(const ugks_case* cases, int32_t n_cases, const ugks_options* opt,
+                      ugks_batch** out);
+
+/*
+ * ugks_batch_step - advance every case n_steps >= 0 steps.  residual_out is
+ * NULL or 2*n_cases doubles: per case the two residuals of ugks_step.  On a
+ * non-positive density or temperature in any case: UGKS_ENUMERIC, with the
+ * failing case named in ugks_batch_last_error.
+ */
+int ugks_batch_step(ugks_batch* batch, int32_t n_steps, double* residual_out);
+
+/* Per-case access, as ugks_moments / ugks_get_state / ugks_info for case i. */
+int ugks_batch_moments(ugks_batch* batch, int32_t i, int32_t which, double* out, int32_t on_device);
+int ugks_batch_get_state(ugks_batch* batch, int32_t i, double* W, double* h, double* b);
+int ugks_batch_case_info(ugks_batch* batch, int32_t i, ugks_info_t* out);
+int ugks_batch_info(const ugks_batch* batch, ugks_batch_info_t* out);
+void ugks_batch_destroy(ugks_batch* batch);
+const char* ugks_batch_last_error(const ugks_batch* batch);
+
+/*
+ * Process-wide autotuner cache (thread-safe).  Entries are keyed by the
+ * case shape (dim, precision, lanes, cells, velocities) and by the batch's
+ * list of shapes.  save writes a plain text file; load merges a file written
+ * by save (UGKS_EINVAL on a malformed file, nothing merged); clear empties it.
+ */
+int ugks_autotune_save(const char* path);
+int ugks_autotune_load(const char* path);
+void ugks_autotune_clear(void);
 
 /* Reason for the last failure on ctx (NULL: the last failed ugks_create of this thread). */
 const char* ugks_last_error(const ugks_ctx* ctx);

@@ -13,7 +13,11 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <fstream>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <sstream>
 
 using namespace ugks;
 
@@ -449,7 +453,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   if (c->fused) {
     // velocity block: B_v velocities = B_v/2 mirror pairs per work item
     const int64_t npairs = (nv + 1) / 2;
-    int64_t cp = Bv ? Bv / 2 : 1024;
+    int64_t cp = Bv ? Bv / 2 : 2048;
     cp = std::max<int64_t>(64, std::min<int64_t>(cp, npairs));
     c->sched.nf = nf;
     c->sched.chunk_pairs = cp;
@@ -645,6 +649,433 @@ void enqueue_step(ugks_ctx* c) {
 }
 
 }  // namespace
+
+// ===========================================================================
+// Batched form
+// ===========================================================================
+struct ugks_batch_impl;
+
+namespace {
+
+// Autotuner cache: case shape -> (velocity-block pairs, tile cells, time),
+// batch shape list -> lanes per work-group.
+struct TuneCase {
+  int64_t chunk_pairs = 0, tile = 0;
+  double us = 0.0;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneCase> g_tune_case;
+std::map<std::string, int> g_tune_batch;
+
+std::string case_key(int D, int prec, int threads, int64_t nc, int64_t nv) {
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "%d %d %d %lld %lld", D, prec, threads, (long long)nc, (long long)nv);
+  return buf;
+}
+
+}  // namespace
+
+struct ugks_batch {
+  std::vector<ugks_ctx*> cases;
+  int D = 0, prec = 64, flags = 0, nr = 1;
+  int threads = 256;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<void*> allocations;
+  CaseDev* cases_dev[2] = {nullptr, nullptr};  // even / odd step: q and qn swapped
+  int64_t* offs = nullptr;                    // cell, face, wall, tab offsets, [4][n+1]
+  int32_t* items = nullptr;
+  int64_t nitems = 0, grid = 0;
+  int64_t ncell = 0, nface = 0, nwall = 0, ntab = 0;
+  int32_t* flags_dev = nullptr;  // [4*n]
+  double* resid_dev = nullptr;   // [8*n]
+  int parity = 0;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  bool use_graph = true, tuned = false;
+  int64_t tune_timings = 0, steps_done = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_create_error;
+
+template <typename T>
+T* balloc(ugks_batch* b, size_t n) {
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+  b->allocations.push_back(p);
+  return static_cast<T*>(p);
+}
+
+BatchDev batch_dev(const ugks_batch* b, int par) {
+  BatchDev bd{};
+  bd.cases = b->cases_dev[par];
+  bd.n = (int32_t)b->cases.size();
+  const int64_t n1 = bd.n + 1;
+  bd.cell_off = b->offs;
+  bd.face_off = b->offs + n1;
+  bd.wall_off = b->offs + 2 * n1;
+  bd.tab_off = b->offs + 3 * n1;
+  bd.items = b->items;
+  bd.nitems = b->nitems;
+  return bd;
+}
+
+// Device case table of one parity from the sub-contexts' buffers.
+void upload_cases(ugks_batch* b) {
+  const size_t n = b->cases.size();
+  for (int par = 0; par < 2; ++par) {
+    std::vector<CaseDev> h(n);
+    for (size_t i = 0; i < n; ++i) {
+      const ugks_ctx* c = b->cases[i];
+      CaseDev& d = h[i];
+      d.m = c->mesh;
+      d.v = c->vel;
+      d.g = c->gas;
+      d.fm = c->fmesh;
+      d.sc = c->sched;
+      d.bcs = c->bcs;
+      d.B = c->buf;
+      if (par) std::swap(d.B.q, d.B.qn);
+    }
+    if (!b->cases_dev[par]) b->cases_dev[par] = balloc<CaseDev>(b, n);
+    HIP_TRY(hipMemcpy(b->cases_dev[par], h.data(), n * sizeof(CaseDev), hipMemcpyHostToDevice));
+  }
+}
+
+// Work list of the batched sweep.  Tiles of each case go to the XCD queue
+// with the least work so far; queue x holds the items of its tiles, velocity
+// block by velocity block; queues are padded to one length and interleaved
+// so that item w lands on a work-group with index = w (mod 8), i.e. on XCD w mod 8.
+std::vector<int32_t> work_list(const ugks_batch* b, const std::vector<int64_t>& only) {
+  std::vector<std::vector<int32_t>> q(8);
+  std::vector<double> load(8, 0.0);
+  auto add_case = [&](int64_t ci) {
+    const ugks_ctx* c = b->cases[ci];
+    const SweepSched& sc = c->sched;
+    const int64_t ntile = (c->nc + sc.tile - 1) / sc.tile;
+    for (int64_t t = 0; t < ntile; ++t) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      const int64_t c0 = t * sc.tile, c1 = std::min(c->nc, c0 + sc.tile);
+      for (int64_t ch = 0; ch < sc.nchunk; ++ch)
+        for (int64_t ic = c0; ic < c1; ++ic) {
+          q[x].push_back((int32_t)ci);
+          q[x].push_back((int32_t)ic);
+          q[x].push_back((int32_t)ch);
+          q[x].push_back(0);
+        }
+      load[x] += (double)(c1 - c0) * (double)((c->nv + 1) / 2);
+    }
+  };
+  if (only.empty())
+    for (int64_t ci = 0; ci < (int64_t)b->cases.size(); ++ci) add_case(ci);
+  else
+    for (int64_t ci : only) add_case(ci);
+  size_t len = 0;
+  for (auto& v : q) len = std::max(len, v.size() / 4);
+  std::vector<int32_t> out(8 * len * 4, 0);
+  for (size_t j = 0; j < len; ++j)
+    for (int x = 0; x < 8; ++x) {
+      int32_t* o = &out[(8 * j + x) * 4];
+      if (j < q[x].size() / 4) std::memcpy(o, &q[x][4 * j], 4 * sizeof(int32_t));
+      else o[0] = -1;
+    }
+  return out;
+}
+
+int64_t sweep_grid(const ugks_batch* b, int64_t nitems) {
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int per = std::max(1, sweep_b_blocks_per_cu(b->D, b->prec, b->threads));
+  int64_t g = (int64_t)ncu * per;
+  g = std::min<int64_t>(g, nitems);
+  g = std::max<int64_t>(8, g / 8 * 8);
+  return g;
+}
+
+void set_items(ugks_batch* b, const std::vector<int32_t>& items, int32_t** dst, int64_t* cap) {
+  const int64_t n = (int64_t)items.size() / 4;
+  if (n > *cap) {
+    *dst = balloc<int32_t>(b, items.size());
+    *cap = n;
+  }
+  HIP_TRY(hipMemcpy(*dst, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+}
+
+// The phases of one step for every case of the batch.
+void enqueue_batch_step(ugks_batch* b, int par) {
+  const int D = b->D, P = b->prec;
+  const BatchDev bd = batch_dev(b, par);
+  hipStream_t s = b->stream;
+  // 1 primitives of W^n and the first-stage cell data
+  HIP_TRY(launch_cell_prep_b(D, bd, b->ncell, 0, s));
+  // 4 macroscopic reconstruction; 6.1-6.6 interface equilibrium
+  HIP_TRY(launch_gradW_b(D, bd, b->ncell, s));
+  HIP_TRY(launch_face_eq_b(D, bd, b->nface, s));
+  // 7 wall densities
+  HIP_TRY(launch_wall_rho_b(D, P, bd, b->nwall, s));
+  // Maxwellian axis tables
+  HIP_TRY(launch_tables_b(D, bd, b->ntab, s));
+  // 5, 6.7-6.8, 9: the fused velocity sweep, one persistent launch
+  HIP_TRY(launch_sweep_b(D, P, bd, b->grid, b->threads, s));
+  // 8 conservative update; 10 new equilibrium
+  HIP_TRY(launch_apply_dW_b(D, bd, b->ncell, s));
+  HIP_TRY(launch_cell_prep_b(D, bd, b->ncell, 1, s));
+  // 11 second stage with the heat flux of h^{n+1}
+  HIP_TRY(launch_stage2_q_b(D, P, bd, b->ncell, s));
+  // 12 residuals, commit W^{n+1}
+  if (!(b->flags & 1)) HIP_TRY(launch_residual_b(bd, s));
+  HIP_TRY(launch_commit_W_b(D, bd, b->ncell, s));
+}
+
+// Average duration of `reps` launches of the batched sweep over `items`.
+double time_sweep(ugks_batch* b, const std::vector<int32_t>& items, int32_t** buf, int64_t* cap,
+                  int reps) {
+  upload_cases(b);  // the kernels read each case's schedule from the case table
+  set_items(b, items, buf, cap);
+  BatchDev bd = batch_dev(b, 0);
+  bd.items = *buf;
+  bd.nitems = (int64_t)items.size() / 4;
+  const int64_t g = sweep_grid(b, bd.nitems);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(launch_sweep_b(b->D, b->prec, bd, g, b->threads, b->stream));  // warm-up
+  HIP_TRY(hipEventRecord(e0, b->stream));
+  for (int r = 0; r < reps; ++r) HIP_TRY(launch_sweep_b(b->D, b->prec, bd, g, b->threads, b->stream));
+  HIP_TRY(hipEventRecord(e1, b->stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->tune_timings += reps + 1;
+  return 1e3 * ms / reps;
+}
+
+void apply_sched(ugks_ctx* c, int64_t chunk_pairs, int64_t tile) {
+  const int64_t npairs = (c->nv + 1) / 2;
+  // at least 64 pairs (or all): the per-block moment buffer was sized for that
+  chunk_pairs = std::max(std::min<int64_t>(64, npairs), std::min(chunk_pairs, npairs));
+  c->sched.chunk_pairs = chunk_pairs;
+  c->sched.nchunk = (npairs + chunk_pairs - 1) / chunk_pairs;
+  c->sched.tile = std::max<int64_t>(1, std::min(tile, c->nc));
+  c->Bv = (int)(2 * chunk_pairs);
+}
+
+// Autotuner: for each lane count, each case's velocity block and tile by
+// timing that case's sweep alone, then the lane count by timing the whole
+// batch's sweep; shapes found in the cache are not timed again.
+void autotune(ugks_batch* b) {
+  const int64_t n = (int64_t)b->cases.size();
+  int32_t* buf = nullptr;
+  int64_t cap = 0;
+  std::string bkey = "batch";
+  for (ugks_ctx* c : b->cases) bkey += " " + case_key(b->D, b->prec, 0, c->nc, c->nv);
+  int best_threads = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_batch.find(bkey);
+    if (it != g_tune_batch.end()) best_threads = it->second;
+  }
+  const int cand_threads[3] = {64, 128, 256};
+  double best_t = INFINITY;
+  for (int th : cand_threads) {
+    if (best_threads && th != best_threads) continue;
+    b->threads = th;
+    for (int64_t i = 0; i < n; ++i) {
+      ugks_ctx* c = b->cases[i];
+      const std::string key = case_key(b->D, b->prec, th, c->nc, c->nv);
+      TuneCase tc;
+      bool hit = false;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_case.find(key);
+        if (it != g_tune_case.end()) {
+          tc = it->second;
+          hit = true;
+        }
+      }
+      if (!hit) {
+        const int64_t npairs = (c->nv + 1) / 2;
+        tc.us = INFINITY;
+        int64_t last_cp = -1;
+        for (int mult : {1, 2, 4, 8, 1 << 20}) {
+          const int64_t cp = std::min<int64_t>(npairs, (int64_t)mult * th);
+          if (cp == last_cp) continue;
+          last_cp = cp;
+          for (int64_t tile : {16, 64, 256}) {
+            if (tile > 16 && tile / 4 >= c->nc) continue;
+            apply_sched(c, cp, tile);
+            const double us = time_sweep(b, work_list(b, {i}), &buf, &cap, 3);
+            if (us < tc.us) tc = {c->sched.chunk_pairs, c->sched.tile, us};
+          }
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_case[key] = tc;
+      }
+      apply_sched(c, tc.chunk_pairs, tc.tile);
+    }
+    if (best_threads) break;  // cached lane count: schedules applied above
+    const double t = time_sweep(b, work_list(b, {}), &buf, &cap, 3);
+    if (t < best_t) {
+      best_t = t;
+      best_threads = th;
+    }
+  }
+  if (b->threads != best_threads) {
+    // re-apply the winning lane count's schedules (all cached by now)
+    b->threads = best_threads;
+    for (int64_t i = 0; i < n; ++i) {
+      ugks_ctx* c = b->cases[i];
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      const TuneCase& tc = g_tune_case[case_key(b->D, b->prec, best_threads, c->nc, c->nv)];
+      apply_sched(c, tc.chunk_pairs, tc.tile);
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_batch[bkey] = best_threads;
+}
+
+void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_options* opt) {
+  fail_if(!cases || n < 1, "need at least one case");
+  const int prec = opt && opt->precision ? opt->precision : UGKS_FP64;
+  fail_if(prec != UGKS_FP64 && prec != UGKS_FP32, "precision must be 64 or 32");
+  const int fixed_bv = opt ? opt->block_v : 0, fixed_tile = opt ? opt->tile_cells : 0;
+  fail_if(fixed_bv < 0 || fixed_bv % WAVE != 0, "block_v must be 0 or a positive multiple of 64");
+  fail_if(fixed_tile < 0, "tile_cells must be >= 0");
+  b->prec = prec;
+  b->flags = opt ? opt->flags : 0;
+  b->use_graph = !(b->flags & 8);
+  if (opt && opt->stream) {
+    b->stream = (hipStream_t)opt->stream;
+  } else {
+    HIP_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    b->own_stream = true;
+  }
+  b->flags_dev = balloc<int32_t>(b, 4 * (size_t)n);
+  b->resid_dev = balloc<double>(b, 8 * (size_t)n);
+  HIP_TRY(hipMemset(b->flags_dev, 0, 4 * (size_t)n * sizeof(int32_t)));
+  HIP_TRY(hipMemset(b->resid_dev, 0, 8 * (size_t)n * sizeof(double)));
+  for (int32_t i = 0; i < n; ++i) {
+    const ugks_case& k = cases[i];
+    ugks_options o{};
+    o.precision = prec;
+    o.block_v = 128;  // smallest velocity block: sizes the per-block moment buffer
+    o.tile_cells = 0;
+    o.flags = b->flags & ~(2 | 8);
+    o.stream = b->stream;
+    std::unique_ptr<ugks_ctx> c(new ugks_ctx());
+    try {
+      build(c.get(), k.mesh, k.vel, k.gas, k.bcs, k.n_bc, k.W0, &o);
+    } catch (InvalidArg& e) {
+      ugks_destroy(c.release());
+      throw InvalidArg{"case " + std::to_string(i) + ": " + e.msg};
+    } catch (std::pair<int, std::string>& e) {
+      ugks_destroy(c.release());
+      throw std::pair<int, std::string>(e.first, "case " + std::to_string(i) + ": " + e.second);
+    } catch (...) {
+      ugks_destroy(c.release());
+      throw;
+    }
+    ugks_ctx* cc = c.release();
+    b->cases.push_back(cc);
+    if (i == 0) {
+      b->D = cc->D;
+      b->nr = cc->nr;
+    }
+    fail_if(cc->D != b->D, "case " + std::to_string(i) + ": every case needs the same dimension");
+    if (!cc->fused)
+      throw std::pair<int, std::string>(
+          UGKS_EUNSUPPORTED, "case " + std::to_string(i) +
+                                 ": the batched form needs the fused sweep (symmetric tensor "
+                                 "velocity set, interior/periodic/wall faces, <= 4 faces per cell)");
+    // flags and residuals of all cases side by side: one copy reads them all
+    cc->buf.flag = b->flags_dev + 4 * i;
+    cc->buf.resid = b->resid_dev + 8 * i;
+    // heat flux of the initial state
+    HIP_TRY(launch_prims(cc->D, cc->mesh, cc->gas, cc->buf.W, cc->buf.prim, cc->buf.flag, 1, b->stream));
+    HIP_TRY(launch_heatflux(cc->D, cc->prec, cc->mesh, cc->vel, cc->buf.h, cc->buf.b, cc->buf.prim,
+                            cc->buf.q, cc->buf.flag, b->stream));
+    cc->q_valid = true;
+  }
+  // case-offset tables
+  const int64_t n1 = n + 1;
+  std::vector<int64_t> off(4 * n1, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    const ugks_ctx* c = b->cases[i];
+    off[i + 1] = off[i] + c->nc;
+    off[n1 + i + 1] = off[n1 + i] + c->nf;
+    off[2 * n1 + i + 1] = off[2 * n1 + i] + c->mesh.nwall;
+    off[3 * n1 + i + 1] = off[3 * n1 + i] + (c->nf + c->nc) * (int64_t)c->D * c->fmesh.na;
+  }
+  b->ncell = off[n];
+  b->nface = off[n1 + n];
+  b->nwall = off[2 * n1 + n];
+  b->ntab = off[3 * n1 + n];
+  b->offs = balloc<int64_t>(b, off.size());
+  HIP_TRY(hipMemcpy(b->offs, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  upload_cases(b);
+  // the step's phases up to the sweep once, so the autotuner times the
+  // sweep on this batch's own records
+  {
+    const BatchDev bd = batch_dev(b, 0);
+    HIP_TRY(launch_cell_prep_b(b->D, bd, b->ncell, 0, b->stream));
+    HIP_TRY(launch_gradW_b(b->D, bd, b->ncell, b->stream));
+    HIP_TRY(launch_face_eq_b(b->D, bd, b->nface, b->stream));
+    HIP_TRY(launch_wall_rho_b(b->D, b->prec, bd, b->nwall, b->stream));
+    HIP_TRY(launch_tables_b(b->D, bd, b->ntab, b->stream));
+  }
+  if (fixed_bv || fixed_tile) {
+    b->threads = 256;
+    for (ugks_ctx* c : b->cases)
+      apply_sched(c, fixed_bv ? fixed_bv / 2 : 2048, fixed_tile ? fixed_tile : 256);
+  } else {
+    autotune(b);
+    b->tuned = true;
+  }
+  upload_cases(b);
+  const std::vector<int32_t> items = work_list(b, {});
+  int64_t cap = 0;
+  set_items(b, items, &b->items, &cap);
+  b->nitems = (int64_t)items.size() / 4;
+  b->grid = sweep_grid(b, b->nitems);
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int32_t f0 = 0;
+  std::vector<int32_t> fl(4 * (size_t)n);
+  HIP_TRY(hipMemcpy(fl.data(), b->flags_dev, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < n; ++i) f0 |= fl[4 * i];
+  fail_if(f0 != 0, "non-positive density or temperature in an initial state");
+  if (b->use_graph) {
+    for (int par = 0; par < 2; ++par) {
+      HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_batch_step(b, par);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(b->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIP_TRY(hipStreamEndCapture(b->stream, &b->graph[par]));
+      HIP_TRY(hipGraphInstantiate(&b->exec[par], b->graph[par], nullptr, nullptr, 0));
+    }
+  }
+}
+
+int batch_err(ugks_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  else g_batch_create_error = msg;
+  return code;
+}
+
+}  // namespace
+
 
 extern "C" {
 
@@ -911,6 +1342,172 @@ void ugks_destroy(ugks_ctx* c) {
 
 const char* ugks_last_error(const ugks_ctx* c) {
   return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+
+int ugks_batch_create(const ugks_case* cases, int32_t n_cases, const ugks_options* opt,
+                      ugks_batch** out) {
+  if (!out) return batch_err(nullptr, UGKS_EINVAL, "out is NULL");
+  std::unique_ptr<ugks_batch> b(new ugks_batch());
+  try {
+    batch_build(b.get(), cases, n_cases, opt);
+  } catch (const InvalidArg& e) {
+    ugks_batch_destroy(b.release());
+    return batch_err(nullptr, UGKS_EINVAL, e.msg);
+  } catch (const std::pair<int, std::string>& e) {
+    ugks_batch_destroy(b.release());
+    return batch_err(nullptr, e.first, e.second);
+  } catch (const HipFail& e) {
+    ugks_batch_destroy(b.release());
+    int code = (e.e == hipErrorOutOfMemory) ? UGKS_ENOMEM : UGKS_EHIP;
+    return batch_err(nullptr, code, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  *out = b.release();
+  return UGKS_OK;
+}
+
+int ugks_batch_step(ugks_batch* b, int32_t n_steps, double* residual_out) {
+  if (!b) return batch_err(nullptr, UGKS_EINVAL, "batch is NULL");
+  if (n_steps < 0) return batch_err(b, UGKS_EINVAL, "n_steps < 0");
+  const size_t n = b->cases.size();
+  try {
+    for (int32_t s = 0; s < n_steps; ++s) {
+      if (b->use_graph) HIP_TRY(hipGraphLaunch(b->exec[b->parity], b->stream));
+      else enqueue_batch_step(b, b->parity);
+      b->parity ^= 1;
+    }
+    std::vector<int32_t> fl(4 * n);
+    std::vector<double> rs(8 * n);
+    HIP_TRY(hipMemcpyAsync(fl.data(), b->flags_dev, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipMemcpyAsync(rs.data(), b->resid_dev, rs.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < n; ++i)
+      if (fl[4 * i]) {
+        return batch_err(b, UGKS_ENUMERIC, "case " + std::to_string(i) +
+                                               ": non-positive density or temperature");
+      }
+    b->steps_done += n_steps;
+    for (ugks_ctx* c : b->cases) c->steps_done += n_steps;
+    if (residual_out)
+      for (size_t i = 0; i < n; ++i) {
+        residual_out[2 * i] = rs[8 * i];
+        residual_out[2 * i + 1] = rs[8 * i + 1];
+      }
+  } catch (const HipFail& e) {
+    return batch_err(b, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return UGKS_OK;
+}
+
+int ugks_batch_moments(ugks_batch* b, int32_t i, int32_t which, double* out, int32_t on_device) {
+  if (!b) return batch_err(nullptr, UGKS_EINVAL, "batch is NULL");
+  if (i < 0 || i >= (int32_t)b->cases.size()) return batch_err(b, UGKS_EINVAL, "case index out of range");
+  ugks_ctx* c = b->cases[i];
+  // the batch alternates q and qn by step parity; the case's own view is the
+  // even one, so after an odd number of steps its scratch qn is the current q
+  if (b->parity) std::swap(c->buf.q, c->buf.qn);
+  int rc = ugks_moments(c, which, out, on_device);
+  if (b->parity) std::swap(c->buf.q, c->buf.qn);
+  if (rc) batch_err(b, rc, c->err);
+  return rc;
+}
+
+int ugks_batch_get_state(ugks_batch* b, int32_t i, double* W, double* h, double* bb) {
+  if (!b) return batch_err(nullptr, UGKS_EINVAL, "batch is NULL");
+  if (i < 0 || i >= (int32_t)b->cases.size()) return batch_err(b, UGKS_EINVAL, "case index out of range");
+  int rc = ugks_get_state(b->cases[i], W, h, bb);
+  if (rc) batch_err(b, rc, b->cases[i]->err);
+  return rc;
+}
+
+int ugks_batch_case_info(ugks_batch* b, int32_t i, ugks_info_t* out) {
+  if (!b || !out) return UGKS_EINVAL;
+  if (i < 0 || i >= (int32_t)b->cases.size()) return batch_err(b, UGKS_EINVAL, "case index out of range");
+  return ugks_info(b->cases[i], out);
+}
+
+int ugks_batch_info(const ugks_batch* b, ugks_batch_info_t* out) {
+  if (!b || !out) return UGKS_EINVAL;
+  out->n_cases = (int32_t)b->cases.size();
+  out->dim = b->D;
+  out->precision = b->prec;
+  out->threads = b->threads;
+  out->work_items = b->nitems;
+  out->grid = b->grid;
+  out->graph = b->use_graph ? 1 : 0;
+  out->tuned = b->tuned ? 1 : 0;
+  out->tune_timings = b->tune_timings;
+  out->steps_done = b->steps_done;
+  return UGKS_OK;
+}
+
+void ugks_batch_destroy(ugks_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (int par = 0; par < 2; ++par) {
+    if (b->exec[par]) (void)hipGraphExecDestroy(b->exec[par]);
+    if (b->graph[par]) (void)hipGraphDestroy(b->graph[par]);
+  }
+  for (ugks_ctx* c : b->cases) ugks_destroy(c);
+  for (void* p : b->allocations) (void)hipFree(p);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+const char* ugks_batch_last_error(const ugks_batch* b) {
+  return b ? b->err.c_str() : g_batch_create_error.c_str();
+}
+
+int ugks_autotune_save(const char* path) {
+  if (!path) return UGKS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::ofstream f(path);
+  if (!f) return UGKS_EINVAL;
+  f << "ugks-autotune 1\n";
+  for (auto& e : g_tune_case)
+    f << "case " << e.first << " : " << e.second.chunk_pairs << " " << e.second.tile << " "
+      << e.second.us << "\n";
+  for (auto& e : g_tune_batch) f << e.first << " : " << e.second << "\n";
+  return f.good() ? UGKS_OK : UGKS_EINVAL;
+}
+
+int ugks_autotune_load(const char* path) {
+  if (!path) return UGKS_EINVAL;
+  std::ifstream f(path);
+  if (!f) return UGKS_EINVAL;
+  std::string line;
+  if (!std::getline(f, line) || line != "ugks-autotune 1") return UGKS_EINVAL;
+  std::map<std::string, TuneCase> cs;
+  std::map<std::string, int> bs;
+  while (std::getline(f, line)) {
+    if (line.empty()) continue;
+    const size_t sep = line.find(" : ");
+    if (sep == std::string::npos) return UGKS_EINVAL;
+    const std::string key = line.substr(0, sep);
+    std::istringstream val(line.substr(sep + 3));
+    if (key.rfind("case ", 0) == 0) {
+      TuneCase t;
+      if (!(val >> t.chunk_pairs >> t.tile >> t.us) || t.chunk_pairs < 1 || t.tile < 1)
+        return UGKS_EINVAL;
+      cs[key.substr(5)] = t;
+    } else if (key.rfind("batch", 0) == 0) {
+      int th = 0;
+      if (!(val >> th) || (th != 64 && th != 128 && th != 256)) return UGKS_EINVAL;
+      bs[key] = th;
+    } else {
+      return UGKS_EINVAL;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : cs) g_tune_case[e.first] = e.second;
+  for (auto& e : bs) g_tune_batch[e.first] = e.second;
+  return UGKS_OK;
+}
+
+void ugks_autotune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_case.clear();
+  g_tune_batch.clear();
 }
 
 }  // extern "C"

@@ -140,6 +140,31 @@ struct StepBuffers {
   int32_t* flag;   // numeric error flag
 };
 
+// One case of a batch as the batched kernels see it (an array of these in
+// device memory; the pointers are the case's own buffers).
+struct CaseDev {
+  DevMesh m;
+  DevVel v;
+  GasP g;
+  FusedMesh fm;
+  SweepSched sc;
+  const DevBC* bcs;
+  StepBuffers B;
+};
+
+// A batch of cases run by one launch per phase: flattened element ranges
+// with case-offset tables (prefix sums) and the sweep's work list.
+struct BatchDev {
+  const CaseDev* cases;     // [n]
+  int32_t n;
+  const int64_t* cell_off;  // [n+1] cells
+  const int64_t* face_off;  // [n+1] faces
+  const int64_t* wall_off;  // [n+1] wall faces
+  const int64_t* tab_off;   // [n+1] Maxwellian axis-table entries, (nf+nc)*D*na
+  const int32_t* items;     // [4*nitems] sweep work items: case (-1 = padding), cell, block, 0
+  int64_t nitems;
+};
+
 hipError_t launch_prims(int D, const DevMesh& m, const GasP& g, const double* W, double* prim,
                         int32_t* flag, int checkflag, hipStream_t s);
 hipError_t launch_heatflux(int D, int prec, const DevMesh& m, const DevVel& v, const void* h,
@@ -198,6 +223,21 @@ hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v
 hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
                                   const GasP& g, const void* h, double* frec, const int32_t* flag,
                                   hipStream_t s);
+
+// batched forms (one launch per phase over every case of a batch)
+hipError_t launch_cell_prep_b(int D, const BatchDev& bd, int64_t ncell, int next, hipStream_t s);
+hipError_t launch_gradW_b(int D, const BatchDev& bd, int64_t ncell, hipStream_t s);
+hipError_t launch_face_eq_b(int D, const BatchDev& bd, int64_t nface, hipStream_t s);
+hipError_t launch_wall_rho_b(int D, int prec, const BatchDev& bd, int64_t nwall, hipStream_t s);
+hipError_t launch_tables_b(int D, const BatchDev& bd, int64_t ntab, hipStream_t s);
+hipError_t launch_sweep_b(int D, int prec, const BatchDev& bd, int64_t grid, int threads,
+                          hipStream_t s);
+// resident work-groups of the batched sweep per CU at `threads` lanes
+int sweep_b_blocks_per_cu(int D, int prec, int threads);
+hipError_t launch_apply_dW_b(int D, const BatchDev& bd, int64_t ncell, hipStream_t s);
+hipError_t launch_stage2_q_b(int D, int prec, const BatchDev& bd, int64_t ncell, hipStream_t s);
+hipError_t launch_residual_b(const BatchDev& bd, hipStream_t s);
+hipError_t launch_commit_W_b(int D, const BatchDev& bd, int64_t ncell, hipStream_t s);
 
 }  // namespace ugks
 

@@ -56,10 +56,10 @@ __global__ __launch_bounds__(TPB) void k_heatflux(DevVel v, const T* __restrict_
 
 // Macroscopic least-squares gradients of W (step 4).
 template <int D>
-__global__ void k_gradW(DevMesh m, const DevBC* __restrict__ bcs, GasP g, const double* __restrict__ W,
-                        double* __restrict__ gW, const int32_t* flag) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= m.nc || *flag) return;
+__device__ __forceinline__ void gradW_at(int64_t i, const DevMesh& m, const DevBC* __restrict__ bcs,
+                                         const GasP& g, const double* __restrict__ W,
+                                         double* __restrict__ gW, const int32_t* flag) {
+  if (*flag) return;
   const int nfc = m.nfc[i];
   const double* Wi = &W[i * (D + 2)];
   double acc[3][5];
@@ -85,14 +85,22 @@ __global__ void k_gradW(DevMesh m, const DevBC* __restrict__ bcs, GasP g, const 
     for (int v = 0; v < 5; ++v) gW[(i * 3 + d) * 5 + v] = (d < D && v < D + 2) ? acc[d][v] : 0.0;
 }
 
+template <int D>
+__global__ void k_gradW(DevMesh m, const DevBC* __restrict__ bcs, GasP g, const double* __restrict__ W,
+                        double* __restrict__ gW, const int32_t* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < m.nc) gradW_at<D>(i, m, bcs, g, W, gW, flag);
+}
+
 // Interface equilibrium data of every face (steps 6.1-6.6), wall Maxwellian
 // data of wall faces.
 template <int D>
-__global__ void k_face_eq(DevMesh m, const DevBC* __restrict__ bcs, GasP g,
-                          const double* __restrict__ W, const double* __restrict__ gW,
-                          const double* __restrict__ q, double* __restrict__ frec, int32_t* flag) {
-  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (f >= m.nf || *flag) return;
+__device__ __forceinline__ void face_eq_at(int64_t f, const DevMesh& m, const DevBC* __restrict__ bcs,
+                                           const GasP& g, const double* __restrict__ W,
+                                           const double* __restrict__ gW,
+                                           const double* __restrict__ q, double* __restrict__ frec,
+                                           int32_t* flag) {
+  if (*flag) return;
   double* R = &frec[f * FREC];
   const int kind = m.fbc[f];
   const int L = m.fL[f];
@@ -256,6 +264,14 @@ __global__ void k_face_eq(DevMesh m, const DevBC* __restrict__ bcs, GasP g,
       R[FR_PB + x] = x < Cb::N ? PB[x] : 0.0;
     }
   }
+}
+
+template <int D>
+__global__ void k_face_eq(DevMesh m, const DevBC* __restrict__ bcs, GasP g,
+                          const double* __restrict__ W, const double* __restrict__ gW,
+                          const double* __restrict__ q, double* __restrict__ frec, int32_t* flag) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f < m.nf) face_eq_at<D>(f, m, bcs, g, W, gW, q, frec, flag);
 }
 
 // Microscopic gradients of h (and b) for every (cell, velocity) (step 5).
@@ -591,9 +607,9 @@ __global__ __launch_bounds__(TPB) void k_stage2(DevVel v, GasP g, const double* 
 }
 
 // Residual of the density: one block, fixed summation order.
-__global__ __launch_bounds__(1024) void k_residual(int64_t nc, const double* __restrict__ cellred,
-                                                   double* __restrict__ resid, const int32_t* flag) {
-  __shared__ double lds[3 * 16];
+__device__ __forceinline__ void residual_of(int64_t nc, const double* __restrict__ cellred,
+                                            double* __restrict__ resid, const int32_t* flag,
+                                            double* lds) {
   if (*flag) return;
   double acc[3] = {0, 0, 0};
   for (int64_t i = threadIdx.x; i < nc; i += blockDim.x)
@@ -605,6 +621,12 @@ __global__ __launch_bounds__(1024) void k_residual(int64_t nc, const double* __r
     resid[0] = resid[3] > 0.0 ? nrm / resid[3] : 0.0;
     resid[1] = nrm / sqrt(acc[2] / acc[1]);
   }
+}
+
+__global__ __launch_bounds__(1024) void k_residual(int64_t nc, const double* __restrict__ cellred,
+                                                   double* __restrict__ resid, const int32_t* flag) {
+  __shared__ double lds[3 * 16];
+  residual_of(nc, cellred, resid, flag, lds);
 }
 
 template <int D>
@@ -675,6 +697,53 @@ __global__ __launch_bounds__(TPB) void k_dt_cells(DevMesh m, DevVel v, double* _
 }
 
 inline unsigned blocks_for(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
+
+// ---- batched forms: one launch covers every case of a batch ---------------
+__device__ __forceinline__ int case_of(const int64_t* __restrict__ off, int n, int64_t t) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int D>
+__global__ void k_gradW_b(BatchDev bd) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= bd.cell_off[bd.n]) return;
+  const int c = case_of(bd.cell_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  gradW_at<D>(t - bd.cell_off[c], C.m, C.bcs, C.g, C.B.W, C.B.gW, C.B.flag);
+}
+
+template <int D>
+__global__ void k_face_eq_b(BatchDev bd) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= bd.face_off[bd.n]) return;
+  const int c = case_of(bd.face_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  face_eq_at<D>(t - bd.face_off[c], C.m, C.bcs, C.g, C.B.W, C.B.gW, C.B.q, C.B.frec, C.B.flag);
+}
+
+// one block per case
+__global__ __launch_bounds__(1024) void k_residual_b(BatchDev bd) {
+  __shared__ double lds[3 * 16];
+  const CaseDev& C = bd.cases[blockIdx.x];
+  residual_of(C.m.nc, C.B.cellred, C.B.resid, C.B.flag, lds);
+}
+
+template <int D>
+__global__ void k_commit_W_b(BatchDev bd) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= bd.cell_off[bd.n]) return;
+  const int c = case_of(bd.cell_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  if (*C.B.flag) return;
+  const int64_t i = t - bd.cell_off[c];
+  for (int x = 0; x < D + 2; ++x) C.B.W[i * (D + 2) + x] = C.B.Wn[i * (D + 2) + x];
+}
 
 }  // namespace
 
@@ -807,6 +876,36 @@ hipError_t launch_wall_rho(int D, int prec, const DevMesh& m, const DevVel& v, c
   if (m.nwall == 0) return hipSuccess;
   UGKS_DISPATCH_DT(D, prec, k_wall_rho<DD, TT><<<(unsigned)m.nwall, TPB, 0, s>>>(
       m, v, g, (const TT*)h, gh, frec, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_gradW_b(int D, const BatchDev& bd, int64_t ncell, hipStream_t s) {
+  if (ncell == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((ncell + 127) / 128);
+  if (D == 2) k_gradW_b<2><<<grid, 128, 0, s>>>(bd);
+  else k_gradW_b<3><<<grid, 128, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_eq_b(int D, const BatchDev& bd, int64_t nface, hipStream_t s) {
+  if (nface == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((nface + 63) / 64);
+  if (D == 2) k_face_eq_b<2><<<grid, 64, 0, s>>>(bd);
+  else k_face_eq_b<3><<<grid, 64, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_b(const BatchDev& bd, hipStream_t s) {
+  if (bd.n == 0) return hipSuccess;
+  k_residual_b<<<(unsigned)bd.n, 1024, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit_W_b(int D, const BatchDev& bd, int64_t ncell, hipStream_t s) {
+  if (ncell == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((ncell + 255) / 256);
+  if (D == 2) k_commit_W_b<2><<<grid, 256, 0, s>>>(bd);
+  else k_commit_W_b<3><<<grid, 256, 0, s>>>(bd);
   return hipGetLastError();
 }
 

@@ -36,11 +36,34 @@ constexpr int SWF = 4;      // faces per cell on the fused path (triangles, quad
 constexpr int SWT = 256;    // threads per work-group
 constexpr int NAX = 64;     // nodes per velocity axis (max)
 
+// A wave-uniform row of f in the global address space, kept opaque in
+// scalar registers, so that every load from it is one scalar base plus a
+// 32-bit per-lane byte offset (no reassociated 64-bit vector addresses).
+typedef const __attribute__((address_space(1))) char grow_t;
+
+template <typename T>
+__device__ __forceinline__ grow_t* srow(const T* p) {
+  grow_t* g = (grow_t*)p;
+  __asm__("" : "+s"(g));
+  return g;
+}
+
+// Per-cell and per-face records are read-only during the sweep; read
+// through the constant address space their wave-uniform loads are always
+// scalar loads, also where the record pointers themselves come from memory
+// (the batched form).
+typedef const __attribute__((address_space(4))) int32_t crec_i_t;
+typedef const __attribute__((address_space(4))) double crec_d_t;
+
+template <typename T>
+__device__ __forceinline__ double ldo(grow_t* row, uint32_t off) {
+  return static_cast<double>(*(const __attribute__((address_space(1))) T*)(row + off));
+}
+
 // Even and odd parts of a cubic (monomial order of Cubic<D>) at u by nested
 // Horner forms:  P(u) = E(u) + O(u),  P(-u) = E(u) - O(u).
-template <int D>
-__device__ __forceinline__ void cubic_eo(const double* __restrict__ P, const double* v, double& E,
-                                         double& O) {
+template <int D, typename PT>
+__device__ __forceinline__ void cubic_eo(PT P, const double* v, double& E, double& O) {
   if constexpr (D == 3) {
     const double x = v[0], y = v[1], z = v[2];
     // quadratics xx yy zz xy xz yz = P[4..9], cubics xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz = P[10..19]
@@ -59,11 +82,11 @@ __device__ __forceinline__ void cubic_eo(const double* __restrict__ P, const dou
 // Per-cell first-stage data of one step: dt/(2 tau), K_xi/(2 lambda) and the
 // Shakhov polynomials H+/H, B+/B of the cell's equilibrium (Eqs. H_plus, B_plus).
 template <int D>
-__global__ void k_cell_prep(int64_t nc, GasP g, const double* __restrict__ W,
-                            const double* __restrict__ q, double* __restrict__ prim,
-                            double* __restrict__ cs, int32_t* flag) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nc || *flag) return;
+__device__ __forceinline__ void cell_prep_at(int64_t i, const GasP& g, const double* __restrict__ W,
+                                             const double* __restrict__ q,
+                                             double* __restrict__ prim, double* __restrict__ cs,
+                                             int32_t* flag) {
+  if (*flag) return;
   double* P = &prim[i * NPRIM];
   if (!prim_of<D>(&W[i * (D + 2)], g, P)) {
     atomicOr(flag, 1);
@@ -88,19 +111,29 @@ __global__ void k_cell_prep(int64_t nc, GasP g, const double* __restrict__ W,
   }
 }
 
+template <int D>
+__global__ void k_cell_prep(int64_t nc, GasP g, const double* __restrict__ W,
+                            const double* __restrict__ q, double* __restrict__ prim,
+                            double* __restrict__ cs, int32_t* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nc) cell_prep_at<D>(i, g, W, q, prim, cs, flag);
+}
+
 // Axis tables of every face Maxwellian and every cell Maxwellian of the
 // step, tab[e][d][n] = scale_d exp(-lambda (a_n - U_d)^2) with the density
 // and normalisation folded into d = 0, so that g(u) at a tensor point is a
 // product of D entries.  Entities 0..nf-1 are faces (interface g0, or on a
 // wall the re-emitted Maxwellian scaled by rho_w dt), nf..nf+nc-1 cells.
 template <int D>
-__global__ void k_tables(int64_t nf, int64_t nc, int na, const double* __restrict__ axis,
-                         const int32_t* __restrict__ fbc, GasP g, const double* __restrict__ frec,
-                         const double* __restrict__ prim, const double* __restrict__ cs,
-                         double* __restrict__ tabs, const int32_t* __restrict__ flag) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void tables_at(int64_t t, int64_t nf, int na,
+                                          const double* __restrict__ axis,
+                                          const int32_t* __restrict__ fbc, const GasP& g,
+                                          const double* __restrict__ frec,
+                                          const double* __restrict__ prim,
+                                          const double* __restrict__ cs, double* __restrict__ tabs,
+                                          const int32_t* __restrict__ flag) {
   const int64_t per = (int64_t)D * na;
-  if (t >= (nf + nc) * per || *flag) return;
+  if (*flag) return;
   const int64_t e = t / per;
   const int r = (int)(t % per), d = r / na, n = r % na;
   const double a = axis[n];
@@ -120,49 +153,55 @@ __global__ void k_tables(int64_t nf, int64_t nc, int na, const double* __restric
   tabs[e * per + d * na + n] = scale * exp(-lam * (a - U) * (a - U));
 }
 
-// Every read-only array is its own __restrict__ kernel argument so that the
-// compiler can prove no store of the kernel clobbers it and serve the
+template <int D>
+__global__ void k_tables(int64_t nf, int64_t nc, int na, const double* __restrict__ axis,
+                         const int32_t* __restrict__ fbc, GasP g, const double* __restrict__ frec,
+                         const double* __restrict__ prim, const double* __restrict__ cs,
+                         double* __restrict__ tabs, const int32_t* __restrict__ flag) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < (nf + nc) * (int64_t)D * na) tables_at<D>(t, nf, na, axis, fbc, g, frec, prim, cs, tabs, flag);
+}
+
+// LDS of one sweep work item: the Maxwellian axis tables of the cell's four
+// faces and of the cell, the velocity nodes and the reduction scratch.
+struct SweepLds {
+  double tab[SWF][3][NAX];
+  double ctab[3][NAX];
+  double ax[NAX];
+  double red[5 * 16];
+};
+
+// One work item of the fused sweep: cell ic, velocity block `chunk`.
+// Every read-only array is its own __restrict__ argument so that the
+// compiler can prove no store of the sweep clobbers it and serve the
 // wave-uniform reads from the scalar cache.
 template <int D, typename T>
-__global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
-    FusedMesh fm, GasP g, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
+__device__ __forceinline__ void sweep_item(
+    const FusedMesh& fm, int64_t nvp, const SweepSched& sc, const int32_t* __restrict__ crec_i,
     const double* __restrict__ crec_d, const int32_t* __restrict__ vidx,
     const double* __restrict__ w, const double* __restrict__ cs, const double* __restrict__ frec,
     const double* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
     T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dWp,
-    const int32_t* __restrict__ flag) {
-  __shared__ double tab[SWF][3][NAX];
-  __shared__ double ctab[3][NAX];
-  __shared__ double ax[NAX];
+    const int32_t* __restrict__ flag, int64_t ic, int64_t chunk, SweepLds& L) {
   if (*flag) return;
-  // Work item = (cell, velocity block).  Blocks are dealt round-robin to the
-  // 8 XCDs; XCD x takes tiles x, x+8, ... of sc.tile consecutive (Z-order)
-  // cells and runs all of a tile's cells through velocity block 0, then 1,
-  // ..., so the stencil rows of one tile and one velocity block are what
-  // its L2 must hold.
-  const int64_t xcd = blockIdx.x % 8, local = blockIdx.x / 8;
-  const int64_t per_tile = sc.nchunk * sc.tile;
-  const int64_t tile = (local / per_tile) * 8 + xcd;
-  const int64_t rem = local % per_tile;
-  const int64_t chunk = rem / sc.tile;
-  const int64_t ic = tile * sc.tile + rem % sc.tile;
-  if (ic >= fm.nc) return;
   // every pointer below is wave-uniform: its loads are scalar loads
-  const int32_t* __restrict__ ci0 = crec_i + ic * CRI;
-  const double* __restrict__ cd0 = crec_d + ic * CRD;
-  const double* __restrict__ cc0 = cs + ic * CSREC;
+  crec_i_t* ci0 = (crec_i_t*)(crec_i + ic * CRI);
+  crec_d_t* cd0 = (crec_d_t*)(crec_d + ic * CRD);
+  crec_d_t* cc0 = (crec_d_t*)(cs + ic * CSREC);
+  crec_d_t* frc = (crec_d_t*)frec;
+  const unsigned nthr = blockDim.x;  // lanes of the work-group, one mirror pair each
   const int na = fm.na;
   {
     // stage this cell's face and cell tables in LDS (faces 0..3, then the cell)
     const int per = D * na, n_all = 5 * per;
-    for (int t = threadIdx.x; t < n_all; t += SWT) {
+    for (int t = threadIdx.x; t < n_all; t += nthr) {
       const int p = t / per, r = t % per, d = r / na, n = r % na;
       const int64_t e = p < 4 ? (int64_t)ci0[CRI_F0 + CRI_FS * p] : sc.nf + ic;
       const double v = tabs[e * per + d * na + n];
-      if (p < 4) tab[p][d][n] = v;
-      else ctab[d][n] = v;
+      if (p < 4) L.tab[p][d][n] = v;
+      else L.ctab[d][n] = v;
     }
-    for (int t = threadIdx.x; t < na; t += SWT) ax[t] = fm.axis[t];
+    for (int t = threadIdx.x; t < na; t += nthr) L.ax[t] = fm.axis[t];
     __syncthreads();
   }
   constexpr int NM = D + 2;
@@ -180,18 +219,21 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
 #pragma unroll
   for (int x = 0; x < NM; ++x) mw[x] = 0.0;
 
-  for (unsigned kp = kbeg + threadIdx.x; kp < kend; kp += SWT) {
+  // the packed axis indices of the next pair are loaded one iteration ahead
+  int pk_next = kbeg + threadIdx.x < kend ? vidx[kbeg + threadIdx.x] : 0;
+  for (unsigned kp = kbeg + threadIdx.x; kp < kend; kp += nthr) {
     // The cell and face records are loop invariant but too large to keep in
     // scalar registers for the whole loop: an opaque uniform zero added to
     // their addresses makes them scalar re-loads (scalar cache) each
     // iteration instead of hoisted, spilled registers.
     int z;
     __asm__ volatile("s_mov_b32 %0, 0" : "=s"(z));
-    const int32_t* __restrict__ ci = ci0 + z;
-    const double* __restrict__ cd = cd0 + z;
-    const double* __restrict__ cc = cc0 + z;
+    crec_i_t* ci = ci0 + z;
+    crec_d_t* cd = cd0 + z;
+    crec_d_t* cc = cc0 + z;
     const unsigned k0 = kp, k1 = nv - 1 - kp;
-    const int pk = vidx[k0];
+    const int pk = pk_next;
+    pk_next = vidx[min(kp + nthr, kend - 1)];
     int id[3], im[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -200,7 +242,7 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
     }
     double vv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int d = 0; d < D; ++d) vv[d] = ax[id[d]];
+    for (int d = 0; d < D; ++d) vv[d] = L.ax[id[d]];
     // orientation of u against every outward normal
     double sp[4];
 #pragma unroll
@@ -211,38 +253,44 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
       sp[p] = s;
     }
     // ---- the cell's own stencil at u and -u (4 rows, padded) ----
-    const double h0 = ld(hi, k0), h1 = ld(hi, k1);
+    const uint32_t o0 = k0 * (uint32_t)sizeof(T), o1 = k1 * (uint32_t)sizeof(T);
+    grow_t* rhi = srow(hi);
+    const double h0 = ldo<T>(rhi, o0), h1 = ldo<T>(rhi, o1);
     double b0 = 0.0, b1 = 0.0;
     if (B2) {
-      b0 = ld(bi, k0);
-      b1 = ld(bi, k1);
+      grow_t* rbi = srow(bi);
+      b0 = ldo<T>(rbi, o0);
+      b1 = ldo<T>(rbi, o1);
     }
     double os0[4], os1[4], ob0[4], ob1[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t cell = ci[2 + s];
-      os0[s] = ld(h + cell * nvp, k0);
-      os1[s] = ld(h + cell * nvp, k1);
+      grow_t* rh = srow(h + cell * nvp);
+      os0[s] = ldo<T>(rh, o0);
+      os1[s] = ldo<T>(rh, o1);
       ob0[s] = ob1[s] = 0.0;
       if (B2) {
-        ob0[s] = ld(b + cell * nvp, k0);
-        ob1[s] = ld(b + cell * nvp, k1);
+        grow_t* rb = srow(b + cell * nvp);
+        ob0[s] = ldo<T>(rb, o0);
+        ob1[s] = ldo<T>(rb, o1);
       }
     }
     // ---- every neighbour's value and stencil at the incoming member ----
     double nh[4], nhs[4][4], nb[4], nbs[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      const int32_t* fi = ci + CRI_F0 + CRI_FS * p;
-      const unsigned kin = sp[p] > 0.0 ? k1 : k0;
+      crec_i_t* fi = ci + CRI_F0 + CRI_FS * p;
+      uint32_t oin = sp[p] > 0.0 ? o1 : o0;
+      __asm__("" : "+v"(oin));  // keep the select on the offset, not on 64-bit addresses
       const int64_t j = fi[3];
-      nh[p] = ld(h + j * nvp, kin);
-      nb[p] = B2 ? ld(b + j * nvp, kin) : 0.0;
+      nh[p] = ldo<T>(srow(h + j * nvp), oin);
+      nb[p] = B2 ? ldo<T>(srow(b + j * nvp), oin) : 0.0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t cell = fi[5 + r];
-        nhs[p][r] = ld(h + cell * nvp, kin);
-        nbs[p][r] = B2 ? ld(b + cell * nvp, kin) : 0.0;
+        nhs[p][r] = ldo<T>(srow(h + cell * nvp), oin);
+        nbs[p][r] = B2 ? ldo<T>(srow(b + cell * nvp), oin) : 0.0;
       }
     }
     // ---- arithmetic ----
@@ -278,8 +326,8 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
     double acc0 = 0.0, acc1 = 0.0, accb0 = 0.0, accb1 = 0.0;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      const double* fd = cd + CRD_F0 + CRD_FS * p;
-      const double* R = frec + (int64_t)ci[CRI_F0 + CRI_FS * p] * FREC;
+      crec_d_t* fd = cd + CRD_F0 + CRD_FS * p;
+      crec_d_t* R = frc + (int64_t)ci[CRI_F0 + CRI_FS * p] * FREC;
       const bool pos = sp[p] > 0.0;
       const double as = fabs(sp[p]);
       const double G1 = R[FR_G], G2 = R[FR_G + 1];
@@ -312,11 +360,11 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
       ugj *= sgn_in;
       // g0 (or the scaled wall Maxwellian) at u and -u from the axis tables,
       // times the equilibrium polynomial (constant on a wall)
-      double e0 = tab[p][0][id[0]], e1 = tab[p][0][im[0]];
+      double e0 = L.tab[p][0][id[0]], e1 = L.tab[p][0][im[0]];
 #pragma unroll
       for (int d = 1; d < D; ++d) {
-        e0 *= tab[p][d][id[d]];
-        e1 *= tab[p][d][im[d]];
+        e0 *= L.tab[p][d][id[d]];
+        e1 *= L.tab[p][d][im[d]];
       }
       double E, O;
       cubic_eo<D>(R + FR_PH, vv, E, O);
@@ -365,11 +413,11 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
       mw[D + 1] += e;
     }
     // first stage with the cell's BGK-Shakhov equilibrium at u and -u
-    double c0 = ctab[0][id[0]], c1 = ctab[0][im[0]];
+    double c0 = L.ctab[0][id[0]], c1 = L.ctab[0][im[0]];
 #pragma unroll
     for (int d = 1; d < D; ++d) {
-      c0 *= ctab[d][id[d]];
-      c1 *= ctab[d][im[d]];
+      c0 *= L.ctab[d][id[d]];
+      c1 *= L.ctab[d][im[d]];
     }
     double E, O;
     cubic_eo<D>(cc + CS_SH, vv, E, O);
@@ -386,20 +434,93 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
       if (k1 != k0) st(bto, k1, b1 - accb1 + ccoll * (kc * c1 * (1.0 + Eb - Ob) - b1));
     }
   }
-  __shared__ double red[5 * 16];
-  block_sum<NM>(mw, red);
+  block_sum<NM>(mw, L.red);
   if (threadIdx.x == 0)
     for (int x = 0; x < 5; ++x) dWp[(ic * sc.nchunk + chunk) * 5 + x] = x < NM ? mw[x] : 0.0;
+}
+
+
+template <int D, typename T>
+__global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
+    FusedMesh fm, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
+    const double* __restrict__ crec_d, const int32_t* __restrict__ vidx,
+    const double* __restrict__ w, const double* __restrict__ cs, const double* __restrict__ frec,
+    const double* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
+    T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dWp,
+    const int32_t* __restrict__ flag) {
+  __shared__ SweepLds L;
+  // Work item = (cell, velocity block).  Blocks are dealt round-robin to the
+  // 8 XCDs; XCD x takes tiles x, x+8, ... of sc.tile consecutive (Z-order)
+  // cells and runs all of a tile's cells through velocity block 0, then 1,
+  // ..., so the stencil rows of one tile and one velocity block are what
+  // its L2 must hold.
+  const int64_t xcd = blockIdx.x % 8, local = blockIdx.x / 8;
+  const int64_t per_tile = sc.nchunk * sc.tile;
+  const int64_t tile = (local / per_tile) * 8 + xcd;
+  const int64_t rem = local % per_tile;
+  const int64_t chunk = rem / sc.tile;
+  const int64_t ic = tile * sc.tile + rem % sc.tile;
+  if (ic >= fm.nc) return;
+  sweep_item<D, T>(fm, nvp, sc, crec_i, crec_d, vidx, w, cs, frec, tabs, h, b, ht, bt, dWp, flag,
+                   ic, chunk, L);
+}
+
+// The fused sweep over a batch of cases: a persistent grid walks a list of
+// (case, cell, velocity block) work items; item w runs on block w mod the
+// grid size, and the host orders the list so that the blocks of one XCD
+// (block index mod 8) take whole tiles of one case.
+template <int D, typename T>
+__global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep_b(BatchDev bd) {
+  __shared__ SweepLds L;
+  // The work list and the case table are read-only for the whole launch:
+  // read through the constant address space they are scalar loads, so the
+  // case's pointers and sizes land in scalar registers as kernel arguments do.
+  typedef const __attribute__((address_space(4))) int32_t citem_t;
+  typedef const __attribute__((address_space(4))) CaseDev ccase_t;
+  citem_t* items = (citem_t*)bd.items;
+  ccase_t* cases = (ccase_t*)bd.cases;
+  for (int64_t it = blockIdx.x; it < bd.nitems; it += gridDim.x) {
+    const int c = items[4 * it];
+    if (c < 0) continue;  // padding
+    const int64_t ic = items[4 * it + 1], chunk = items[4 * it + 2];
+    FusedMesh fm;
+    fm.nc = cases[c].fm.nc;
+    fm.nv = cases[c].fm.nv;
+    fm.na = cases[c].fm.na;
+    fm.axis = cases[c].fm.axis;
+    fm.vidx = cases[c].fm.vidx;
+    fm.crec_i = cases[c].fm.crec_i;
+    fm.crec_d = cases[c].fm.crec_d;
+    SweepSched sc;
+    sc.nf = cases[c].sc.nf;
+    sc.tile = cases[c].sc.tile;
+    sc.nchunk = cases[c].sc.nchunk;
+    sc.chunk_pairs = cases[c].sc.chunk_pairs;
+    const int64_t nvp = cases[c].v.nvp;
+    const double* w = cases[c].v.w;
+    const double* cs = cases[c].B.cs;
+    const double* frec = cases[c].B.frec;
+    const double* tabs = cases[c].B.tabs;
+    const T* h = (const T*)cases[c].B.h;
+    const T* b = (const T*)cases[c].B.b;
+    T* ht = (T*)cases[c].B.ht;
+    T* bt = (T*)cases[c].B.bt;
+    double* dW = cases[c].B.dW;
+    const int32_t* flag = cases[c].B.flag;
+    __syncthreads();  // the previous item's readers of L are done
+    sweep_item<D, T>(fm, nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, w, cs, frec, tabs, h, b, ht, bt,
+                     dW, flag, ic, chunk, L);
+  }
 }
 
 // Conservative update of the fused path: W^{n+1} = W^n - dW.
 // The partial sums of the velocity blocks are added in block order.
 template <int D>
-__global__ void k_apply_dW(int64_t nc, int64_t nchunk, const double* __restrict__ vol,
-                           const double* __restrict__ W, const double* __restrict__ dWp,
-                           double* __restrict__ Wn, double* __restrict__ cellred, const int32_t* flag) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nc || *flag) return;
+__device__ __forceinline__ void apply_dW_at(int64_t i, int64_t nchunk, const double* __restrict__ vol,
+                                            const double* __restrict__ W,
+                                            const double* __restrict__ dWp, double* __restrict__ Wn,
+                                            double* __restrict__ cellred, const int32_t* flag) {
+  if (*flag) return;
   for (int x = 0; x < D + 2; ++x) {
     double s = 0.0;
     for (int64_t c = 0; c < nchunk; ++c) s += dWp[(i * nchunk + c) * 5 + x];
@@ -412,23 +533,34 @@ __global__ void k_apply_dW(int64_t nc, int64_t nchunk, const double* __restrict_
   cellred[i * 3 + 2] = V * W[i * (D + 2)] * W[i * (D + 2)];
 }
 
+template <int D>
+__global__ void k_apply_dW(int64_t nc, int64_t nchunk, const double* __restrict__ vol,
+                           const double* __restrict__ W, const double* __restrict__ dWp,
+                           double* __restrict__ Wn, double* __restrict__ cellred, const int32_t* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nc) apply_dW_at<D>(i, nchunk, vol, W, dWp, Wn, cellred, flag);
+}
+
 // Second stage (Eq. f_final) fused with the heat flux of the result.
 // csn holds dt/(2 tau^{n+1}) and the Shakhov polynomials of W^{n+1} with q^n.
+struct Stage2Lds {
+  double ctab[3][NAX];
+  double ax[NAX];
+  double red[3 * 16];
+};
+
 template <int D, typename T>
-__global__ __launch_bounds__(SWT) void k_stage2_q(FusedMesh fm, int64_t nvp,
-                                                  const double* __restrict__ w,
-                                                  const double* __restrict__ primn,
-                                                  const double* __restrict__ csn,
-                                                  const T* __restrict__ ht, const T* __restrict__ bt,
-                                                  T* __restrict__ h, T* __restrict__ b,
-                                                  double* __restrict__ qn, const int32_t* flag) {
-  __shared__ double ctab[3][NAX];
-  __shared__ double ax[NAX];
-  __shared__ double red[3 * 16];
+__device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, int64_t nvp,
+                                              const double* __restrict__ w,
+                                              const double* __restrict__ primn,
+                                              const double* __restrict__ csn,
+                                              const T* __restrict__ ht, const T* __restrict__ bt,
+                                              T* __restrict__ h, T* __restrict__ b,
+                                              double* __restrict__ qn, const int32_t* flag,
+                                              Stage2Lds& L) {
   if (*flag) return;
-  const int64_t per = (fm.nc + 7) / 8;
-  const int64_t ic = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (ic >= fm.nc) return;
+  double(&ctab)[3][NAX] = L.ctab;
+  double(&ax)[NAX] = L.ax;
   const int na = fm.na;
   const double* __restrict__ P = primn + ic * NPRIM;
   const double* __restrict__ cc = csn + ic * CSREC;
@@ -478,20 +610,34 @@ __global__ __launch_bounds__(SWT) void k_stage2_q(FusedMesh fm, int64_t nvp,
 #pragma unroll
     for (int d = 0; d < D; ++d) acc[d] += s * c[d];
   }
-  block_sum<3>(acc, red);
+  block_sum<3>(acc, L.red);
   if (threadIdx.x == 0)
     for (int d = 0; d < 3; ++d) qn[ic * 3 + d] = d < D ? 0.5 * acc[d] : 0.0;
 }
 
+template <int D, typename T>
+__global__ __launch_bounds__(SWT) void k_stage2_q(FusedMesh fm, int64_t nvp,
+                                                  const double* __restrict__ w,
+                                                  const double* __restrict__ primn,
+                                                  const double* __restrict__ csn,
+                                                  const T* __restrict__ ht, const T* __restrict__ bt,
+                                                  T* __restrict__ h, T* __restrict__ b,
+                                                  double* __restrict__ qn, const int32_t* flag) {
+  __shared__ Stage2Lds L;
+  const int64_t per = (fm.nc + 7) / 8;
+  const int64_t ic = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (ic >= fm.nc) return;
+  stage2_q_cell<D, T>(ic, fm, nvp, w, primn, csn, ht, bt, h, b, qn, flag, L);
+}
+
 // Wall density with the wall cell's gradient evaluated in place.
 template <int D, typename T>
-__global__ __launch_bounds__(SWT) void k_wall_rho_inline(DevMesh m, DevVel v, GasP g,
-                                                         const T* __restrict__ h,
-                                                         double* __restrict__ frec,
-                                                         const int32_t* flag) {
-  __shared__ double red[2 * 16];
+__device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const DevVel& v,
+                                            const GasP& g, const T* __restrict__ h,
+                                            double* __restrict__ frec, const int32_t* flag,
+                                            double* red) {
   if (*flag) return;
-  const int f = m.walls[blockIdx.x];
+  const int f = m.walls[wi];
   const int64_t L = m.fL[f];
   const int64_t nvp = v.nvp;
   double* R = &frec[(int64_t)f * FREC];
@@ -527,6 +673,81 @@ __global__ __launch_bounds__(SWT) void k_wall_rho_inline(DevMesh m, DevVel v, Ga
   }
   block_sum<2>(acc, red);
   if (threadIdx.x == 0) R[FR_RHOW] = -acc[0] / (dt * acc[1]);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(SWT) void k_wall_rho_inline(DevMesh m, DevVel v, GasP g,
+                                                         const T* __restrict__ h,
+                                                         double* __restrict__ frec,
+                                                         const int32_t* flag) {
+  __shared__ double red[2 * 16];
+  wall_rho_at<D, T>(blockIdx.x, m, v, g, h, frec, flag, red);
+}
+
+// ---- batched forms: one launch covers every case of a batch ---------------
+// Element t of a flattened range belongs to case c with off[c] <= t < off[c+1].
+__device__ __forceinline__ int case_of(const int64_t* __restrict__ off, int n, int64_t t) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// next = 0: W^n, q -> prim, cs;  next = 1: W^{n+1}, q -> primn, csn
+template <int D>
+__global__ void k_cell_prep_b(BatchDev bd, int next) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= bd.cell_off[bd.n]) return;
+  const int c = case_of(bd.cell_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  const int64_t i = t - bd.cell_off[c];
+  if (next) cell_prep_at<D>(i, C.g, C.B.Wn, C.B.q, C.B.primn, C.B.csn, C.B.flag);
+  else cell_prep_at<D>(i, C.g, C.B.W, C.B.q, C.B.prim, C.B.cs, C.B.flag);
+}
+
+template <int D>
+__global__ void k_tables_b(BatchDev bd) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= bd.tab_off[bd.n]) return;
+  const int c = case_of(bd.tab_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  tables_at<D>(t - bd.tab_off[c], C.m.nf, C.fm.na, C.fm.axis, C.m.fbc, C.g, C.B.frec, C.B.prim,
+               C.B.cs, C.B.tabs, C.B.flag);
+}
+
+template <int D>
+__global__ void k_apply_dW_b(BatchDev bd) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= bd.cell_off[bd.n]) return;
+  const int c = case_of(bd.cell_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  apply_dW_at<D>(t - bd.cell_off[c], C.sc.nchunk, C.m.vol, C.B.W, C.B.dW, C.B.Wn, C.B.cellred,
+                 C.B.flag);
+}
+
+// one block per cell of the batch
+template <int D, typename T>
+__global__ __launch_bounds__(SWT) void k_stage2_q_b(BatchDev bd) {
+  __shared__ Stage2Lds L;
+  const int64_t t = blockIdx.x;
+  const int c = case_of(bd.cell_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  stage2_q_cell<D, T>(t - bd.cell_off[c], C.fm, C.v.nvp, C.v.w, C.B.primn, C.B.csn,
+                      (const T*)C.B.ht, (const T*)C.B.bt, (T*)C.B.h, (T*)C.B.b, C.B.qn, C.B.flag,
+                      L);
+}
+
+// one block per wall face of the batch
+template <int D, typename T>
+__global__ __launch_bounds__(SWT) void k_wall_rho_b(BatchDev bd) {
+  __shared__ double red[2 * 16];
+  const int64_t t = blockIdx.x;
+  const int c = case_of(bd.wall_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  wall_rho_at<D, T>(t - bd.wall_off[c], C.m, C.v, C.g, (const T*)C.B.h, C.B.frec, C.B.flag, red);
 }
 
 }  // namespace
@@ -585,7 +806,7 @@ hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, c
   const int64_t ntile = (fm.nc + sc.tile - 1) / sc.tile;
   const unsigned grid = (unsigned)(((ntile + 7) / 8) * 8 * sc.nchunk * sc.tile);
   UGKS_DISPATCH_DT(D, prec, k_sweep<DD, TT><<<grid, SWT, 0, s>>>(
-      fm, g, v.nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, v.w, cs, frec, tabs, (const TT*)h,
+      fm, v.nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, v.w, cs, frec, tabs, (const TT*)h,
       (const TT*)b, (TT*)ht, (TT*)bt, dWp, flag));
   return hipGetLastError();
 }
@@ -606,6 +827,56 @@ hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVe
   UGKS_DISPATCH_DT(D, prec, k_wall_rho_inline<DD, TT><<<(unsigned)m.nwall, SWT, 0, s>>>(
       m, v, g, (const TT*)h, frec, flag));
   return hipGetLastError();
+}
+
+// ---- batched launchers ------------------------------------------------------
+hipError_t launch_cell_prep_b(int D, const BatchDev& bd, int64_t ncell, int next, hipStream_t s) {
+  if (ncell == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((ncell + 127) / 128);
+  UGKS_DISPATCH_D(D, k_cell_prep_b<DD><<<grid, 128, 0, s>>>(bd, next));
+  return hipGetLastError();
+}
+
+hipError_t launch_tables_b(int D, const BatchDev& bd, int64_t ntab, hipStream_t s) {
+  if (ntab == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((ntab + 255) / 256);
+  UGKS_DISPATCH_D(D, k_tables_b<DD><<<grid, 256, 0, s>>>(bd));
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_dW_b(int D, const BatchDev& bd, int64_t ncell, hipStream_t s) {
+  if (ncell == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((ncell + 255) / 256);
+  UGKS_DISPATCH_D(D, k_apply_dW_b<DD><<<grid, 256, 0, s>>>(bd));
+  return hipGetLastError();
+}
+
+hipError_t launch_stage2_q_b(int D, int prec, const BatchDev& bd, int64_t ncell, hipStream_t s) {
+  if (ncell == 0) return hipSuccess;
+  UGKS_DISPATCH_DT(D, prec, k_stage2_q_b<DD, TT><<<(unsigned)ncell, SWT, 0, s>>>(bd));
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_rho_b(int D, int prec, const BatchDev& bd, int64_t nwall, hipStream_t s) {
+  if (nwall == 0) return hipSuccess;
+  UGKS_DISPATCH_DT(D, prec, k_wall_rho_b<DD, TT><<<(unsigned)nwall, SWT, 0, s>>>(bd));
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_b(int D, int prec, const BatchDev& bd, int64_t grid, int threads,
+                          hipStream_t s) {
+  if (bd.nitems == 0) return hipSuccess;
+  if (threads % 64 != 0 || threads < 64 || threads > SWT) return hipErrorInvalidValue;
+  UGKS_DISPATCH_DT(D, prec, k_sweep_b<DD, TT><<<(unsigned)grid, threads, 0, s>>>(bd));
+  return hipGetLastError();
+}
+
+int sweep_b_blocks_per_cu(int D, int prec, int threads) {
+  int n = 0;
+  hipError_t e = hipSuccess;
+  UGKS_DISPATCH_DT(D, prec, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                &n, reinterpret_cast<const void*>(&k_sweep_b<DD, TT>), threads, 0));
+  return e == hipSuccess ? n : 0;
 }
 
 }  // namespace ugks

@@ -23,7 +23,9 @@ UGKS_FP64, UGKS_FP32 = 64, 32
 EXPORTED = [
     "ugks_create", "ugks_step", "ugks_moments", "ugks_get_state", "ugks_set_state",
     "ugks_face_data", "ugks_info", "ugks_destroy", "ugks_last_error", "ugks_profile_enable",
-    "ugks_profile_read",
+    "ugks_profile_read", "ugks_batch_create", "ugks_batch_step", "ugks_batch_moments",
+    "ugks_batch_get_state", "ugks_batch_case_info", "ugks_batch_info", "ugks_batch_destroy",
+    "ugks_batch_last_error", "ugks_autotune_save", "ugks_autotune_load", "ugks_autotune_clear",
 ]
 
 
@@ -60,6 +62,18 @@ class ugks_info_t(C.Structure):
                 ("nv", C.c_int64), ("nv_padded", C.c_int64), ("dt", C.c_double),
                 ("steps_done", C.c_int64), ("device_bytes", C.c_int64), ("fused", C.c_int32),
                 ("tile_cells", C.c_int32)]
+
+
+class ugks_case(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("vel", C.c_void_p), ("gas", C.c_void_p),
+                ("bcs", C.c_void_p), ("n_bc", C.c_int32), ("W0", C.c_void_p)]
+
+
+class ugks_batch_info_t(C.Structure):
+    _fields_ = [("n_cases", C.c_int32), ("dim", C.c_int32), ("precision", C.c_int32),
+                ("threads", C.c_int32), ("work_items", C.c_int64), ("grid", C.c_int64),
+                ("graph", C.c_int32), ("tuned", C.c_int32), ("tune_timings", C.c_int64),
+                ("steps_done", C.c_int64)]
 
 
 class ugks_kernel_time(C.Structure):
@@ -101,6 +115,28 @@ def load_library(path: str = LIB_PATH):
     lib.ugks_profile_enable.argtypes = [P, C.c_int32]
     lib.ugks_profile_read.restype = C.c_int
     lib.ugks_profile_read.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
+    lib.ugks_batch_create.restype = C.c_int
+    lib.ugks_batch_create.argtypes = [P, C.c_int32, C.POINTER(ugks_options), C.POINTER(C.c_void_p)]
+    lib.ugks_batch_step.restype = C.c_int
+    lib.ugks_batch_step.argtypes = [P, C.c_int32, P]
+    lib.ugks_batch_moments.restype = C.c_int
+    lib.ugks_batch_moments.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32]
+    lib.ugks_batch_get_state.restype = C.c_int
+    lib.ugks_batch_get_state.argtypes = [P, C.c_int32, P, P, P]
+    lib.ugks_batch_case_info.restype = C.c_int
+    lib.ugks_batch_case_info.argtypes = [P, C.c_int32, C.POINTER(ugks_info_t)]
+    lib.ugks_batch_info.restype = C.c_int
+    lib.ugks_batch_info.argtypes = [P, C.POINTER(ugks_batch_info_t)]
+    lib.ugks_batch_destroy.restype = None
+    lib.ugks_batch_destroy.argtypes = [P]
+    lib.ugks_batch_last_error.restype = C.c_char_p
+    lib.ugks_batch_last_error.argtypes = [P]
+    lib.ugks_autotune_save.restype = C.c_int
+    lib.ugks_autotune_save.argtypes = [C.c_char_p]
+    lib.ugks_autotune_load.restype = C.c_int
+    lib.ugks_autotune_load.argtypes = [C.c_char_p]
+    lib.ugks_autotune_clear.restype = None
+    lib.ugks_autotune_clear.argtypes = []
     _lib = lib
     return lib
 
@@ -134,24 +170,33 @@ def ugks_create(mesh, vel, gas, bcs, W0, precision=UGKS_FP64, block_v=0, flags=0
     keepalive only needs to live for the call.
     """
     lib = load_library()
+    keep = _marshal(mesh, vel, gas, bcs, W0)
+    opt = ugks_options(precision, block_v, flags, tile_cells, C.c_void_p(stream) if stream else None)
+    h = C.c_void_p()
+    rc = lib.ugks_create(C.byref(keep["cm"]), C.byref(keep["cv"]), C.byref(keep["cg"]),
+                         C.cast(keep["bcs"], C.c_void_p), keep["nb"], _p(keep["W0"]), C.byref(opt),
+                         C.byref(h))
+    _check(rc, None)
+    return h, keep
+
+
+def _marshal(mesh, vel, gas, bcs, W0) -> dict:
+    """C structs of one case; the dict keeps every array they point into alive."""
     m = mesh.contiguous()
     keep = dict(mesh=m, u=_f8(vel.u), w=_f8(vel.w), W0=_f8(W0))
-    cm = ugks_mesh(m.dim, m.n_cells, m.n_faces, _p(m.cell_volume), _p(m.cell_centroid),
-                   _p(m.face_cells), _p(m.face_area), _p(m.face_normal), _p(m.face_centroid),
-                   _p(m.face_shift), _p(m.face_bc), _p(m.face_bc_id))
-    cv = ugks_velocity(vel.nv, _p(keep["u"]), _p(keep["w"]))
-    cg = ugks_gas(gas.K, gas.Pr, gas.R, gas.T_ref, gas.mu_ref, gas.omega, gas.cfl, gas.dt)
+    keep["cm"] = ugks_mesh(m.dim, m.n_cells, m.n_faces, _p(m.cell_volume), _p(m.cell_centroid),
+                           _p(m.face_cells), _p(m.face_area), _p(m.face_normal),
+                           _p(m.face_centroid), _p(m.face_shift), _p(m.face_bc), _p(m.face_bc_id))
+    keep["cv"] = ugks_velocity(vel.nv, _p(keep["u"]), _p(keep["w"]))
+    keep["cg"] = ugks_gas(gas.K, gas.Pr, gas.R, gas.T_ref, gas.mu_ref, gas.omega, gas.cfl, gas.dt)
     nb = len(bcs)
     arr = (ugks_bc * max(nb, 1))()
     for i, b in enumerate(bcs):
         U = list(b.U) + [0.0] * (3 - len(b.U))
         arr[i] = ugks_bc(b.kind, b.rho, (C.c_double * 3)(*U[:3]), b.T)
-    opt = ugks_options(precision, block_v, flags, tile_cells, C.c_void_p(stream) if stream else None)
-    h = C.c_void_p()
-    rc = lib.ugks_create(C.byref(cm), C.byref(cv), C.byref(cg), C.cast(arr, C.c_void_p), nb,
-                         _p(keep["W0"]), C.byref(opt), C.byref(h))
-    _check(rc, None)
-    return h, keep
+    keep["bcs"] = arr
+    keep["nb"] = nb
+    return keep
 
 
 def ugks_step(h, n_steps: int):
@@ -265,3 +310,125 @@ class Solver:
         rw = np.zeros(self.nf)
         ugks_face_data(self.h, F, rw)
         return F, rw
+
+
+# ---- batched form ----------------------------------------------------------
+
+def _check_batch(rc, b=None):
+    if rc != UGKS_OK:
+        msg = load_library().ugks_batch_last_error(b)
+        raise UGKSError(rc, msg.decode() if msg else "")
+
+
+def ugks_batch_create(cases, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0):
+    """Create a batch from a list of ``ugks_cases.Case``; returns the handle."""
+    lib = load_library()
+    keeps = [_marshal(c.mesh, c.vel, c.gas, c.bcs, c.W0) for c in cases]
+    arr = (ugks_case * len(cases))()
+    for i, k in enumerate(keeps):
+        arr[i] = ugks_case(C.cast(C.pointer(k["cm"]), C.c_void_p), C.cast(C.pointer(k["cv"]), C.c_void_p),
+                           C.cast(C.pointer(k["cg"]), C.c_void_p), C.cast(k["bcs"], C.c_void_p),
+                           k["nb"], _p(k["W0"]))
+    opt = ugks_options(precision, block_v, flags, tile_cells, C.c_void_p(stream) if stream else None)
+    h = C.c_void_p()
+    rc = lib.ugks_batch_create(C.cast(arr, C.c_void_p), len(cases), C.byref(opt), C.byref(h))
+    _check_batch(rc, None)
+    return h
+
+
+def ugks_batch_step(b, n_steps: int, n_cases: int):
+    res = np.zeros(2 * n_cases)
+    _check_batch(load_library().ugks_batch_step(b, int(n_steps), _p(res)), b)
+    return res.reshape(n_cases, 2)
+
+
+def ugks_batch_moments(b, i: int, which: int, out, on_device: bool = False):
+    ptr = C.c_void_p(out.data_ptr()) if on_device else _p(out)
+    _check_batch(load_library().ugks_batch_moments(b, int(i), int(which), ptr, 1 if on_device else 0), b)
+    return out
+
+
+def ugks_batch_get_state(b, i: int, W, hdist, bdist):
+    _check_batch(load_library().ugks_batch_get_state(b, int(i), _p(W), _p(hdist), _p(bdist)), b)
+
+
+def ugks_batch_case_info(b, i: int) -> dict:
+    info = ugks_info_t()
+    _check_batch(load_library().ugks_batch_case_info(b, int(i), C.byref(info)), b)
+    return {f: getattr(info, f) for f, _ in ugks_info_t._fields_}
+
+
+def ugks_batch_info(b) -> dict:
+    info = ugks_batch_info_t()
+    _check_batch(load_library().ugks_batch_info(b, C.byref(info)), b)
+    return {f: getattr(info, f) for f, _ in ugks_batch_info_t._fields_}
+
+
+def ugks_batch_destroy(b):
+    if b:
+        load_library().ugks_batch_destroy(b)
+
+
+def ugks_batch_last_error(b=None) -> str:
+    s = load_library().ugks_batch_last_error(b)
+    return s.decode() if s else ""
+
+
+def ugks_autotune_save(path: str):
+    _check(load_library().ugks_autotune_save(path.encode()))
+
+
+def ugks_autotune_load(path: str):
+    rc = load_library().ugks_autotune_load(path.encode())
+    if rc != UGKS_OK:
+        raise UGKSError(rc, f"cannot load autotune cache {path}")
+
+
+def ugks_autotune_clear():
+    load_library().ugks_autotune_clear()
+
+
+class Batch:
+    """Owning wrapper around one batch of ``ugks_cases.Case`` objects."""
+
+    def __init__(self, cases, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0):
+        self.cases = list(cases)
+        self.h = ugks_batch_create(self.cases, precision=precision, block_v=block_v, flags=flags,
+                                   stream=stream, tile_cells=tile_cells)
+
+    def close(self):
+        if getattr(self, "h", None):
+            ugks_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def info(self) -> dict:
+        return ugks_batch_info(self.h)
+
+    def case_info(self, i: int) -> dict:
+        return ugks_batch_case_info(self.h, i)
+
+    def step(self, n: int = 1):
+        return ugks_batch_step(self.h, n, len(self.cases))
+
+    def W(self, i: int):
+        c = self.cases[i]
+        out = np.zeros((c.mesh.n_cells, c.mesh.dim + 2))
+        return ugks_batch_moments(self.h, i, 0, out)
+
+    def moments(self, i: int, which: int):
+        c = self.cases[i]
+        ncol = c.mesh.dim if which == 2 else c.mesh.dim + 2
+        out = np.zeros((c.mesh.n_cells, ncol))
+        return ugks_batch_moments(self.h, i, which, out)
+
+    def state(self, i: int):
+        c = self.cases[i]
+        W = np.zeros((c.mesh.n_cells, c.mesh.dim + 2))
+        hd = np.zeros((c.mesh.n_cells, c.vel.nv))
+        bd = np.zeros((c.mesh.n_cells, c.vel.nv))
+        ugks_batch_get_state(self.h, i, W, hd, bd)
+        return W, hd, bd

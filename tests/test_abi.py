@@ -76,3 +76,35 @@ def test_rejects_invalid_input(what):
         _create(case, **kw)
     assert e.value.code == ugks.UGKS_EINVAL
     assert ugks.ugks_last_error(None)
+
+
+def test_autotune_cache_file_round_trip(tmp_path):
+    """The tuning cache is host-side: save / load / clear need no GPU."""
+    lib = ugks.load_library()
+    lib.ugks_autotune_clear()
+    empty = tmp_path / "empty.txt"
+    assert lib.ugks_autotune_save(str(empty).encode()) == 0
+    assert empty.read_text() == "ugks-autotune 1\n"
+    good = tmp_path / "good.txt"
+    good.write_text("ugks-autotune 1\ncase 2 64 128 100 256 : 128 64 12.5\n"
+                    "batch 2 64 0 100 256 : 128\n")
+    assert lib.ugks_autotune_load(str(good).encode()) == 0
+    out = tmp_path / "out.txt"
+    assert lib.ugks_autotune_save(str(out).encode()) == 0
+    text = out.read_text().splitlines()
+    assert text[0] == "ugks-autotune 1"
+    assert "case 2 64 128 100 256 : 128 64 12.5" in text
+    assert "batch 2 64 0 100 256 : 128" in text
+    for bad in ("not-a-cache\n", "ugks-autotune 1\ncase 2 64 128 100 256 : 0 64 1\n",
+                "ugks-autotune 1\nbatch x : 96\n", "ugks-autotune 1\nother : 1\n"):
+        p = tmp_path / "bad.txt"
+        p.write_text(bad)
+        assert lib.ugks_autotune_load(str(p).encode()) == -1
+    lib.ugks_autotune_clear()
+
+
+def test_batch_create_rejects_empty_batch():
+    from paper_2606_15720_amd import ugks as U
+    with pytest.raises(U.UGKSError) as e:
+        U.ugks_batch_create([])
+    assert e.value.code == U.UGKS_EINVAL

@@ -1,0 +1,137 @@
+"""GPU: the batched form (many uneven 2-D cases, one launch per phase).
+
+Each case of a batch must follow the CPU oracle run on that case alone, to the
+same FP64 bound as the single-case parity tests.  The captured HIP graph must
+reproduce the eager launches bit for bit on every replay, with eager work and
+synchronisations between replays.  The autotuner's cache must round-trip
+through a file: a second batch of the same shapes is scheduled without
+timing anything and gets the same schedule.
+"""
+
+import numpy as np
+import pytest
+
+import ugks_cases as uc
+from oracle import Oracle
+from paper_2606_15720_amd import ugks as U
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+EAGER = 8  # ugks_options.flags bit: no graph
+
+
+def _scales(W):
+    D = W.shape[1] - 2
+    rho, rE = W[:, 0], W[:, D + 1]
+    mom = np.max(np.sqrt(2.0 * rho * rE))
+    return np.array([rho.max()] + [mom] * D + [np.abs(rE).max()])
+
+
+def _small_batch(seed=7, count=6):
+    # the batch recipe at oracle-friendly sizes: uneven meshes, grids and Kn
+    return uc.batch_cases(seed=seed, count=count, n_range=(5, 12), nv_range=(8, 16))
+
+
+def test_batch_cases_follow_the_oracle():
+    cases = _small_batch()
+    print("shapes", [(c.mesh.n_cells, c.vel.nv) for c in cases], flush=True)
+    b = U.Batch(cases)
+    info = b.info
+    print("batch", info, flush=True)
+    assert info["n_cases"] == len(cases) and info["graph"] == 1
+    oracles = [Oracle(c) for c in cases]
+    for i, c in enumerate(cases):
+        assert b.case_info(i)["dt"] == pytest.approx(oracles[i].dt, rel=1e-14)
+    steps_done = 0
+    for n in (1, 4):
+        res = b.step(n)
+        steps_done += n
+        assert res.shape == (len(cases), 2)
+        for i, (c, o) in enumerate(zip(cases, oracles)):
+            o.step(n)
+            Wo, ho, bo, qo = o.state()
+            Wg, hg, bg = b.state(i)
+            err = np.abs(Wg - Wo).max(axis=0) / _scales(Wo)
+            herr = np.abs(hg - ho).max() / np.abs(ho).max()
+            berr = np.abs(bg - bo).max() / np.abs(bo).max()
+            print(f"case {i} ({c.name}) step {steps_done}: W {err.max():.2e} h {herr:.2e} b {berr:.2e}",
+                  flush=True)
+            assert np.all(err <= TOL), (i, err)
+            assert herr <= TOL and berr <= TOL, (i, herr, berr)
+            qg = b.moments(i, 2)
+            np.testing.assert_allclose(qg, qo, rtol=0, atol=1e-13 * np.abs(Wo[:, -1]).max())
+    assert b.info["steps_done"] == 5
+    b.close()
+
+
+def test_batch_matches_cases_run_alone():
+    """Same schedule alone and in the batch: identical up to reduction order."""
+    cases = _small_batch(seed=11, count=5)
+    b = U.Batch(cases)
+    b.step(3)
+    for i, c in enumerate(cases):
+        ci = b.case_info(i)
+        # a block that covers every pair is the single-case default (0)
+        bv = ci["block_v"] if ci["block_v"] < c.vel.nv else 0
+        s = U.Solver(c, block_v=bv, tile_cells=ci["tile_cells"])
+        s.step(3)
+        Ws, Wb = s.W(), b.W(i)
+        err = np.abs(Wb - Ws).max(axis=0) / _scales(Ws)
+        assert np.all(err <= 1e-14), (i, err)
+        s.close()
+    b.close()
+
+
+def test_graph_replays_match_eager_launches():
+    cases = _small_batch(seed=3, count=4)
+    bg = U.Batch(cases)
+    be = U.Batch(cases, flags=EAGER)
+    assert bg.info["graph"] == 1 and be.info["graph"] == 0
+    assert bg.info["threads"] == be.info["threads"]  # same shapes: cached schedule
+    for rep in range(4):
+        bg.step(1)
+        be.step(1)
+        # eager work on the same device between replays
+        for i in range(len(cases)):
+            a, e = bg.W(i), be.W(i)
+            assert np.array_equal(a, e), (rep, i, np.abs(a - e).max())
+    bg.step(3)
+    be.step(3)
+    for i in range(len(cases)):
+        assert np.array_equal(bg.state(i)[1], be.state(i)[1])
+    bg.close()
+    be.close()
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    cases = _small_batch(seed=5, count=3)
+    U.ugks_autotune_clear()
+    b1 = U.Batch(cases)
+    i1 = b1.info
+    assert i1["tuned"] == 1 and i1["tune_timings"] > 0
+    sched1 = [(b1.case_info(i)["block_v"], b1.case_info(i)["tile_cells"]) for i in range(len(cases))]
+    path = str(tmp_path / "tune.txt")
+    U.ugks_autotune_save(path)
+    b1.close()
+    U.ugks_autotune_clear()
+    U.ugks_autotune_load(path)
+    b2 = U.Batch(cases)
+    i2 = b2.info
+    assert i2["tune_timings"] == 0
+    assert i2["threads"] == i1["threads"]
+    sched2 = [(b2.case_info(i)["block_v"], b2.case_info(i)["tile_cells"]) for i in range(len(cases))]
+    assert sched2 == sched1
+    b2.close()
+
+
+def test_fixed_schedule_and_mixed_dimension_rejected():
+    cases = _small_batch(seed=9, count=2)
+    b = U.Batch(cases, block_v=256, tile_cells=16)
+    assert b.info["tuned"] == 0
+    assert b.case_info(0)["tile_cells"] == min(16, cases[0].mesh.n_cells)
+    b.close()
+    mixed = [cases[0], uc.sod3d_tets(n=2, nv=8)]
+    with pytest.raises(U.UGKSError) as e:
+        U.Batch(mixed)
+    assert e.value.code == U.UGKS_EINVAL and "case 1" in str(e.value)
