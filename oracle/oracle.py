@@ -68,6 +68,8 @@ def _load():
     lib.oracle_last_error.argtypes = [P]
     lib.oracle_steps_done.restype = i64
     lib.oracle_steps_done.argtypes = [P]
+    lib.oracle_grad_W.restype = None
+    lib.oracle_grad_W.argtypes = [P, P]
     lib.oracle_threads.restype = i32
     lib.oracle_threads.argtypes = []
     _lib = lib
@@ -157,6 +159,13 @@ class Oracle:
         G = np.zeros(self.dim * m)
         self.lib.oracle_ls_coeffs(self.h_, i, _p(G))
         return G.reshape(self.dim, m)
+
+    def grad_W(self):
+        """Least-squares gradients of W at the current state, [nc, D, D+2]."""
+        nw = self.dim + 2
+        g = np.zeros((self.nc, self.dim, nw))
+        self.lib.oracle_grad_W(self.h_, _p(g))
+        return g
 
     @property
     def steps_done(self) -> int:

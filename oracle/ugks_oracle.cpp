@@ -420,6 +420,7 @@ struct oracle_ctx {
   }
 
   int step_once();
+  void macro_grad(const std::vector<double>& Wg, std::vector<double>& gW) const;
 };
 
 extern "C" {
@@ -658,6 +659,32 @@ int oracle_slopes(int D, double rho, const double* U, double lam, const double* 
 }
 
 // ---------------------------------------------------------------------------
+// Least-squares gradients of every conservative component of every cell
+// (step 4), with the ghost rules of R6: the neighbour's value through an
+// interior face, the cell's own value through a wall, the ghost state Wg of
+// a far-field or outflow face.  gW[(i*D + d)*nw + v] = d W_v / d x_d.
+void oracle_ctx::macro_grad(const std::vector<double>& Wg, std::vector<double>& gW) const {
+  const int nw = NW();
+  auto nbW = [&](int64_t i, int64_t f, int v) -> double {
+    if (fbc[f] == BC_INTERIOR) return W[(fL[f] == i ? fR[f] : fL[f]) * nw + v];
+    if (fbc[f] == BC_WALL) return W[i * nw + v];
+    return Wg[f * nw + v];
+  };
+  gW.assign(nc * D * nw, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nc; ++i) {
+    int m = (int)cfaces[i].size();
+    std::vector<double> nb(m);
+    for (int v = 0; v < nw; ++v) {
+      for (int p = 0; p < m; ++p) nb[p] = nbW(i, cfaces[i][p], v);
+      double g[3];
+      ls_grad(i, W[i * nw + v], nb.data(), g);
+      for (int d = 0; d < D; ++d) gW[(i * D + d) * nw + v] = g[d];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One time step (the numbered steps follow the one-step algorithm).
 int oracle_ctx::step_once() {
   const int nw = NW();
@@ -677,26 +704,9 @@ int oracle_ctx::step_once() {
   for (int64_t f = 0; f < nf; ++f)
     if (fbc[f] == BC_FARFIELD || fbc[f] == BC_OUTFLOW) Pg[f] = prim(&Wg[f * nw]);
 
-  // stencil value of a cell field through face f of cell i, for a macroscopic
-  // component v (ghost rules of R6)
-  auto nbW = [&](int64_t i, int64_t f, int v) -> double {
-    if (fbc[f] == BC_INTERIOR) return W[(fL[f] == i ? fR[f] : fL[f]) * nw + v];
-    if (fbc[f] == BC_WALL) return W[i * nw + v];
-    return Wg[f * nw + v];
-  };
   // 4. macroscopic gradients
-  std::vector<double> gW(nc * D * nw);
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < nc; ++i) {
-    int m = (int)cfaces[i].size();
-    std::vector<double> nb(m);
-    for (int v = 0; v < nw; ++v) {
-      for (int p = 0; p < m; ++p) nb[p] = nbW(i, cfaces[i][p], v);
-      double g[3];
-      ls_grad(i, W[i * nw + v], nb.data(), g);
-      for (int d = 0; d < D; ++d) gW[(i * D + d) * nw + v] = g[d];
-    }
-  }
+  std::vector<double> gW;
+  macro_grad(Wg, gW);
 
   // 6.1-6.6 interface equilibrium data of every non-wall face
   struct FaceEq {
@@ -977,6 +987,17 @@ int oracle_ctx::step_once() {
   W.swap(Wn);
   ++steps_done;
   return 0;
+}
+
+// Macroscopic gradients of the current state (steps 3-4 only; nothing advances).
+extern "C" void oracle_grad_W(const oracle_ctx* o, double* gW) {
+  const int nw = o->NW();
+  std::vector<double> Wg(o->nf * nw, 0.0);
+  for (int64_t f = 0; f < o->nf; ++f)
+    if (o->fbc[f] == BC_FARFIELD || o->fbc[f] == BC_OUTFLOW) o->ghost_W(f, &o->W[o->fL[f] * nw], &Wg[f * nw]);
+  std::vector<double> g;
+  o->macro_grad(Wg, g);
+  std::copy(g.begin(), g.end(), gW);
 }
 
 extern "C" const char* oracle_last_error(const oracle_ctx* o) { return o->err.c_str(); }
