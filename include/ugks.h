@@ -143,9 +143,10 @@ typedef struct {
  *   The fused sweep (one pass for reconstruction, interface flux, moment
  *   sums and the first stage) applies when the velocity set is a tensor
  *   product of one 1-D node set symmetric about zero, listed with the first
- *   axis slowest, every cell has at most 4 faces and every boundary face is a
- *   wall.  Otherwise the staged sweep keeps the microscopic gradients and
- *   fluxes of the whole velocity space in device memory.
+ *   axis slowest, and every cell has at most 4 faces (far-field and outflow
+ *   faces read per-step ghost rows holding the ghost Maxwellian).  Otherwise
+ *   the staged sweep keeps the microscopic gradients and fluxes of the whole
+ *   velocity space in device memory.
  *   stream     hipStream_t to enqueue on, or NULL for a library-owned stream.
  *              A caller stream is borrowed, never destroyed.
  */
@@ -263,7 +264,7 @@ void ugks_destroy(ugks_ctx* ctx);
  * other phases flatten the cells, faces or wall faces of every case behind
  * case-offset tables, and the whole step is captured once into a HIP graph
  * and replayed.  Every case must qualify for the fused sweep (a tensor
- * product of one symmetric 1-D node set; interior, periodic and wall faces;
+ * product of one symmetric 1-D node set; any face kinds;
  * at most four faces per cell).
  *
  * The velocity-block size and the cell-tile size of each case, and the
@@ -332,6 +333,69 @@ const char* ugks_batch_last_error(const ugks_batch* batch);
 int ugks_autotune_save(const char* path);
 int ugks_autotune_load(const char* path);
 void ugks_autotune_clear(void);
+
+/*
+ * Learned warm start.  A 9-64-64-9 tanh network maps per-cell features of
+ * the macroscopic state to the nonequilibrium stress and heat flux, and the
+ * initial f of a cell is Grad's 13-moment form about the Maxwellian of W
+ * built from them; this is a Chapman-Enskog-type closure of the BGK-Shakhov
+ * model of Sec. 2.1 learned from the method's own solutions, used to start
+ * the steady-state iteration of Sec. 2.2 closer to its answer.
+ *
+ * Features (9, dimensionless, from W, its least-squares gradient as in the
+ * macroscopic reconstruction, and tau = mu/p):
+ *   tau S_xx, tau S_yy, tau S_xy, tau S_xz, tau S_yz   (S: traceless strain rate)
+ *   L dT/dx / T, L dT/dy / T, L dT/dz / T               (L = tau sqrt(2RT))
+ *   L |grad rho| / rho                                  (local Knudsen number)
+ * Targets / outputs (9): sigma/p for xx yy zz xy xz yz (sigma_ab = int c_a c_b f
+ * - p d_ab; in 2-D the zz entry comes from b) and q/(p sqrt(2RT)) for x y z
+ * (Eq. reduced_heat_flux).  Rows of 9 floats, one row per cell or sample.
+ *
+ * The network: y = out_scale * N(in_scale * x), tanh hidden layers, linear
+ * output; parameters as 5385 floats W1[64][9] b1[64] W2[64][64] b2[64]
+ * W3[9][64] b3[9] (rows are output units).  Inference rounds weights and
+ * layer inputs to bfloat16 and accumulates in FP32 on the matrix cores;
+ * training is FP32 (forward, backward, Adam with beta = 0.9, 0.999,
+ * eps = 1e-8) on the mean over samples of sum_j (N_j - t_j/out_scale_j)^2.
+ *
+ * Ownership as for contexts: the network copies its inputs and owns its
+ * device memory; `stream` is borrowed (NULL: the network makes its own).
+ * on_device = 1: x, t, y are device pointers (e.g. a tensor's data_ptr()).
+ */
+typedef struct ugks_mlp ugks_mlp;
+
+int ugks_mlp_create(const float* params, const float* in_scale, const float* out_scale,
+                    void* stream, ugks_mlp** out);
+/* FP32 parameters, 5385 floats, to host memory */
+int ugks_mlp_get_params(ugks_mlp* net, float* params);
+/* training box: a cell whose features leave [lo, hi] (9 each) keeps the Maxwellian */
+int ugks_mlp_set_box(ugks_mlp* net, const float* lo, const float* hi);
+/* y[rows*9] = network(x[rows*9]) in physical units (bf16 matrix-core inference) */
+int ugks_mlp_forward(ugks_mlp* net, const float* x, int64_t rows, float* y, int32_t on_device);
+/* loss and its gradient (5385 floats, host) over all rows; the parameters are unchanged */
+int ugks_mlp_loss_grad(ugks_mlp* net, const float* x, const float* t, int64_t rows, float* grad,
+                       double* loss, int32_t on_device);
+/* `steps` Adam steps over consecutive slices of `batch` rows (wrapping to the
+ * start when a slice would run past the end); loss_out NULL or steps doubles */
+int ugks_mlp_train(ugks_mlp* net, const float* x, const float* t, int64_t rows, int64_t batch,
+                   int32_t steps, float lr, int32_t on_device, double* loss_out);
+void ugks_mlp_destroy(ugks_mlp* net);
+const char* ugks_mlp_last_error(const ugks_mlp* net);
+
+/*
+ * ugks_snapshot - features and targets of every cell of the current state
+ * (host arrays of n_cells*9 floats, caller's cell order; either may be NULL).
+ */
+int ugks_snapshot(ugks_ctx* ctx, float* features, float* targets);
+
+/*
+ * ugks_warm_start - optionally set W (caller order, as ugks_set_state), then
+ * replace h and b of every cell by the Grad-type distribution from the
+ * network's prediction for its features, or by the Maxwellian of W where the
+ * features leave the training box.  *n_fallback (may be NULL) receives the
+ * number of Maxwellian cells.  The residual normalisation restarts.
+ */
+int ugks_warm_start(ugks_ctx* ctx, const ugks_mlp* net, const double* W, int64_t* n_fallback);
 
 /* Reason for the last failure on ctx (NULL: the last failed ugks_create of this thread). */
 const char* ugks_last_error(const ugks_ctx* ctx);

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libugks.so")
-SOURCES = ["ugks_host.hip", "ugks_kernels.hip", "ugks_sweep.hip"]
+SOURCES = ["ugks_host.hip", "ugks_kernels.hip", "ugks_sweep.hip", "ugks_learned.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

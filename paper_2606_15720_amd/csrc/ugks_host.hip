@@ -6,7 +6,7 @@
 // neighbour or mirror ghost), pads the velocity set with zero-weight points
 // to a multiple of the velocity block, fixes the time step from the CFL bound
 // and allocates every device buffer once.  ugks_step only enqueues kernels.
-#include "ugks_internal.h"
+#include "ugks_host_util.h"
 
 #include <algorithm>
 #include <cmath>
@@ -20,43 +20,11 @@
 #include <sstream>
 
 using namespace ugks;
+using namespace ugks::host;
 
 namespace {
 
 thread_local std::string g_create_error;
-
-struct HipFail {
-  hipError_t e;
-  const char* what;
-};
-
-#define HIP_TRY(call)                              \
-  do {                                             \
-    hipError_t _e = (call);                        \
-    if (_e != hipSuccess) throw HipFail{_e, #call}; \
-  } while (0)
-
-struct InvalidArg {
-  std::string msg;
-};
-
-template <typename T>
-T* dalloc(ugks_ctx* c, size_t n) {
-  if (n == 0) n = 1;
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, n * sizeof(T));
-  if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
-  c->allocations.push_back(p);
-  c->bytes += (int64_t)(n * sizeof(T));
-  return static_cast<T*>(p);
-}
-
-template <typename T>
-T* upload(ugks_ctx* c, const std::vector<T>& v) {
-  T* p = dalloc<T>(c, v.size());
-  if (!v.empty()) HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  return p;
-}
 
 // Solve the D x D SPD normal system by Cholesky; returns false if singular.
 bool chol_inverse(int D, const double* N, double* Ninv) {
@@ -89,9 +57,6 @@ bool chol_inverse(int D, const double* N, double* Ninv) {
   return true;
 }
 
-void fail_if(bool cond, const std::string& msg) {
-  if (cond) throw InvalidArg{msg};
-}
 
 void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas* gas,
            const ugks_bc* bcs, int32_t n_bc, const double* W0, const ugks_options* opt) {
@@ -294,7 +259,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
       }
     }
     for (int64_t f = 0; ok && f < nf; ++f)
-      ok = mesh->face_bc[f] == UGKS_BC_INTERIOR || mesh->face_bc[f] == UGKS_BC_WALL;
+      ok = mesh->face_bc[f] >= UGKS_BC_INTERIOR && mesh->face_bc[f] <= UGKS_BC_OUTFLOW;
     for (int64_t i = 0; ok && i < nc; ++i) ok = nfc[i] <= 4;
     c->fused = ok;
     if (ok) {
@@ -366,15 +331,27 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     //     the constant 1 (or K_xi/(2 lambda_w) for b), so the incoming flux
     //     is the re-emitted wall Maxwellian; the outgoing member's
     //     equilibrium term is switched off by the multiplier 0;
+    //   * a far-field or outflow face's neighbour is a ghost row (rows
+    //     nc+1 ... of h and b, refilled every step with the ghost Maxwellian)
+    //     whose stencil is itself with coefficient 0, i.e. the ghost value
+    //     with zero gradient; the ghost row also enters the least-squares
+    //     stencil of the cell that owns the face, as its mirror-ghost row;
     //   * a missing face (cells with 3 faces) repeats face 0 with S/V = 0.
     const int32_t zero_row = (int32_t)nc;
+    std::vector<int32_t> ghost_row(nf, -1), ffaces;
+    for (int64_t f = 0; f < nf; ++f)
+      if (fbc[f] == UGKS_BC_FARFIELD || fbc[f] == UGKS_BC_OUTFLOW) {
+        ghost_row[f] = (int32_t)(nc + 1 + (int64_t)ffaces.size());
+        ffaces.push_back((int32_t)f);
+      }
     std::vector<int32_t> ci(nc * CRI, 0);
     std::vector<double> cdr(nc * CRD, 0.0);
     auto stencil = [&](int64_t cell, int32_t pad_row, int32_t* cells, double* G /* [d*4 + s] */) {
       int n = 0;
       for (int p = 0; p < nfc[cell]; ++p) {
         int j = cnbr[cell * MAXF + p];
-        if (j < 0) continue;  // a wall row adds nothing to the gradient
+        if (j < 0) j = ghost_row[cface[cell * MAXF + p]];
+        if (j < 0) continue;  // a wall row (the cell's own value) adds nothing to the gradient
         cells[n] = j;
         for (int d = 0; d < 3; ++d) G[d * 4 + n] = lsG[(cell * 3 + d) * MAXF + p];
         ++n;
@@ -400,20 +377,22 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
         fi[0] = f;
         fi[1] = fbc[f];
         fi[2] = (p < nfc[i] && sg > 0.0) ? 1 : 0;
-        fi[3] = j >= 0 ? j : zero_row;
+        const int32_t gr = ghost_row[f];
+        fi[3] = j >= 0 ? j : (gr >= 0 ? gr : zero_row);
         fi[4] = j >= 0 ? stencil(j, j, &fi[5], &fd[10]) : 0;
         if (j < 0)
           for (int r = 0; r < 4; ++r) {
-            fi[5 + r] = zero_row;
+            fi[5 + r] = fi[3];
             for (int d = 0; d < 3; ++d) fd[10 + d * 4 + r] = 0.0;
           }
         for (int d = 0; d < 3; ++d) {
           fd[0 + d] = sg * fnorm[f * 3 + d];
           fd[4 + d] = sg > 0.0 ? fdxL[f * 3 + d] : fdxR[f * 3 + d];
-          fd[7 + d] = sg > 0.0 ? fdxR[f * 3 + d] : fdxL[f * 3 + d];
+          fd[7 + d] = j >= 0 ? (sg > 0.0 ? fdxR[f * 3 + d] : fdxL[f * 3 + d]) : 0.0;
         }
         fd[3] = p < nfc[i] ? farea[f] / vol[i] : 0.0;
-        fd[22] = j >= 0 ? 1.0 : 0.0;  // equilibrium term of the outgoing member
+        // equilibrium term of the outgoing member: none at a wall
+        fd[22] = (j >= 0 || gr >= 0) ? 1.0 : 0.0;
       }
     }
     std::vector<int32_t> vidx(nv);
@@ -433,6 +412,8 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     c->fmesh.vidx = upload(c, vidx);
     c->fmesh.crec_i = upload(c, ci);
     c->fmesh.crec_d = upload(c, cdr);
+    c->fmesh.nff = (int64_t)ffaces.size();
+    c->fmesh.ffaces = upload(c, ffaces);
   }
   c->cell_perm = perm;
   c->face_perm.resize(nf);
@@ -467,13 +448,15 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   } else {
     B.dW = dalloc<double>(c, nc * 5);
   }
-  // row nc of h and b stays zero: the fused sweep's wall faces read it
-  B.h = dalloc<char>(c, (size_t)(nc + 1) * nvp * esz);
+  // row nc of h and b stays zero: the fused sweep's wall faces read it;
+  // rows nc+1 ... are the fused sweep's far-field ghost rows
+  const int64_t rows = nc + 1 + (c->fused ? c->fmesh.nff : 0);
+  B.h = dalloc<char>(c, (size_t)rows * nvp * esz);
   B.ht = dalloc<char>(c, (size_t)nc * nvp * esz);
-  B.b = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)(nc + 1) * nvp * esz) : nullptr;
+  B.b = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)rows * nvp * esz) : nullptr;
   B.bt = c->nr == 2 ? (void*)dalloc<char>(c, (size_t)nc * nvp * esz) : nullptr;
-  HIP_TRY(hipMemset(B.h, 0, (size_t)(nc + 1) * nvp * esz));
-  if (B.b) HIP_TRY(hipMemset(B.b, 0, (size_t)(nc + 1) * nvp * esz));
+  HIP_TRY(hipMemset(B.h, 0, (size_t)rows * nvp * esz));
+  if (B.b) HIP_TRY(hipMemset(B.b, 0, (size_t)rows * nvp * esz));
   if (!c->fused) {
     // the staged sweep keeps every gradient and microscopic flux in HBM
     B.gradh = dalloc<double>(c, (size_t)nc * 3 * nvp);
@@ -591,8 +574,10 @@ void enqueue_step_fused(ugks_ctx* c) {
   // 4 macroscopic reconstruction; 6.1-6.6 interface equilibrium
   TIMED(KK_GRADW, launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
   TIMED(KK_FACE_EQ, launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
-  // 7 wall densities
+  // 7 wall densities; far-field ghost rows
   TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, g, B.h, B.frec, B.flag, s));
+  if (c->fmesh.nff)
+    TIMED(KK_WALL, launch_ghost_rows(D, P, c->fmesh, v, B.frec, B.h, B.b, B.flag, s));
   // Maxwellian axis tables of every face and cell of this step
   TIMED(KK_TABLES, launch_tables(D, m, c->fmesh, g, B.frec, B.prim, B.cs, B.tabs, B.flag, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep
@@ -683,10 +668,10 @@ struct ugks_batch {
   bool own_stream = false;
   std::vector<void*> allocations;
   CaseDev* cases_dev[2] = {nullptr, nullptr};  // even / odd step: q and qn swapped
-  int64_t* offs = nullptr;                    // cell, face, wall, tab offsets, [4][n+1]
+  int64_t* offs = nullptr;                    // cell, face, wall, tab, ghost offsets, [5][n+1]
   int32_t* items = nullptr;
   int64_t nitems = 0, grid = 0;
-  int64_t ncell = 0, nface = 0, nwall = 0, ntab = 0;
+  int64_t ncell = 0, nface = 0, nwall = 0, ntab = 0, nff = 0;
   int32_t* flags_dev = nullptr;  // [4*n]
   double* resid_dev = nullptr;   // [8*n]
   int parity = 0;
@@ -720,6 +705,7 @@ BatchDev batch_dev(const ugks_batch* b, int par) {
   bd.face_off = b->offs + n1;
   bd.wall_off = b->offs + 2 * n1;
   bd.tab_off = b->offs + 3 * n1;
+  bd.ff_off = b->offs + 4 * n1;
   bd.items = b->items;
   bd.nitems = b->nitems;
   return bd;
@@ -817,8 +803,9 @@ void enqueue_batch_step(ugks_batch* b, int par) {
   // 4 macroscopic reconstruction; 6.1-6.6 interface equilibrium
   HIP_TRY(launch_gradW_b(D, bd, b->ncell, s));
   HIP_TRY(launch_face_eq_b(D, bd, b->nface, s));
-  // 7 wall densities
+  // 7 wall densities; far-field ghost rows
   HIP_TRY(launch_wall_rho_b(D, P, bd, b->nwall, s));
+  HIP_TRY(launch_ghost_rows_b(D, P, bd, b->nff, s));
   // Maxwellian axis tables
   HIP_TRY(launch_tables_b(D, bd, b->ntab, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep, one persistent launch
@@ -994,7 +981,7 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
       throw std::pair<int, std::string>(
           UGKS_EUNSUPPORTED, "case " + std::to_string(i) +
                                  ": the batched form needs the fused sweep (symmetric tensor "
-                                 "velocity set, interior/periodic/wall faces, <= 4 faces per cell)");
+                                 "velocity set, at most 4 faces per cell)");
     // flags and residuals of all cases side by side: one copy reads them all
     cc->buf.flag = b->flags_dev + 4 * i;
     cc->buf.resid = b->resid_dev + 8 * i;
@@ -1006,18 +993,20 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
   }
   // case-offset tables
   const int64_t n1 = n + 1;
-  std::vector<int64_t> off(4 * n1, 0);
+  std::vector<int64_t> off(5 * n1, 0);
   for (int32_t i = 0; i < n; ++i) {
     const ugks_ctx* c = b->cases[i];
     off[i + 1] = off[i] + c->nc;
     off[n1 + i + 1] = off[n1 + i] + c->nf;
     off[2 * n1 + i + 1] = off[2 * n1 + i] + c->mesh.nwall;
     off[3 * n1 + i + 1] = off[3 * n1 + i] + (c->nf + c->nc) * (int64_t)c->D * c->fmesh.na;
+    off[4 * n1 + i + 1] = off[4 * n1 + i] + c->fmesh.nff;
   }
   b->ncell = off[n];
   b->nface = off[n1 + n];
   b->nwall = off[2 * n1 + n];
   b->ntab = off[3 * n1 + n];
+  b->nff = off[4 * n1 + n];
   b->offs = balloc<int64_t>(b, off.size());
   HIP_TRY(hipMemcpy(b->offs, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   upload_cases(b);
@@ -1029,6 +1018,7 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
     HIP_TRY(launch_gradW_b(b->D, bd, b->ncell, b->stream));
     HIP_TRY(launch_face_eq_b(b->D, bd, b->nface, b->stream));
     HIP_TRY(launch_wall_rho_b(b->D, b->prec, bd, b->nwall, b->stream));
+    HIP_TRY(launch_ghost_rows_b(b->D, b->prec, bd, b->nff, b->stream));
     HIP_TRY(launch_tables_b(b->D, bd, b->ntab, b->stream));
   }
   if (fixed_bv || fixed_tile) {

@@ -1,0 +1,53 @@
+// Host-side helpers shared by the library's C-ABI sources (not public).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ugks_internal.h"
+
+namespace ugks {
+namespace host {
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIP_TRY(call)                              \
+  do {                                             \
+    hipError_t _e = (call);                        \
+    if (_e != hipSuccess) throw HipFail{_e, #call}; \
+  } while (0)
+
+struct InvalidArg {
+  std::string msg;
+};
+
+template <typename T>
+inline T* dalloc(ugks_ctx* c, size_t n) {
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+  c->allocations.push_back(p);
+  c->bytes += (int64_t)(n * sizeof(T));
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+inline T* upload(ugks_ctx* c, const std::vector<T>& v) {
+  T* p = dalloc<T>(c, v.size());
+  if (!v.empty()) HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+
+inline void fail_if(bool cond, const std::string& msg) {
+  if (cond) throw InvalidArg{msg};
+}
+
+}  // namespace host
+}  // namespace ugks

@@ -85,6 +85,8 @@ struct FusedMesh {
   const int32_t* vidx;      // [nv] packed axis indices of point k (8 bits per axis, first axis low)
   const int32_t* crec_i;    // [nc*CRI]
   const double* crec_d;     // [nc*CRD]
+  const int32_t* ffaces;    // [nff] far-field / outflow faces; face m owns ghost row nc+1+m
+  int64_t nff;
 };
 
 // Schedule of the fused sweep: work item = (cell, velocity block of
@@ -161,6 +163,7 @@ struct BatchDev {
   const int64_t* face_off;  // [n+1] faces
   const int64_t* wall_off;  // [n+1] wall faces
   const int64_t* tab_off;   // [n+1] Maxwellian axis-table entries, (nf+nc)*D*na
+  const int64_t* ff_off;    // [n+1] far-field / outflow faces (ghost rows)
   const int32_t* items;     // [4*nitems] sweep work items: case (-1 = padding), cell, block, 0
   int64_t nitems;
 };
@@ -223,6 +226,9 @@ hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v
 hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
                                   const GasP& g, const void* h, double* frec, const int32_t* flag,
                                   hipStream_t s);
+hipError_t launch_ghost_rows(int D, int prec, const FusedMesh& fm, const DevVel& v,
+                             const double* frec, void* h, void* b, const int32_t* flag,
+                             hipStream_t s);
 
 // batched forms (one launch per phase over every case of a batch)
 hipError_t launch_cell_prep_b(int D, const BatchDev& bd, int64_t ncell, int next, hipStream_t s);
@@ -230,6 +236,7 @@ hipError_t launch_gradW_b(int D, const BatchDev& bd, int64_t ncell, hipStream_t 
 hipError_t launch_face_eq_b(int D, const BatchDev& bd, int64_t nface, hipStream_t s);
 hipError_t launch_wall_rho_b(int D, int prec, const BatchDev& bd, int64_t nwall, hipStream_t s);
 hipError_t launch_tables_b(int D, const BatchDev& bd, int64_t ntab, hipStream_t s);
+hipError_t launch_ghost_rows_b(int D, int prec, const BatchDev& bd, int64_t nff, hipStream_t s);
 hipError_t launch_sweep_b(int D, int prec, const BatchDev& bd, int64_t grid, int threads,
                           hipStream_t s);
 // resident work-groups of the batched sweep per CU at `threads` lanes

@@ -652,8 +652,23 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
       double gr[3] = {0, 0, 0};
       for (int p = 0; p < nfc; ++p) {
         const int j = m.cnbr[L * MAXF + p];
-        if (j < 0) continue;
-        const double dh = ld(h, (int64_t)j * nvp + k) - hl;
+        double hj;
+        if (j >= 0) {
+          hj = ld(h, (int64_t)j * nvp + k);
+        } else {
+          // a wall row (the cell's own value) adds nothing; a far-field or
+          // outflow row is the ghost Maxwellian of that face
+          const int f2 = m.cface[L * MAXF + p];
+          if (m.fbc[f2] == UGKS_BC_WALL) continue;
+          const double* R2 = &frec[(int64_t)f2 * FREC];
+          double c2 = 0.0;
+          for (int d = 0; d < D; ++d) {
+            const double c = v.u[d * nvp + k] - R2[FR_GU + d];
+            c2 += c * c;
+          }
+          hj = R2[FR_GC] * exp(-R2[FR_GLAM] * c2);
+        }
+        const double dh = hj - hl;
         for (int d = 0; d < D; ++d) gr[d] += m.lsG[(L * 3 + d) * MAXF + p] * dh;
       }
       double hf = hl, ugh = 0.0;
@@ -682,6 +697,42 @@ __global__ __launch_bounds__(SWT) void k_wall_rho_inline(DevMesh m, DevVel v, Ga
                                                          const int32_t* flag) {
   __shared__ double red[2 * 16];
   wall_rho_at<D, T>(blockIdx.x, m, v, g, h, frec, flag, red);
+}
+
+// Ghost rows of the far-field / outflow faces: the Maxwellian of the face's
+// ghost state W_g (written by the interface-equilibrium pass), h and, in
+// 2-D, b = K_xi/(2 lambda_g) h, so the sweep reads them as neighbour rows.
+template <int D, typename T>
+__device__ __forceinline__ void ghost_row_at(int64_t m, int64_t nc, const int32_t* __restrict__ ffaces,
+                                             const DevVel& v, const double* __restrict__ frec,
+                                             T* __restrict__ h, T* __restrict__ b,
+                                             const int32_t* flag) {
+  if (*flag) return;
+  const double* R = &frec[(int64_t)ffaces[m] * FREC];
+  const double C = R[FR_GC], lam = R[FR_GLAM];
+  const double U[3] = {R[FR_GU], R[FR_GU + 1], R[FR_GU + 2]};
+  const int64_t row = (nc + 1 + m) * v.nvp;
+  for (int64_t k = threadIdx.x; k < v.nvp; k += blockDim.x) {
+    double hv = 0.0;
+    if (k < v.nv) {
+      double c2 = 0.0;
+      for (int d = 0; d < D; ++d) {
+        const double c = v.u[d * v.nvp + k] - U[d];
+        c2 += c * c;
+      }
+      hv = C * exp(-lam * c2);
+    }
+    st(h, row + k, hv);
+    if (D == 2) st(b, row + k, (3 - D) / (2.0 * lam) * hv);
+  }
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(SWT) void k_ghost_rows(int64_t nc, const int32_t* __restrict__ ffaces,
+                                                    DevVel v, const double* __restrict__ frec,
+                                                    T* __restrict__ h, T* __restrict__ b,
+                                                    const int32_t* flag) {
+  ghost_row_at<D, T>(blockIdx.x, nc, ffaces, v, frec, h, b, flag);
 }
 
 // ---- batched forms: one launch covers every case of a batch ---------------
@@ -738,6 +789,16 @@ __global__ __launch_bounds__(SWT) void k_stage2_q_b(BatchDev bd) {
   stage2_q_cell<D, T>(t - bd.cell_off[c], C.fm, C.v.nvp, C.v.w, C.B.primn, C.B.csn,
                       (const T*)C.B.ht, (const T*)C.B.bt, (T*)C.B.h, (T*)C.B.b, C.B.qn, C.B.flag,
                       L);
+}
+
+// one block per far-field / outflow face of the batch
+template <int D, typename T>
+__global__ __launch_bounds__(SWT) void k_ghost_rows_b(BatchDev bd) {
+  const int64_t t = blockIdx.x;
+  const int c = case_of(bd.ff_off, bd.n, t);
+  const CaseDev& C = bd.cases[c];
+  ghost_row_at<D, T>(t - bd.ff_off[c], C.m.nc, C.fm.ffaces, C.v, C.B.frec, (T*)C.B.h, (T*)C.B.b,
+                     C.B.flag);
 }
 
 // one block per wall face of the batch
@@ -860,6 +921,21 @@ hipError_t launch_stage2_q_b(int D, int prec, const BatchDev& bd, int64_t ncell,
 hipError_t launch_wall_rho_b(int D, int prec, const BatchDev& bd, int64_t nwall, hipStream_t s) {
   if (nwall == 0) return hipSuccess;
   UGKS_DISPATCH_DT(D, prec, k_wall_rho_b<DD, TT><<<(unsigned)nwall, SWT, 0, s>>>(bd));
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost_rows(int D, int prec, const FusedMesh& fm, const DevVel& v,
+                             const double* frec, void* h, void* b, const int32_t* flag,
+                             hipStream_t s) {
+  if (fm.nff == 0) return hipSuccess;
+  UGKS_DISPATCH_DT(D, prec, k_ghost_rows<DD, TT><<<(unsigned)fm.nff, SWT, 0, s>>>(
+      fm.nc, fm.ffaces, v, frec, (TT*)h, (TT*)b, flag));
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost_rows_b(int D, int prec, const BatchDev& bd, int64_t nff, hipStream_t s) {
+  if (nff == 0) return hipSuccess;
+  UGKS_DISPATCH_DT(D, prec, k_ghost_rows_b<DD, TT><<<(unsigned)nff, SWT, 0, s>>>(bd));
   return hipGetLastError();
 }
 

@@ -26,7 +26,12 @@ EXPORTED = [
     "ugks_profile_read", "ugks_batch_create", "ugks_batch_step", "ugks_batch_moments",
     "ugks_batch_get_state", "ugks_batch_case_info", "ugks_batch_info", "ugks_batch_destroy",
     "ugks_batch_last_error", "ugks_autotune_save", "ugks_autotune_load", "ugks_autotune_clear",
+    "ugks_mlp_create", "ugks_mlp_get_params", "ugks_mlp_set_box", "ugks_mlp_forward",
+    "ugks_mlp_loss_grad", "ugks_mlp_train", "ugks_mlp_destroy", "ugks_mlp_last_error",
+    "ugks_snapshot", "ugks_warm_start",
 ]
+
+MLP_NPARAM = 5385
 
 
 class ugks_mesh(C.Structure):
@@ -137,6 +142,26 @@ def load_library(path: str = LIB_PATH):
     lib.ugks_autotune_load.argtypes = [C.c_char_p]
     lib.ugks_autotune_clear.restype = None
     lib.ugks_autotune_clear.argtypes = []
+    lib.ugks_mlp_create.restype = C.c_int
+    lib.ugks_mlp_create.argtypes = [P, P, P, P, C.POINTER(C.c_void_p)]
+    lib.ugks_mlp_get_params.restype = C.c_int
+    lib.ugks_mlp_get_params.argtypes = [P, P]
+    lib.ugks_mlp_set_box.restype = C.c_int
+    lib.ugks_mlp_set_box.argtypes = [P, P, P]
+    lib.ugks_mlp_forward.restype = C.c_int
+    lib.ugks_mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32]
+    lib.ugks_mlp_loss_grad.restype = C.c_int
+    lib.ugks_mlp_loss_grad.argtypes = [P, P, P, C.c_int64, P, P, C.c_int32]
+    lib.ugks_mlp_train.restype = C.c_int
+    lib.ugks_mlp_train.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int32, C.c_float, C.c_int32, P]
+    lib.ugks_mlp_destroy.restype = None
+    lib.ugks_mlp_destroy.argtypes = [P]
+    lib.ugks_mlp_last_error.restype = C.c_char_p
+    lib.ugks_mlp_last_error.argtypes = [P]
+    lib.ugks_snapshot.restype = C.c_int
+    lib.ugks_snapshot.argtypes = [P, P, P]
+    lib.ugks_warm_start.restype = C.c_int
+    lib.ugks_warm_start.argtypes = [P, P, P, C.POINTER(C.c_int64)]
     _lib = lib
     return lib
 
@@ -432,3 +457,82 @@ class Batch:
         bd = np.zeros((c.mesh.n_cells, c.vel.nv))
         ugks_batch_get_state(self.h, i, W, hd, bd)
         return W, hd, bd
+
+
+# ---- learned warm start ----------------------------------------------------
+
+def _f4(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _check_mlp(rc, n=None):
+    if rc != UGKS_OK:
+        msg = load_library().ugks_mlp_last_error(n)
+        raise UGKSError(rc, msg.decode() if msg else "")
+
+
+def ugks_snapshot(h, nc: int):
+    """(features, targets) of every cell, float32 [nc, 9] each."""
+    F = np.zeros((nc, 9), dtype=np.float32)
+    T = np.zeros((nc, 9), dtype=np.float32)
+    _check(load_library().ugks_snapshot(h, _p(F), _p(T)), h)
+    return F, T
+
+
+def ugks_warm_start(h, net, W=None) -> int:
+    """Grad-type f from the network (an ``MLP`` or a raw handle); returns the fallback count."""
+    nf = C.c_int64(0)
+    W = None if W is None else _f8(W)
+    handle = net.h if isinstance(net, MLP) else net
+    _check(load_library().ugks_warm_start(h, handle, _p(W), C.byref(nf)), h)
+    return int(nf.value)
+
+
+class MLP:
+    """Owning wrapper around a ``ugks_mlp`` network on the device."""
+
+    def __init__(self, params, in_scale, out_scale, stream=None):
+        p, si, so = _f4(params), _f4(in_scale), _f4(out_scale)
+        assert p.size == MLP_NPARAM and si.size == 9 and so.size == 9
+        self.h = C.c_void_p()
+        rc = load_library().ugks_mlp_create(_p(p), _p(si), _p(so),
+                                             C.c_void_p(stream) if stream else None, C.byref(self.h))
+        _check_mlp(rc, None)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().ugks_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def params(self):
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check_mlp(load_library().ugks_mlp_get_params(self.h, _p(out)), self.h)
+        return out
+
+    def set_box(self, lo, hi):
+        lo, hi = _f4(lo), _f4(hi)
+        _check_mlp(load_library().ugks_mlp_set_box(self.h, _p(lo), _p(hi)), self.h)
+
+    def forward(self, x):
+        x = _f4(x)
+        y = np.zeros_like(x)
+        _check_mlp(load_library().ugks_mlp_forward(self.h, _p(x), x.shape[0], _p(y), 0), self.h)
+        return y
+
+    def loss_grad(self, x, t):
+        x, t = _f4(x), _f4(t)
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        loss = C.c_double(0.0)
+        _check_mlp(load_library().ugks_mlp_loss_grad(self.h, _p(x), _p(t), x.shape[0], _p(g),
+                                                     C.byref(loss), 0), self.h)
+        return float(loss.value), g
+
+    def train(self, x, t, batch: int, steps: int, lr: float):
+        x, t = _f4(x), _f4(t)
+        losses = np.zeros(steps)
+        _check_mlp(load_library().ugks_mlp_train(self.h, _p(x), _p(t), x.shape[0], int(batch),
+                                                 int(steps), float(lr), 0, _p(losses)), self.h)
+        return losses

@@ -34,7 +34,8 @@ def _small_batch(seed=7, count=6):
 
 
 def test_batch_cases_follow_the_oracle():
-    cases = _small_batch()
+    # uneven cavities and Couette flows, plus a channel with far-field ends
+    cases = _small_batch() + [uc.channel2d(n=6, nv=10, kn=0.1)]
     print("shapes", [(c.mesh.n_cells, c.vel.nv) for c in cases], flush=True)
     b = U.Batch(cases)
     info = b.info

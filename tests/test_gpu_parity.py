@@ -163,3 +163,18 @@ def test_numeric_failure_is_reported_and_state_kept():
     np.testing.assert_array_equal(W2, bad)
     np.testing.assert_array_equal(h2, h)
     s.close()
+
+
+@pytest.mark.parametrize("flags", [0, STAGED], ids=["fused", "staged"])
+@pytest.mark.parametrize("which", ["channel2d", "sphere3d"])
+def test_farfield_parity(which, flags):
+    """Far-field inflow/outflow faces (ghost states of R16): the fused sweep
+    reads them as per-step ghost rows, the staged sweep in place."""
+    if which == "channel2d":
+        case, steps = uc.channel2d(n=10, nv=12, kn=0.05), 20
+    else:
+        case, steps = uc.sphere_mach5(n_ang=2, n_rad=3, nv=8, first=0.5), 4
+    s = Solver(case, flags=flags)
+    assert s.info["fused"] == (0 if flags & STAGED else 1)
+    s.close()
+    _compare_step(case, steps, flags=flags)

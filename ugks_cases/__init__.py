@@ -19,5 +19,5 @@ from .velocity import Velocity, midpoint_grid, gauss_hermite_grid  # noqa: F401
 from .configs import (  # noqa: F401
     Gas, BC, Case, BC_INTERIOR, BC_WALL, BC_FARFIELD, BC_OUTFLOW,
     hard_sphere_mu_ref, cavity2d, couette2d, sod3d_tets, batch_cases,
-    sphere_mach5, make_case, uniform_W, maxwellian_box_case,
+    sphere_mach5, channel2d, make_case, uniform_W, maxwellian_box_case,
 )

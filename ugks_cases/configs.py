@@ -146,7 +146,22 @@ def batch_cases(seed: int = 4, count: int = 64, n_range=(16, 96), nv_range=(16, 
     return out
 
 
-def sphere_mach5(n_ang: int = 11, n_rad: int = 23, nv: int = 28, a: float = 11.0,
+def channel2d(n: int = 16, nv: int = 16, a: float = 4.0, kn: float = 0.05, u_in: float = 0.3,
+              cfl: float = 0.8) -> Case:
+    """2-D channel: far field on the left (inflow rho = 1, U = (u_in, 0), T = 1)
+    and on the right (the same free stream, so it acts as an outflow there),
+    walls at rest at y = 0 and y = 1; gas initially at rest."""
+    mesh = quad_mesh(n, n, wall_ids=(0, 1, 0, 1), name=f"channel{n}")
+    side = mesh.face_bc_id == 1
+    mesh.face_bc = np.where(side, BC_FARFIELD, mesh.face_bc).astype(mesh.face_bc.dtype)
+    vel = midpoint_grid(nv, a, 2)
+    bcs = [BC(BC_WALL, 1.0, (0.0, 0.0, 0.0), 1.0), BC(BC_FARFIELD, 1.0, (u_in, 0.0, 0.0), 1.0)]
+    gas = Gas(mu_ref=hard_sphere_mu_ref(kn), cfl=cfl)
+    W0 = uniform_W(mesh.n_cells, 2, 1.0, (0.0, 0.0), 1.0)
+    return Case(f"channel2d_n{n}_v{nv * nv}_kn{kn}", mesh, vel, gas, bcs, W0, 0, {"kn": kn})
+
+
+def sphere_mach5(n_ang: int = 8, n_rad: int = 22, nv: int = 28, a: float = 11.0,
                  kn: float = 0.01, mach: float = 5.0, first: float = 0.02) -> Case:
     """Mach-5 flow along +x over the unit sphere (far field at r = 6).
 

@@ -295,10 +295,11 @@ def cubed_sphere_shell(n_ang: int = 11, n_rad: int = 23, *, r0: float = 1.0, r1:
     The sphere is split into the six faces of a cube, each gnomonically
     projected and divided into n_ang x n_ang patches; radially there are n_rad
     layers with first thickness ``first`` and a constant growth ratio chosen so
-    the layers end at r1.  Each hexahedral (patch x layer) element is split into
-    6 Kuhn tets over a global vertex numbering whose ordering is the same on
-    both sides of every shared quad, so the tet faces conform.  Tags: the inner
-    sphere is BC row 0 (wall), the outer sphere row 1 (far field).
+    the layers end at r1.  Each hexahedral (patch x layer) element gets a
+    centroid vertex and 12 tets, one per triangle of its quads, each quad cut
+    along the diagonal through its smallest global vertex id, so the tets
+    conform: 72 n_ang^2 n_rad cells.  Tags: the inner sphere is BC row 0
+    (wall), the outer sphere row 1 (far field).
     """
     # radial distribution with geometric growth
     def total(q):
@@ -349,12 +350,29 @@ def cubed_sphere_shell(n_ang: int = 11, n_rad: int = 23, *, r0: float = 1.0, r1:
     ns = surf.shape[0]
     verts = (radii[:, None, None] * surf[None, :, :]).reshape(-1, 3)
     gid = lambda layer, s: layer * ns + s  # noqa: E731
+    # each hexahedral (patch x layer) element: a centroid vertex and 12 tets,
+    # one per triangle of its six quads, every quad cut along the diagonal
+    # through its smallest global vertex id (so both hexes sharing a quad cut
+    # it the same way and the tets conform)
+    hex_faces = ((0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7))
     tets = []
+    centroids = []
+    nlat = verts.shape[0]
     for quad in quads:
         for layer in range(n_rad):
-            # hex vertices: bottom quad (layer) then top quad (layer+1)
             hexv = [gid(layer, s) for s in quad] + [gid(layer + 1, s) for s in quad]
-            tets.extend(_split_hex_by_global_order(hexv, verts))
+            cid = nlat + len(centroids)
+            centroids.append(verts[hexv].mean(axis=0))
+            for fq in hex_faces:
+                q4 = [hexv[x] for x in fq]
+                k = int(np.argmin(q4))
+                if k % 2 == 0:
+                    tris = ((q4[0], q4[1], q4[2]), (q4[0], q4[2], q4[3]))
+                else:
+                    tris = ((q4[1], q4[2], q4[3]), (q4[1], q4[3], q4[0]))
+                for t3 in tris:
+                    tets.append([t3[0], t3[1], t3[2], cid])
+    verts = np.concatenate([verts, np.array(centroids)])
     tets = np.array(tets, dtype=np.int64)
     p = verts[tets]
     s6 = np.einsum("ti,ti->t", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])
