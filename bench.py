@@ -105,6 +105,32 @@ def run_cpu_baseline(n: int):
                        f"({case.mesh.n_cells} tets) x 24^3 velocities, {t:.1f} s")
 
 
+def run_warm_start(args):
+    """Time to a steady density residual, plain FP64 against the learned start."""
+    import ugks_cases as uc
+    from paper_2606_15720_amd import warmstart as WS
+
+    na, nr = (int(x) for x in args.ws_mesh.split(","))
+    a = 3.0 * args.ws_mach  # velocity box half-width (units sqrt(2RT_inf))
+    fine = uc.sphere_mach5(n_ang=na, n_rad=nr, nv=args.ws_nv, a=a, kn=args.ws_kn, mach=args.ws_mach,
+                           first=0.05)
+    coarse = uc.sphere_mach5(n_ang=na, n_rad=nr, nv=args.ws_nv_predictor, a=args.ws_a_predictor,
+                             kn=args.ws_kn, mach=args.ws_mach, first=0.05)
+    t0 = time.perf_counter()
+
+    def log(*x):
+        print(f"[{time.perf_counter() - t0:7.1f}s]", *x, flush=True)
+
+    out = WS.time_to_residual(fine, coarse, target=args.ws_target, max_steps=args.ws_max_steps,
+                              predictor_target=args.ws_predictor_target, log=log,
+                              arms_run=tuple(args.ws_arms.split(",")))
+    out["metric"] = "time to 1e-6 density residual (s)"
+    out["reconstruction"] = "first order (no limiter: unlimited slopes fail at this Mach number)"
+    out["mach"] = args.ws_mach
+    out["kn"] = args.ws_kn
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +139,20 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=14)
+    ap.add_argument("--warm-start", action="store_true",
+                    help="instead of the throughput line, the time to a 1e-6 density residual on "
+                         "the reduced sphere: plain FP64 against predictor + learned warm start")
+    ap.add_argument("--ws-mesh", default="4,10", help="sphere patches per cube edge, radial layers")
+    ap.add_argument("--ws-nv", type=int, default=24, help="velocity points per axis (fine)")
+    ap.add_argument("--ws-nv-predictor", type=int, default=16)
+    ap.add_argument("--ws-a-predictor", type=float, default=7.5,
+                    help="velocity box half-width of the predictor run")
+    ap.add_argument("--ws-predictor-target", type=float, default=5e-6)
+    ap.add_argument("--ws-mach", type=float, default=3.0)
+    ap.add_argument("--ws-kn", type=float, default=0.01)
+    ap.add_argument("--ws-target", type=float, default=1e-6)
+    ap.add_argument("--ws-max-steps", type=int, default=60000)
+    ap.add_argument("--ws-arms", default="plain64,maxwell32,learned32,learned64")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="instead of the step, copy this many GiB device-to-device with a plain "
                          "copy kernel (calibrates HBM byte counters)")
@@ -126,6 +166,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_per_launch": n * 8, "launches": 3}), flush=True)
+        return
+    if args.warm_start:
+        run_warm_start(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

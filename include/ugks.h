@@ -140,6 +140,10 @@ typedef struct {
  *              bit 2: keep the caller's cell order internally (by default
  *                     cells are renumbered along a Z-order curve of their
  *                     centroids; inputs and outputs always use the caller's order).
+ *              bit 4: first-order reconstruction: every least-squares gradient
+ *                     (Sec. 2.2 steps 4 and 5) is zero, so each face sees the
+ *                     piecewise-constant states of its two cells; robust where
+ *                     unlimited second-order slopes overshoot (strong shocks).
  *   The fused sweep (one pass for reconstruction, interface flux, moment
  *   sums and the first stage) applies when the velocity set is a tensor
  *   product of one 1-D node set symmetric about zero, listed with the first

@@ -68,6 +68,8 @@ def _load():
     lib.oracle_last_error.argtypes = [P]
     lib.oracle_steps_done.restype = i64
     lib.oracle_steps_done.argtypes = [P]
+    lib.oracle_set_order.restype = None
+    lib.oracle_set_order.argtypes = [P, i32]
     lib.oracle_grad_W.restype = None
     lib.oracle_grad_W.argtypes = [P, P]
     lib.oracle_threads.restype = i32
@@ -87,7 +89,7 @@ def _f8(a):
 class Oracle:
     """One oracle context for a ``ugks_cases.Case``."""
 
-    def __init__(self, case, dt: float | None = None):
+    def __init__(self, case, dt: float | None = None, order: int = 2):
         lib = _load()
         m = case.mesh.contiguous()
         v = case.vel
@@ -113,6 +115,8 @@ class Oracle:
         if not self.h_:
             raise ValueError("oracle_create rejected the case")
         self.lib = lib
+        if order == 1:
+            lib.oracle_set_order(self.h_, 1)
 
     def __del__(self):
         if getattr(self, "h_", None):

@@ -371,7 +371,11 @@ struct oracle_ctx {
 
   // Gradient of a cell field given per-face neighbour values (step 4/5).
   // nb[p] is the stencil value through face p of cell i.
-  void ls_grad(int64_t i, double vi, const double* nb, double* g) const {
+  void ls_grad(int64_t i, double vi, const double* nb, double* g, bool exact = false) const {
+    if (first_order && !exact) {  // piecewise-constant reconstruction
+      for (int d = 0; d < D; ++d) g[d] = 0.0;
+      return;
+    }
     int m = (int)cfaces[i].size();
     const std::vector<double>& G = lsG[i];
     for (int d = 0; d < D; ++d) {
@@ -420,7 +424,8 @@ struct oracle_ctx {
   }
 
   int step_once();
-  void macro_grad(const std::vector<double>& Wg, std::vector<double>& gW) const;
+  bool first_order = false;  // zero every least-squares gradient
+  void macro_grad(const std::vector<double>& Wg, std::vector<double>& gW, bool exact = false) const;
 };
 
 extern "C" {
@@ -663,7 +668,7 @@ int oracle_slopes(int D, double rho, const double* U, double lam, const double* 
 // (step 4), with the ghost rules of R6: the neighbour's value through an
 // interior face, the cell's own value through a wall, the ghost state Wg of
 // a far-field or outflow face.  gW[(i*D + d)*nw + v] = d W_v / d x_d.
-void oracle_ctx::macro_grad(const std::vector<double>& Wg, std::vector<double>& gW) const {
+void oracle_ctx::macro_grad(const std::vector<double>& Wg, std::vector<double>& gW, bool exact) const {
   const int nw = NW();
   auto nbW = [&](int64_t i, int64_t f, int v) -> double {
     if (fbc[f] == BC_INTERIOR) return W[(fL[f] == i ? fR[f] : fL[f]) * nw + v];
@@ -678,7 +683,7 @@ void oracle_ctx::macro_grad(const std::vector<double>& Wg, std::vector<double>& 
     for (int v = 0; v < nw; ++v) {
       for (int p = 0; p < m; ++p) nb[p] = nbW(i, cfaces[i][p], v);
       double g[3];
-      ls_grad(i, W[i * nw + v], nb.data(), g);
+      ls_grad(i, W[i * nw + v], nb.data(), g, exact);
       for (int d = 0; d < D; ++d) gW[(i * D + d) * nw + v] = g[d];
     }
   }
@@ -989,14 +994,18 @@ int oracle_ctx::step_once() {
   return 0;
 }
 
-// Macroscopic gradients of the current state (steps 3-4 only; nothing advances).
+// Reconstruction order: 1 = first order (all gradients zero), 2 = least squares.
+extern "C" void oracle_set_order(oracle_ctx* o, int order) { o->first_order = order == 1; }
+
+// Least-squares gradients of the current state (steps 3-4 only; nothing
+// advances), whatever the reconstruction order.
 extern "C" void oracle_grad_W(const oracle_ctx* o, double* gW) {
   const int nw = o->NW();
   std::vector<double> Wg(o->nf * nw, 0.0);
   for (int64_t f = 0; f < o->nf; ++f)
     if (o->fbc[f] == BC_FARFIELD || o->fbc[f] == BC_OUTFLOW) o->ghost_W(f, &o->W[o->fL[f] * nw], &Wg[f * nw]);
   std::vector<double> g;
-  o->macro_grad(Wg, g);
+  o->macro_grad(Wg, g, true);
   std::copy(g.begin(), g.end(), gW);
 }
 

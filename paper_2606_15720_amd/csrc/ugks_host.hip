@@ -221,6 +221,14 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
         lsG[(i * 3 + d) * MAXF + p] = s;
       }
   }
+  // first-order reconstruction: every gradient of the step, macroscopic and
+  // microscopic, is zero (piecewise-constant states on both sides of each
+  // face); the true coefficients are kept for the warm start's features
+  std::vector<double> lsG_true;
+  if (opt && (opt->flags & 16)) {
+    lsG_true = lsG;
+    std::fill(lsG.begin(), lsG.end(), 0.0);
+  }
   // ---- velocity set -----------------------------------------------------
   const int64_t nvp = c->nvp;
   std::vector<double> u(3 * nvp, 0.0), w(nvp, 0.0), u2(nvp, 0.0);
@@ -294,6 +302,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   m.cnbr = upload(c, cnbr);
   m.csign = upload(c, csign);
   m.lsG = upload(c, lsG);
+  c->lsG_exact = lsG_true.empty() ? m.lsG : upload(c, lsG_true);
   m.fL = upload(c, fL);
   m.fR = upload(c, fR);
   m.fbc = upload(c, fbc);

@@ -261,6 +261,7 @@ struct ugks_ctx {
   std::vector<int64_t> face_perm;   // library face f -> caller face
   std::vector<int64_t> vel_perm;    // library velocity k -> caller velocity (k < nv)
   ugks::DevMesh mesh{};
+  const double* lsG_exact = nullptr;  // least-squares coefficients even under first-order reconstruction
   ugks::DevVel vel{};
   ugks::DevBC* bcs = nullptr;
   ugks::StepBuffers buf{};

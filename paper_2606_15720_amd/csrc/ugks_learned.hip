@@ -723,7 +723,9 @@ int ugks_snapshot(ugks_ctx* c, float* feat, float* targ) {
     float* fd = dalloc<float>(c, (size_t)nc * FS);
     float* td = dalloc<float>(c, (size_t)nc * FS);
     HIP_TRY(launch_prims(D, c->mesh, c->gas, B.W, B.prim, B.flag, 0, s));
-    HIP_TRY(launch_gradW(D, c->mesh, c->bcs, c->gas, B.W, B.gW, B.flag, s));
+    DevMesh mg = c->mesh;
+    mg.lsG = c->lsG_exact;  // features use the true gradient at any reconstruction order
+    HIP_TRY(launch_gradW(D, mg, c->bcs, c->gas, B.W, B.gW, B.flag, s));
     const unsigned g1 = (unsigned)((nc + 127) / 128);
     if (D == 2) hipLaunchKernelGGL(k_features<2>, dim3(g1), dim3(128), 0, s, nc, c->gas, B.W, B.gW, fd);
     else hipLaunchKernelGGL(k_features<3>, dim3(g1), dim3(128), 0, s, nc, c->gas, B.W, B.gW, fd);
@@ -776,7 +778,9 @@ int ugks_warm_start(ugks_ctx* c, const ugks_mlp* net, const double* W, int64_t* 
     int32_t* cnt = dalloc<int32_t>(c, 1);
     HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
     HIP_TRY(launch_prims(D, c->mesh, c->gas, B.W, B.prim, B.flag, 0, s));
-    HIP_TRY(launch_gradW(D, c->mesh, c->bcs, c->gas, B.W, B.gW, B.flag, s));
+    DevMesh mg = c->mesh;
+    mg.lsG = c->lsG_exact;  // features use the true gradient at any reconstruction order
+    HIP_TRY(launch_gradW(D, mg, c->bcs, c->gas, B.W, B.gW, B.flag, s));
     const unsigned g1 = (unsigned)((nc + 127) / 128);
     if (D == 2) hipLaunchKernelGGL(k_features<2>, dim3(g1), dim3(128), 0, s, nc, c->gas, B.W, B.gW, fd);
     else hipLaunchKernelGGL(k_features<3>, dim3(g1), dim3(128), 0, s, nc, c->gas, B.W, B.gW, fd);

@@ -138,3 +138,150 @@ def train(F, T, *, seed=0, steps=2000, batch=512, lr=3e-3, lr_final=3e-4, box_ma
         rate = lr * (lr_final / lr) ** (k / 3.0)
         losses.append(net.train(F, T, batch, steps // 4, rate))
     return net, np.concatenate(losses)
+
+
+# ---------------------------------------------------------------------------
+# time to a steady residual: plain start against predictor + learned start
+
+def run_to_residual(solver, target, max_steps, chunk=500, log=None, label=""):
+    """Step until the density residual (RMS dRho / RMS rho per step) <= target.
+
+    Returns (steps, final residual, reached).  Steps are taken in chunks; the
+    check uses the last step of each chunk, so `steps` is rounded up to the
+    chunk.  `log(label, steps, residual)` is called after every chunk.
+    """
+    done = 0
+    r = float("inf")
+    while done < max_steps:
+        n = min(chunk, max_steps - done)
+        r = solver.step(n)[1]
+        done += n
+        if log:
+            log(label, done, r)
+        if r <= target:
+            return done, r, True
+    return done, r, False
+
+
+def field_errors(W, Wref, dim):
+    """max and RMS relative errors of rho, |U| (scaled by the reference speed
+    range) and T between two states."""
+    def prims(X):
+        rho = X[:, 0]
+        U = X[:, 1:dim + 1] / rho[:, None]
+        e = X[:, dim + 1] / rho - 0.5 * np.sum(U * U, axis=1)
+        return rho, U, e / 1.5
+    r1, u1, t1 = prims(np.asarray(W))
+    r0, u0, t0 = prims(np.asarray(Wref))
+    us = np.sqrt(np.max(np.sum(u0 * u0, axis=1))) + 1e-300
+    out = {}
+    for name, a, b, s in (("rho", r1, r0, np.abs(r0)), ("T", t1, t0, np.abs(t0))):
+        e = np.abs(a - b) / s
+        out[name] = {"max": float(e.max()), "rms": float(np.sqrt(np.mean(e * e)))}
+    e = np.sqrt(np.sum((u1 - u0) ** 2, axis=1)) / us
+    out["U"] = {"max": float(e.max()), "rms": float(np.sqrt(np.mean(e * e)))}
+    return out
+
+
+def training_cases(seed: int = 4):
+    """2-D runs in the spirit of the batched workload (cavities and Couette
+    flows over a range of Kn) plus channels with far-field inflow at
+    sub- to supersonic speeds, so the training set also holds shocks and
+    expansions.  Returns (case, first_order, snapshot steps) triples."""
+    import ugks_cases as uc
+    rng = np.random.default_rng(seed)
+    out = []
+    for kn in (0.01, 0.05, 0.2, 1.0):
+        out.append((uc.cavity2d(n=24, nv=20, kn=kn, lid=float(rng.uniform(0.15, 0.6))), False))
+    for kn, top in ((0.01, 0.15), (0.1, 0.5), (0.5, 1.0)):
+        out.append((uc.couette2d(n=24, nv=20, kn=kn, top=top), False))
+    for kn, u in ((0.01, 0.3), (0.05, 1.2), (0.01, 2.4), (0.1, 2.4)):
+        a = 4.0 + 1.5 * u
+        out.append((uc.channel2d(n=24, nv=20, a=a, kn=kn, u_in=u), True))
+    return [(c, fo, (200, 600, 1500, 3000)) for c, fo in out]
+
+
+def build_training_set(seed: int = 4, copies: int = 3, log=None):
+    """Snapshots of the training runs (library kernels), rotated copies added."""
+    Fs, Ts = [], []
+    for case, first_order, stops in training_cases(seed):
+        s = U.Solver(case, flags=16 if first_order else 0)
+        done = 0
+        for k in stops:
+            s.step(k - done)
+            done = k
+            F, T = U.ugks_snapshot(s.h, case.mesh.n_cells)
+            Fs.append(F)
+            Ts.append(T)
+        s.close()
+        if log:
+            log("training run", case.name, done)
+    F, T = np.concatenate(Fs), np.concatenate(Ts)
+    return augment(F, T, copies, seed)
+
+
+def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e-4,
+                     max_steps=60000, chunk=1000, flags=16, train_seed=4, log=None,
+                     arms_run=("plain64", "maxwell32", "learned32", "learned64")):
+    """Plain FP64 from the initial state against predictor + learned warm start.
+
+    Arms (all to a density residual <= target, wall time from creation):
+      plain64    FP64 from the case's own initial state;
+      maxwell32  FP32 from the predictor's W with the Maxwellian f (ablation);
+      learned32  FP32 from the predictor's W with the network's Grad-type f;
+      learned64  FP64 from the predictor's W with the network's Grad-type f.
+    The predictor is an FP32 run on the coarse velocity set to
+    `predictor_target`; its time is charged to every arm that uses it.  The
+    network is trained beforehand on snapshots of 2-D runs (its time is
+    reported apart: it is trained once, not per case).
+    """
+    import time
+    out = {"case": case_fine.name, "n_cells": case_fine.mesh.n_cells, "nv": case_fine.vel.nv,
+           "nv_predictor": case_coarse.vel.nv, "target": target, "flags": flags}
+    t0 = time.perf_counter()
+    F, T = build_training_set(train_seed, log=log)
+    t1 = time.perf_counter()
+    net, losses = train(F, T, seed=train_seed, steps=4000, batch=1024)
+    t2 = time.perf_counter()
+    out["training"] = {"samples": int(len(F)), "snapshot_s": t1 - t0, "train_s": t2 - t1,
+                       "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+    arms = {}
+
+    def arm(name, precision, W0=None, warm=False, extra_s=0.0):
+        t = time.perf_counter()
+        case = case_fine
+        if W0 is not None:
+            case = type(case_fine)(case_fine.name, case_fine.mesh, case_fine.vel, case_fine.gas,
+                                   case_fine.bcs, W0, case_fine.steps, case_fine.meta)
+        s = U.Solver(case, precision=precision, flags=flags)
+        nfall = None
+        if warm:
+            nfall = U.ugks_warm_start(s.h, net)
+        steps, r, ok = run_to_residual(s, target, max_steps, chunk, log, name)
+        W = s.W()
+        s.close()
+        dt = time.perf_counter() - t
+        arms[name] = {"precision": precision, "steps": steps, "residual": r, "reached": ok,
+                      "seconds": dt + extra_s, "seconds_without_predictor": dt,
+                      "fallback_cells": nfall}
+        return W
+
+    Wref = arm("plain64", U.UGKS_FP64) if "plain64" in arms_run else None
+    t = time.perf_counter()
+    p = U.Solver(case_coarse, precision=U.UGKS_FP32, flags=flags)
+    psteps, pr, pok = run_to_residual(p, predictor_target, max_steps, chunk, log, "predictor")
+    Wp = p.W()
+    p.close()
+    tp = time.perf_counter() - t
+    out["predictor"] = {"steps": psteps, "residual": pr, "reached": pok, "seconds": tp}
+    D = case_fine.mesh.dim
+    for name, prec, warm in (("maxwell32", U.UGKS_FP32, False), ("learned32", U.UGKS_FP32, True),
+                             ("learned64", U.UGKS_FP64, True)):
+        if name not in arms_run:
+            continue
+        W = arm(name, prec, Wp, warm, tp)
+        if Wref is not None:
+            arms[name]["field_error_vs_plain64"] = field_errors(W, Wref, D)
+    out["arms"] = arms
+    net.close()
+    return out

@@ -168,3 +168,35 @@ def test_warm_start_matches_oracle_grad_distribution(which):
     assert np.abs(Wg - Wo).max() / np.abs(Wo).max() <= 1e-12
     net.close()
     s.close()
+
+
+def test_trained_network_beats_the_maxwellian_start():
+    """What the trained network gains: a rarefied cavity (Kn = 0.1) restarted
+    on a fine velocity set from a coarse-velocity solution converges faster
+    from the network's Grad-type f than from the Maxwellian of the same W.
+    The network is trained here, on the GPU, on snapshots of other runs."""
+    F, T = WS.build_training_set(4)
+    net, losses = WS.train(F, T, seed=4, steps=4000, batch=1024)
+    assert losses[-1] < 0.2 * losses[0]
+    fine = uc.cavity2d(n=24, nv=28, kn=0.1, lid=0.5)
+    coarse = uc.cavity2d(n=24, nv=12, kn=0.1, lid=0.5)
+    p = U.Solver(coarse)
+    _, r, ok = WS.run_to_residual(p, 1e-6, 20000, 500)
+    assert ok
+    Wp = p.W()
+    p.close()
+    hist = {}
+    for warm in (False, True):
+        case = uc.Case(fine.name, fine.mesh, fine.vel, fine.gas, fine.bcs, Wp, 0, fine.meta)
+        s = U.Solver(case)
+        if warm:
+            assert U.ugks_warm_start(s.h, net) == 0  # every cell inside the training box
+        rs = []
+        for n in (400, 400, 800):
+            rs.append(s.step(n)[1])
+        hist[warm] = rs
+        s.close()
+    print("residual after 400/800/1600 steps: maxwell", hist[False], "learned", hist[True], flush=True)
+    assert hist[True][0] < 0.5 * hist[False][0]
+    assert hist[True][2] < 0.5 * hist[False][2]
+    net.close()

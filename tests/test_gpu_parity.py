@@ -42,10 +42,11 @@ def _normwise_F(a, b):
 
 
 STAGED = 2  # ugks_options.flags bit: force the staged (unfused) sweep
+FIRST_ORDER = 16  # ugks_options.flags bit: first-order reconstruction
 
 
 def _compare_step(case, steps, flags=0, tol=TOL):
-    o = Oracle(case)
+    o = Oracle(case, order=1 if flags & FIRST_ORDER else 2)
     s = Solver(case, flags=flags)
     assert s.dt == pytest.approx(o.dt, rel=1e-14)
     done = 0
@@ -177,4 +178,16 @@ def test_farfield_parity(which, flags):
     s = Solver(case, flags=flags)
     assert s.info["fused"] == (0 if flags & STAGED else 1)
     s.close()
+    _compare_step(case, steps, flags=flags)
+
+
+@pytest.mark.parametrize("flags", [FIRST_ORDER, FIRST_ORDER | STAGED], ids=["fused", "staged"])
+@pytest.mark.parametrize("which", ["cavity2d", "sphere3d"])
+def test_first_order_parity(which, flags):
+    """First-order reconstruction (all gradients zero) against the oracle run
+    at the same order; the sphere at Mach 5 from an impulsive start."""
+    if which == "cavity2d":
+        case, steps = uc.cavity2d(n=8, nv=12, kn=0.05), 20
+    else:
+        case, steps = uc.sphere_mach5(n_ang=2, n_rad=3, nv=10, first=0.5), 6
     _compare_step(case, steps, flags=flags)
