@@ -355,27 +355,39 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
       }
     std::vector<int32_t> ci(nc * CRI, 0);
     std::vector<double> cdr(nc * CRD, 0.0);
-    auto stencil = [&](int64_t cell, int32_t pad_row, int32_t* cells, double* G /* [d*4 + s] */) {
-      int n = 0;
-      for (int p = 0; p < nfc[cell]; ++p) {
-        int j = cnbr[cell * MAXF + p];
-        if (j < 0) j = ghost_row[cface[cell * MAXF + p]];
-        if (j < 0) continue;  // a wall row (the cell's own value) adds nothing to the gradient
-        cells[n] = j;
-        for (int d = 0; d < 3; ++d) G[d * 4 + n] = lsG[(cell * 3 + d) * MAXF + p];
-        ++n;
+    // Stencil slot p of a cell is its face p: the neighbour's row with the
+    // least-squares coefficients of that face, the ghost row of a far-field
+    // face, or the zero row with coefficient 0 at a wall (the wall ghost is the
+    // cell's own value and adds nothing); slots past the cell's faces carry
+    // the cell itself with coefficient 0.  So slot p of the cell's own stencil
+    // is also the neighbour row read through face p.
+    auto stencil = [&](int64_t cell, int32_t* cells, double* G /* [d*4 + s] */) {
+      for (int p = 0; p < 4; ++p) {
+        int32_t row = (int32_t)cell;
+        bool coef = false;
+        if (p < nfc[cell]) {
+          const int f = cface[cell * MAXF + p];
+          const int j = cnbr[cell * MAXF + p];
+          if (j >= 0) {
+            row = j;
+            coef = true;
+          } else if (ghost_row[f] >= 0) {
+            row = ghost_row[f];
+            coef = true;
+          } else {
+            row = zero_row;
+          }
+        }
+        cells[p] = row;
+        for (int d = 0; d < 3; ++d) G[d * 4 + p] = coef ? lsG[(cell * 3 + d) * MAXF + p] : 0.0;
       }
-      for (int r = n; r < 4; ++r) {
-        cells[r] = pad_row;
-        for (int d = 0; d < 3; ++d) G[d * 4 + r] = 0.0;
-      }
-      return n;
     };
     for (int64_t i = 0; i < nc; ++i) {
       int32_t* I = &ci[i * CRI];
       double* Dd = &cdr[i * CRD];
       I[0] = nfc[i];
-      I[1] = stencil(i, (int32_t)i, &I[2], Dd);
+      I[1] = 4;
+      stencil(i, &I[2], Dd);
       for (int p = 0; p < 4; ++p) {
         const int pp = p < nfc[i] ? p : 0;
         int32_t* fi = &I[CRI_F0 + CRI_FS * p];
@@ -388,12 +400,25 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
         fi[2] = (p < nfc[i] && sg > 0.0) ? 1 : 0;
         const int32_t gr = ghost_row[f];
         fi[3] = j >= 0 ? j : (gr >= 0 ? gr : zero_row);
-        fi[4] = j >= 0 ? stencil(j, j, &fi[5], &fd[10]) : 0;
-        if (j < 0)
+        fi[4] = 4;
+        if (j >= 0) {
+          // the neighbour's stencil with this cell's row (through the shared
+          // face) moved to slot 0: the sweep reads that value from registers
+          stencil(j, &fi[5], &fd[10]);
+          int q = 0;
+          for (int t = 0; t < nfc[j]; ++t)
+            if (cface[j * MAXF + t] == f) q = t;
+          if (q != 0) {
+            std::swap(fi[5], fi[5 + q]);
+            for (int d = 0; d < 3; ++d) std::swap(fd[10 + d * 4], fd[10 + d * 4 + q]);
+          }
+        } else {
+          // zero or ghost row: its own value with zero gradient
           for (int r = 0; r < 4; ++r) {
             fi[5 + r] = fi[3];
             for (int d = 0; d < 3; ++d) fd[10 + d * 4 + r] = 0.0;
           }
+        }
         for (int d = 0; d < 3; ++d) {
           fd[0 + d] = sg * fnorm[f * 3 + d];
           fd[4 + d] = sg > 0.0 ? fdxL[f * 3 + d] : fdxR[f * 3 + d];

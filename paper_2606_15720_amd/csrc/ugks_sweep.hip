@@ -277,17 +277,21 @@ __device__ __forceinline__ void sweep_item(
       }
     }
     // ---- every neighbour's value and stencil at the incoming member ----
+    // Slot p of the own stencil is the row across face p, and slot 0 of
+    // neighbour p's stencil is this cell: both are already in registers.
     double nh[4], nhs[4][4], nb[4], nbs[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       crec_i_t* fi = ci + CRI_F0 + CRI_FS * p;
-      uint32_t oin = sp[p] > 0.0 ? o1 : o0;
+      const bool in1 = sp[p] > 0.0;  // the incoming member is -u
+      uint32_t oin = in1 ? o1 : o0;
       __asm__("" : "+v"(oin));  // keep the select on the offset, not on 64-bit addresses
-      const int64_t j = fi[3];
-      nh[p] = ldo<T>(srow(h + j * nvp), oin);
-      nb[p] = B2 ? ldo<T>(srow(b + j * nvp), oin) : 0.0;
+      nh[p] = in1 ? os1[p] : os0[p];
+      nb[p] = B2 ? (in1 ? ob1[p] : ob0[p]) : 0.0;
+      nhs[p][0] = in1 ? h1 : h0;
+      nbs[p][0] = B2 ? (in1 ? b1 : b0) : 0.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 1; r < 4; ++r) {
         const int64_t cell = fi[5 + r];
         nhs[p][r] = ldo<T>(srow(h + cell * nvp), oin);
         nbs[p][r] = B2 ? ldo<T>(srow(b + cell * nvp), oin) : 0.0;
