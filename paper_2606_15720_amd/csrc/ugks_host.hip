@@ -446,6 +446,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     c->fmesh.vidx = upload(c, vidx);
     c->fmesh.crec_i = upload(c, ci);
     c->fmesh.crec_d = upload(c, cdr);
+    if (prec == UGKS_FP32) c->fmesh.crec_d32 = upload(c, std::vector<float>(cdr.begin(), cdr.end()));
     c->fmesh.nff = (int64_t)ffaces.size();
     c->fmesh.ffaces = upload(c, ffaces);
   }
@@ -473,12 +474,17 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     c->sched.nf = nf;
     c->sched.chunk_pairs = cp;
     c->sched.nchunk = (npairs + cp - 1) / cp;
-    c->sched.tile = tile ? tile : 256;
+    c->sched.tile = tile ? tile : 64;
     c->Bv = (int)(2 * cp);
     B.dW = dalloc<double>(c, nc * c->sched.nchunk * 5);
     B.tabs = dalloc<double>(c, (nf + nc) * (int64_t)D * c->fmesh.na);
     B.cs = dalloc<double>(c, nc * CSREC);
     B.csn = dalloc<double>(c, nc * CSREC);
+    if (prec == UGKS_FP32) {
+      B.frec32 = dalloc<float>(c, nf * FREC);
+      B.cs32 = dalloc<float>(c, nc * CSREC);
+      B.tabs32 = dalloc<float>(c, (nf + nc) * (int64_t)D * c->fmesh.na);
+    }
   } else {
     B.dW = dalloc<double>(c, nc * 5);
   }
@@ -615,8 +621,16 @@ void enqueue_step_fused(ugks_ctx* c) {
   // Maxwellian axis tables of every face and cell of this step
   TIMED(KK_TABLES, launch_tables(D, m, c->fmesh, g, B.frec, B.prim, B.cs, B.tabs, B.flag, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep
-  TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, c->sched, B.cs, B.frec, B.tabs, B.h, B.b,
-                               B.ht, B.bt, B.dW, B.flag, s));
+  if (P == UGKS_FP32) {
+    // the FP32 sweep reads FP32 copies of this step's records and tables
+    TIMED(KK_TABLES, launch_to_f32(B.frec, B.frec32, c->nf * FREC, B.cs, B.cs32, c->nc * CSREC,
+                                   B.tabs, B.tabs32, (c->nf + c->nc) * (int64_t)D * c->fmesh.na, s));
+    TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, c->sched, c->fmesh.crec_d32, B.cs32,
+                                 B.frec32, B.tabs32, B.h, B.b, B.ht, B.bt, B.dW, B.flag, s));
+  } else {
+    TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, c->sched, c->fmesh.crec_d, B.cs, B.frec,
+                                 B.tabs, B.h, B.b, B.ht, B.bt, B.dW, B.flag, s));
+  }
   // 8 conservative update; 10 new equilibrium (with q^n, reading R17)
   TIMED(KK_MACRO, launch_apply_dW(D, m, c->sched.nchunk, B.W, B.dW, B.Wn, B.cellred, B.flag, s));
   TIMED(KK_PRIMS, launch_cell_prep(D, c->nc, g, B.Wn, B.q, B.primn, B.csn, B.flag, s));

@@ -85,6 +85,7 @@ struct FusedMesh {
   const int32_t* vidx;      // [nv] packed axis indices of point k (8 bits per axis, first axis low)
   const int32_t* crec_i;    // [nc*CRI]
   const double* crec_d;     // [nc*CRD]
+  const float* crec_d32;    // [nc*CRD] FP32 copy (FP32 compute form), else null
   const int32_t* ffaces;    // [nff] far-field / outflow faces; face m owns ghost row nc+1+m
   int64_t nff;
 };
@@ -129,6 +130,9 @@ struct StepBuffers {
   double* tabs;    // [(nf+nc)*D*na] Maxwellian axis tables of the step (fused sweep)
   double* cs;      // [nc*CSREC] per-step cell record of W^n (fused sweep)
   double* csn;     // [nc*CSREC] per-step cell record of W^{n+1}
+  float* frec32;   // FP32 copies of frec, cs, tabs for the FP32 sweep (null in FP64)
+  float* cs32;
+  float* tabs32;
   void* h;         // [nc*nvp] storage type
   void* b;         // [nc*nvp] (2-D only)
   void* ht;        // [nc*nvp] first-stage result
@@ -210,10 +214,13 @@ hipError_t launch_dt_cells(int D, const DevMesh& m, const DevVel& v, double* cel
 // fused sweep (ugks_sweep.hip)
 hipError_t launch_cell_prep(int D, int64_t nc, const GasP& g, const double* W, const double* q,
                             double* prim, double* cs, int32_t* flag, hipStream_t s);
+// crec_d, cs, frec, tabs: FP64 records, or their FP32 copies when prec is FP32
 hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, const GasP& g,
-                        const SweepSched& sc, const double* cs, const double* frec,
-                        const double* tabs, const void* h, const void* b, void* ht, void* bt,
+                        const SweepSched& sc, const void* crec_d, const void* cs, const void* frec,
+                        const void* tabs, const void* h, const void* b, void* ht, void* bt,
                         double* dWp, const int32_t* flag, hipStream_t s);
+hipError_t launch_to_f32(const double* a, float* fa, int64_t na, const double* b, float* fb,
+                         int64_t nb, const double* c, float* fc, int64_t nc, hipStream_t s);
 hipError_t launch_tables(int D, const DevMesh& m, const FusedMesh& fm, const GasP& g,
                          const double* frec, const double* prim, const double* cs, double* tabs,
                          const int32_t* flag, hipStream_t s);

@@ -53,26 +53,27 @@ __device__ __forceinline__ grow_t* srow(const T* p) {
 // scalar loads, also where the record pointers themselves come from memory
 // (the batched form).
 typedef const __attribute__((address_space(4))) int32_t crec_i_t;
-typedef const __attribute__((address_space(4))) double crec_d_t;
+template <typename X>
+using crec_t = const __attribute__((address_space(4))) X;
 
-template <typename T>
-__device__ __forceinline__ double ldo(grow_t* row, uint32_t off) {
-  return static_cast<double>(*(const __attribute__((address_space(1))) T*)(row + off));
+template <typename T, typename C>
+__device__ __forceinline__ C ldo(grow_t* row, uint32_t off) {
+  return static_cast<C>(*(const __attribute__((address_space(1))) T*)(row + off));
 }
 
 // Even and odd parts of a cubic (monomial order of Cubic<D>) at u by nested
 // Horner forms:  P(u) = E(u) + O(u),  P(-u) = E(u) - O(u).
-template <int D, typename PT>
-__device__ __forceinline__ void cubic_eo(PT P, const double* v, double& E, double& O) {
+template <int D, typename C, typename PT>
+__device__ __forceinline__ void cubic_eo(PT P, const C* v, C& E, C& O) {
   if constexpr (D == 3) {
-    const double x = v[0], y = v[1], z = v[2];
+    const C x = v[0], y = v[1], z = v[2];
     // quadratics xx yy zz xy xz yz = P[4..9], cubics xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz = P[10..19]
     E = P[0] + x * (P[4] * x + P[7] * y + P[8] * z) + y * (P[5] * y + P[9] * z) + P[6] * z * z;
     O = x * (P[1] + x * (P[10] * x + P[11] * y + P[12] * z) + y * (P[13] * y + P[14] * z) +
              P[15] * z * z) +
         y * (P[2] + y * (P[16] * y + P[17] * z) + P[18] * z * z) + z * (P[3] + P[19] * z * z);
   } else {
-    const double x = v[0], y = v[1];
+    const C x = v[0], y = v[1];
     // quadratics xx yy xy = P[3..5], cubics xxx xxy xyy yyy = P[6..9]
     E = P[0] + x * (P[3] * x + P[5] * y) + P[4] * y * y;
     O = x * (P[1] + x * (P[6] * x + P[7] * y) + P[8] * y * y) + y * (P[2] + P[9] * y * y);
@@ -164,10 +165,11 @@ __global__ void k_tables(int64_t nf, int64_t nc, int na, const double* __restric
 
 // LDS of one sweep work item: the Maxwellian axis tables of the cell's four
 // faces and of the cell, the velocity nodes and the reduction scratch.
+template <typename C>
 struct SweepLds {
-  double tab[SWF][3][NAX];
-  double ctab[3][NAX];
-  double ax[NAX];
+  C tab[SWF][3][NAX];
+  C ctab[3][NAX];
+  C ax[NAX];
   double red[5 * 16];
 };
 
@@ -175,20 +177,20 @@ struct SweepLds {
 // Every read-only array is its own __restrict__ argument so that the
 // compiler can prove no store of the sweep clobbers it and serve the
 // wave-uniform reads from the scalar cache.
-template <int D, typename T>
+template <int D, typename T, typename C>
 __device__ __forceinline__ void sweep_item(
     const FusedMesh& fm, int64_t nvp, const SweepSched& sc, const int32_t* __restrict__ crec_i,
-    const double* __restrict__ crec_d, const int32_t* __restrict__ vidx,
-    const double* __restrict__ w, const double* __restrict__ cs, const double* __restrict__ frec,
-    const double* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
+    const C* __restrict__ crec_d, const int32_t* __restrict__ vidx,
+    const double* __restrict__ w, const C* __restrict__ cs, const C* __restrict__ frec,
+    const C* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
     T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dWp,
-    const int32_t* __restrict__ flag, int64_t ic, int64_t chunk, SweepLds& L) {
+    const int32_t* __restrict__ flag, int64_t ic, int64_t chunk, SweepLds<C>& L) {
   if (*flag) return;
   // every pointer below is wave-uniform: its loads are scalar loads
   crec_i_t* ci0 = (crec_i_t*)(crec_i + ic * CRI);
-  crec_d_t* cd0 = (crec_d_t*)(crec_d + ic * CRD);
-  crec_d_t* cc0 = (crec_d_t*)(cs + ic * CSREC);
-  crec_d_t* frc = (crec_d_t*)frec;
+  crec_t<C>* cd0 = (crec_t<C>*)(crec_d + ic * CRD);
+  crec_t<C>* cc0 = (crec_t<C>*)(cs + ic * CSREC);
+  crec_t<C>* frc = (crec_t<C>*)frec;
   const unsigned nthr = blockDim.x;  // lanes of the work-group, one mirror pair each
   const int na = fm.na;
   {
@@ -197,7 +199,7 @@ __device__ __forceinline__ void sweep_item(
     for (int t = threadIdx.x; t < n_all; t += nthr) {
       const int p = t / per, r = t % per, d = r / na, n = r % na;
       const int64_t e = p < 4 ? (int64_t)ci0[CRI_F0 + CRI_FS * p] : sc.nf + ic;
-      const double v = tabs[e * per + d * na + n];
+      const C v = tabs[e * per + d * na + n];
       if (p < 4) L.tab[p][d][n] = v;
       else L.ctab[d][n] = v;
     }
@@ -229,8 +231,8 @@ __device__ __forceinline__ void sweep_item(
     int z;
     __asm__ volatile("s_mov_b32 %0, 0" : "=s"(z));
     crec_i_t* ci = ci0 + z;
-    crec_d_t* cd = cd0 + z;
-    crec_d_t* cc = cc0 + z;
+    crec_t<C>* cd = cd0 + z;
+    crec_t<C>* cc = cc0 + z;
     const unsigned k0 = kp, k1 = nv - 1 - kp;
     const int pk = pk_next;
     pk_next = vidx[min(kp + nthr, kend - 1)];
@@ -240,14 +242,14 @@ __device__ __forceinline__ void sweep_item(
       id[d] = (pk >> (8 * d)) & 255;
       im[d] = na - 1 - id[d];
     }
-    double vv[3] = {0.0, 0.0, 0.0};
+    C vv[3] = {C(0), C(0), C(0)};
 #pragma unroll
     for (int d = 0; d < D; ++d) vv[d] = L.ax[id[d]];
     // orientation of u against every outward normal
-    double sp[4];
+    C sp[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      double s = 0.0;
+      C s = C(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) s += vv[d] * cd[CRD_F0 + CRD_FS * p + 0 + d];
       sp[p] = s;
@@ -255,57 +257,57 @@ __device__ __forceinline__ void sweep_item(
     // ---- the cell's own stencil at u and -u (4 rows, padded) ----
     const uint32_t o0 = k0 * (uint32_t)sizeof(T), o1 = k1 * (uint32_t)sizeof(T);
     grow_t* rhi = srow(hi);
-    const double h0 = ldo<T>(rhi, o0), h1 = ldo<T>(rhi, o1);
-    double b0 = 0.0, b1 = 0.0;
+    const C h0 = ldo<T, C>(rhi, o0), h1 = ldo<T, C>(rhi, o1);
+    C b0 = C(0), b1 = C(0);
     if (B2) {
       grow_t* rbi = srow(bi);
-      b0 = ldo<T>(rbi, o0);
-      b1 = ldo<T>(rbi, o1);
+      b0 = ldo<T, C>(rbi, o0);
+      b1 = ldo<T, C>(rbi, o1);
     }
-    double os0[4], os1[4], ob0[4], ob1[4];
+    C os0[4], os1[4], ob0[4], ob1[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t cell = ci[2 + s];
       grow_t* rh = srow(h + cell * nvp);
-      os0[s] = ldo<T>(rh, o0);
-      os1[s] = ldo<T>(rh, o1);
-      ob0[s] = ob1[s] = 0.0;
+      os0[s] = ldo<T, C>(rh, o0);
+      os1[s] = ldo<T, C>(rh, o1);
+      ob0[s] = ob1[s] = C(0);
       if (B2) {
         grow_t* rb = srow(b + cell * nvp);
-        ob0[s] = ldo<T>(rb, o0);
-        ob1[s] = ldo<T>(rb, o1);
+        ob0[s] = ldo<T, C>(rb, o0);
+        ob1[s] = ldo<T, C>(rb, o1);
       }
     }
     // ---- every neighbour's value and stencil at the incoming member ----
     // Slot p of the own stencil is the row across face p, and slot 0 of
     // neighbour p's stencil is this cell: both are already in registers.
-    double nh[4], nhs[4][4], nb[4], nbs[4][4];
+    C nh[4], nhs[4][4], nb[4], nbs[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       crec_i_t* fi = ci + CRI_F0 + CRI_FS * p;
-      const bool in1 = sp[p] > 0.0;  // the incoming member is -u
+      const bool in1 = sp[p] > C(0);  // the incoming member is -u
       uint32_t oin = in1 ? o1 : o0;
       __asm__("" : "+v"(oin));  // keep the select on the offset, not on 64-bit addresses
       nh[p] = in1 ? os1[p] : os0[p];
-      nb[p] = B2 ? (in1 ? ob1[p] : ob0[p]) : 0.0;
+      nb[p] = B2 ? (in1 ? ob1[p] : ob0[p]) : C(0);
       nhs[p][0] = in1 ? h1 : h0;
-      nbs[p][0] = B2 ? (in1 ? b1 : b0) : 0.0;
+      nbs[p][0] = B2 ? (in1 ? b1 : b0) : C(0);
 #pragma unroll
       for (int r = 1; r < 4; ++r) {
         const int64_t cell = fi[5 + r];
-        nhs[p][r] = ldo<T>(srow(h + cell * nvp), oin);
-        nbs[p][r] = B2 ? ldo<T>(srow(b + cell * nvp), oin) : 0.0;
+        nhs[p][r] = ldo<T, C>(srow(h + cell * nvp), oin);
+        nbs[p][r] = B2 ? ldo<T, C>(srow(b + cell * nvp), oin) : C(0);
       }
     }
     // ---- arithmetic ----
-    double g0[3] = {0, 0, 0}, g1[3] = {0, 0, 0}, gb0[3] = {0, 0, 0}, gb1[3] = {0, 0, 0};
+    C g0[3] = {C(0), C(0), C(0)}, g1[3] = {C(0), C(0), C(0)}, gb0[3] = {C(0), C(0), C(0)}, gb1[3] = {C(0), C(0), C(0)};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const double d0 = os0[s] - h0, d1 = os1[s] - h1;
-      const double e0 = ob0[s] - b0, e1 = ob1[s] - b1;
+      const C d0 = os0[s] - h0, d1 = os1[s] - h1;
+      const C e0 = ob0[s] - b0, e1 = ob1[s] - b1;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const double G = cd[d * 4 + s];
+        const C G = cd[d * 4 + s];
         g0[d] += G * d0;
         g1[d] += G * d1;
         if (B2) {
@@ -314,7 +316,7 @@ __device__ __forceinline__ void sweep_item(
         }
       }
     }
-    double ug0 = 0.0, ug1 = 0.0, ub0 = 0.0, ub1 = 0.0;
+    C ug0 = C(0), ug1 = C(0), ub0 = C(0), ub1 = C(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       ug0 += vv[d] * g0[d];
@@ -324,38 +326,38 @@ __device__ __forceinline__ void sweep_item(
         ub1 -= vv[d] * gb1[d];
       }
     }
-    double v2 = 0.0;
+    C v2 = C(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) v2 += vv[d] * vv[d];
-    double acc0 = 0.0, acc1 = 0.0, accb0 = 0.0, accb1 = 0.0;
+    C acc0 = C(0), acc1 = C(0), accb0 = C(0), accb1 = C(0);
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      crec_d_t* fd = cd + CRD_F0 + CRD_FS * p;
-      crec_d_t* R = frc + (int64_t)ci[CRI_F0 + CRI_FS * p] * FREC;
-      const bool pos = sp[p] > 0.0;
-      const double as = fabs(sp[p]);
-      const double G1 = R[FR_G], G2 = R[FR_G + 1];
+      crec_t<C>* fd = cd + CRD_F0 + CRD_FS * p;
+      crec_t<C>* R = frc + (int64_t)ci[CRI_F0 + CRI_FS * p] * FREC;
+      const bool pos = sp[p] > C(0);
+      const C as = fabs(sp[p]);
+      const C G1 = R[FR_G], G2 = R[FR_G + 1];
       // outgoing member: the cell's own reconstruction at the face
-      const double us = pos ? ug0 : ug1;
-      double hf = pos ? h0 : h1;
+      const C us = pos ? ug0 : ug1;
+      C hf = pos ? h0 : h1;
 #pragma unroll
       for (int d = 0; d < D; ++d) hf += fd[4 + d] * (pos ? g0[d] : g1[d]);
       // incoming member: the neighbour's reconstruction at the face (all
       // zero rows on a wall)
-      const double sgn_in = pos ? -1.0 : 1.0;  // u_in = sgn_in * u
-      const double hj = nh[p], bj = nb[p];
-      double gj[3] = {0, 0, 0}, gbj[3] = {0, 0, 0};
+      const C sgn_in = pos ? -1.0 : 1.0;  // u_in = sgn_in * u
+      const C hj = nh[p], bj = nb[p];
+      C gj[3] = {C(0), C(0), C(0)}, gbj[3] = {C(0), C(0), C(0)};
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double dh = nhs[p][r] - hj, db = nbs[p][r] - bj;
+        const C dh = nhs[p][r] - hj, db = nbs[p][r] - bj;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const double G = fd[10 + d * 4 + r];
+          const C G = fd[10 + d * 4 + r];
           gj[d] += G * dh;
           if (B2) gbj[d] += G * db;
         }
       }
-      double hfj = hj, ugj = 0.0;
+      C hfj = hj, ugj = C(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         hfj += fd[7 + d] * gj[d];
@@ -364,41 +366,41 @@ __device__ __forceinline__ void sweep_item(
       ugj *= sgn_in;
       // g0 (or the scaled wall Maxwellian) at u and -u from the axis tables,
       // times the equilibrium polynomial (constant on a wall)
-      double e0 = L.tab[p][0][id[0]], e1 = L.tab[p][0][im[0]];
+      C e0 = L.tab[p][0][id[0]], e1 = L.tab[p][0][im[0]];
 #pragma unroll
       for (int d = 1; d < D; ++d) {
         e0 *= L.tab[p][d][id[d]];
         e1 *= L.tab[p][d][im[d]];
       }
-      double E, O;
+      C E, O;
       cubic_eo<D>(R + FR_PH, vv, E, O);
-      const double q0 = e0 * (E + O), q1 = e1 * (E - O);
-      const double eqm = fd[22];  // 0 on a wall: no equilibrium term going out
-      const double eqo = eqm * (pos ? q0 : q1);
-      const double eqi = pos ? q1 : q0;
-      const double out = as * (G1 * hf + G2 * us + eqo);
-      const double in = -as * (G1 * hfj + G2 * ugj + eqi);
-      double outb = 0.0, inb = 0.0;
+      const C q0 = e0 * (E + O), q1 = e1 * (E - O);
+      const C eqm = fd[22];  // 0 on a wall: no equilibrium term going out
+      const C eqo = eqm * (pos ? q0 : q1);
+      const C eqi = pos ? q1 : q0;
+      const C out = as * (G1 * hf + G2 * us + eqo);
+      const C in = -as * (G1 * hfj + G2 * ugj + eqi);
+      C outb = 0.0, inb = 0.0;
       if (B2) {
-        double bfo = pos ? b0 : b1;
-        const double ubs = pos ? ub0 : ub1;
+        C bfo = pos ? b0 : b1;
+        const C ubs = pos ? ub0 : ub1;
 #pragma unroll
         for (int d = 0; d < D; ++d) bfo += fd[4 + d] * (pos ? gb0[d] : gb1[d]);
-        double bfj = bj, ubj = 0.0;
+        C bfj = bj, ubj = C(0);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           bfj += fd[7 + d] * gbj[d];
           ubj += vv[d] * gbj[d];
         }
         ubj *= sgn_in;
-        double Eb, Ob;
+        C Eb, Ob;
         cubic_eo<D>(R + FR_PB, vv, Eb, Ob);
-        const double r0 = e0 * (Eb + Ob), r1 = e1 * (Eb - Ob);
+        const C r0 = e0 * (Eb + Ob), r1 = e1 * (Eb - Ob);
         outb = as * (G1 * bfo + G2 * ubs + eqm * (pos ? r0 : r1));
         inb = -as * (G1 * bfj + G2 * ubj + (pos ? r1 : r0));
       }
       // fluxes at u and at -u along this cell's outward normal, times S/V
-      const double sv = fd[3];
+      const C sv = fd[3];
       acc0 += sv * (pos ? out : in);
       acc1 += sv * (pos ? in : out);
       if (B2) {
@@ -408,34 +410,34 @@ __device__ __forceinline__ void sweep_item(
     }
     // moments of the net outflow (the zero velocity of an odd grid once)
     {
-      const double a0 = w[k0] * acc0, a1 = (k1 != k0) ? w[k1] * acc1 : 0.0;
+      const double a0 = w[k0] * (double)acc0, a1 = (k1 != k0) ? w[k1] * (double)acc1 : 0.0;
       mw[0] += a0 + a1;
 #pragma unroll
-      for (int d = 0; d < D; ++d) mw[1 + d] += vv[d] * (a0 - a1);
-      double e = 0.5 * v2 * (a0 + a1);
-      if (B2) e += 0.5 * (w[k0] * accb0 + ((k1 != k0) ? w[k1] * accb1 : 0.0));
+      for (int d = 0; d < D; ++d) mw[1 + d] += (double)vv[d] * (a0 - a1);
+      double e = 0.5 * (double)v2 * (a0 + a1);
+      if (B2) e += 0.5 * (w[k0] * (double)accb0 + ((k1 != k0) ? w[k1] * (double)accb1 : 0.0));
       mw[D + 1] += e;
     }
     // first stage with the cell's BGK-Shakhov equilibrium at u and -u
-    double c0 = L.ctab[0][id[0]], c1 = L.ctab[0][im[0]];
+    C c0 = L.ctab[0][id[0]], c1 = L.ctab[0][im[0]];
 #pragma unroll
     for (int d = 1; d < D; ++d) {
       c0 *= L.ctab[d][id[d]];
       c1 *= L.ctab[d][im[d]];
     }
-    double E, O;
+    C E, O;
     cubic_eo<D>(cc + CS_SH, vv, E, O);
-    const double ccoll = cc[CS_CC];
+    const C ccoll = cc[CS_CC];
     T* __restrict__ hto = ht + ic * nvp;
-    st(hto, k0, h0 - acc0 + ccoll * (c0 * (1.0 + E + O) - h0));
-    if (k1 != k0) st(hto, k1, h1 - acc1 + ccoll * (c1 * (1.0 + E - O) - h1));
+    st(hto, k0, h0 - acc0 + ccoll * (c0 * (C(1) + E + O) - h0));
+    if (k1 != k0) st(hto, k1, h1 - acc1 + ccoll * (c1 * (C(1) + E - O) - h1));
     if (B2) {
-      double Eb, Ob;
+      C Eb, Ob;
       cubic_eo<D>(cc + CS_SB, vv, Eb, Ob);
-      const double kc = cc[CS_KAP];
+      const C kc = cc[CS_KAP];
       T* __restrict__ bto = bt + ic * nvp;
-      st(bto, k0, b0 - accb0 + ccoll * (kc * c0 * (1.0 + Eb + Ob) - b0));
-      if (k1 != k0) st(bto, k1, b1 - accb1 + ccoll * (kc * c1 * (1.0 + Eb - Ob) - b1));
+      st(bto, k0, b0 - accb0 + ccoll * (kc * c0 * (C(1) + Eb + Ob) - b0));
+      if (k1 != k0) st(bto, k1, b1 - accb1 + ccoll * (kc * c1 * (C(1) + Eb - Ob) - b1));
     }
   }
   block_sum<NM>(mw, L.red);
@@ -444,15 +446,17 @@ __device__ __forceinline__ void sweep_item(
 }
 
 
+// Single case: the sweep computes in the storage type T (FP32 storage uses
+// FP32 copies of the records and tables; moment sums stay FP64).
 template <int D, typename T>
 __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
     FusedMesh fm, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
-    const double* __restrict__ crec_d, const int32_t* __restrict__ vidx,
-    const double* __restrict__ w, const double* __restrict__ cs, const double* __restrict__ frec,
-    const double* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
+    const T* __restrict__ crec_d, const int32_t* __restrict__ vidx,
+    const double* __restrict__ w, const T* __restrict__ cs, const T* __restrict__ frec,
+    const T* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
     T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dWp,
     const int32_t* __restrict__ flag) {
-  __shared__ SweepLds L;
+  __shared__ SweepLds<T> L;
   // Work item = (cell, velocity block).  Blocks are dealt round-robin to the
   // 8 XCDs; XCD x takes tiles x, x+8, ... of sc.tile consecutive (Z-order)
   // cells and runs all of a tile's cells through velocity block 0, then 1,
@@ -465,8 +469,8 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
   const int64_t chunk = rem / sc.tile;
   const int64_t ic = tile * sc.tile + rem % sc.tile;
   if (ic >= fm.nc) return;
-  sweep_item<D, T>(fm, nvp, sc, crec_i, crec_d, vidx, w, cs, frec, tabs, h, b, ht, bt, dWp, flag,
-                   ic, chunk, L);
+  sweep_item<D, T, T>(fm, nvp, sc, crec_i, crec_d, vidx, w, cs, frec, tabs, h, b, ht, bt, dWp,
+                      flag, ic, chunk, L);
 }
 
 // The fused sweep over a batch of cases: a persistent grid walks a list of
@@ -475,7 +479,7 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
 // (block index mod 8) take whole tiles of one case.
 template <int D, typename T>
 __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep_b(BatchDev bd) {
-  __shared__ SweepLds L;
+  __shared__ SweepLds<double> L;
   // The work list and the case table are read-only for the whole launch:
   // read through the constant address space they are scalar loads, so the
   // case's pointers and sizes land in scalar registers as kernel arguments do.
@@ -512,7 +516,7 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep_b(BatchDev bd) 
     double* dW = cases[c].B.dW;
     const int32_t* flag = cases[c].B.flag;
     __syncthreads();  // the previous item's readers of L are done
-    sweep_item<D, T>(fm, nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, w, cs, frec, tabs, h, b, ht, bt,
+    sweep_item<D, T, double>(fm, nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, w, cs, frec, tabs, h, b, ht, bt,
                      dW, flag, ic, chunk, L);
   }
 }
@@ -865,14 +869,32 @@ hipError_t launch_cell_prep(int D, int64_t nc, const GasP& g, const double* W, c
 }
 
 hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, const GasP& g,
-                        const SweepSched& sc, const double* cs, const double* frec,
-                        const double* tabs, const void* h, const void* b, void* ht, void* bt,
+                        const SweepSched& sc, const void* crec_d, const void* cs, const void* frec,
+                        const void* tabs, const void* h, const void* b, void* ht, void* bt,
                         double* dWp, const int32_t* flag, hipStream_t s) {
   const int64_t ntile = (fm.nc + sc.tile - 1) / sc.tile;
   const unsigned grid = (unsigned)(((ntile + 7) / 8) * 8 * sc.nchunk * sc.tile);
   UGKS_DISPATCH_DT(D, prec, k_sweep<DD, TT><<<grid, SWT, 0, s>>>(
-      fm, v.nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, v.w, cs, frec, tabs, (const TT*)h,
-      (const TT*)b, (TT*)ht, (TT*)bt, dWp, flag));
+      fm, v.nvp, sc, fm.crec_i, (const TT*)crec_d, fm.vidx, v.w, (const TT*)cs, (const TT*)frec,
+      (const TT*)tabs, (const TT*)h, (const TT*)b, (TT*)ht, (TT*)bt, dWp, flag));
+  return hipGetLastError();
+}
+
+// FP64 -> FP32 copies of the sweep's per-step records (FP32 compute form)
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ fa, int64_t na,
+                         const double* __restrict__ b, float* __restrict__ fb, int64_t nb,
+                         const double* __restrict__ c, float* __restrict__ fc, int64_t nc) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < na) fa[t] = (float)a[t];
+  else if (t < na + nb) fb[t - na] = (float)b[t - na];
+  else if (t < na + nb + nc) fc[t - na - nb] = (float)c[t - na - nb];
+}
+
+hipError_t launch_to_f32(const double* a, float* fa, int64_t na, const double* b, float* fb,
+                         int64_t nb, const double* c, float* fc, int64_t nc, hipStream_t s) {
+  const int64_t n = na + nb + nc;
+  if (n == 0) return hipSuccess;
+  k_to_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, fa, na, b, fb, nb, c, fc, nc);
   return hipGetLastError();
 }
 
