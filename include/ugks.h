@@ -133,7 +133,7 @@ typedef struct {
  *   block_v    velocity-block size B_v of the fused sweep: velocities per
  *              work item (a multiple of 64, at least 128; 0 = 4096), the
  *              paper's B_v (Eq. velocity_block_partition) as a scheduling unit.
- *   tile_cells cells per tile of the fused sweep's schedule (0 = 64); each
+ *   tile_cells cells per tile of the fused sweep's schedule (0 = 32); each
  *              XCD runs one tile through one velocity block at a time.
  *   flags      bit 0: skip the density residual (saves one small reduction).
  *              bit 1: use the staged sweep even where the fused one applies.

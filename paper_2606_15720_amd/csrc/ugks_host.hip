@@ -474,7 +474,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     c->sched.nf = nf;
     c->sched.chunk_pairs = cp;
     c->sched.nchunk = (npairs + cp - 1) / cp;
-    c->sched.tile = tile ? tile : 64;
+    c->sched.tile = tile ? tile : 32;
     c->Bv = (int)(2 * cp);
     B.dW = dalloc<double>(c, nc * c->sched.nchunk * 5);
     B.tabs = dalloc<double>(c, (nf + nc) * (int64_t)D * c->fmesh.na);
