@@ -615,7 +615,7 @@ void enqueue_step_fused(ugks_ctx* c) {
   TIMED(KK_GRADW, launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
   TIMED(KK_FACE_EQ, launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
   // 7 wall densities; far-field ghost rows
-  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, g, B.h, B.frec, B.flag, s));
+  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, c->fmesh, g, B.h, B.frec, B.flag, s));
   if (c->fmesh.nff)
     TIMED(KK_WALL, launch_ghost_rows(D, P, c->fmesh, v, B.frec, B.h, B.b, B.flag, s));
   // Maxwellian axis tables of every face and cell of this step

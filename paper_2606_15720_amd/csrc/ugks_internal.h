@@ -231,8 +231,8 @@ hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v
                            const double* primn, const double* csn, const void* ht, const void* bt,
                            void* h, void* b, double* qn, const int32_t* flag, hipStream_t s);
 hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
-                                  const GasP& g, const void* h, double* frec, const int32_t* flag,
-                                  hipStream_t s);
+                                  const FusedMesh& fm, const GasP& g, const void* h, double* frec,
+                                  const int32_t* flag, hipStream_t s);
 hipError_t launch_ghost_rows(int D, int prec, const FusedMesh& fm, const DevVel& v,
                              const double* frec, void* h, void* b, const int32_t* flag,
                              hipStream_t s);

@@ -447,9 +447,11 @@ __device__ __forceinline__ void sweep_item(
 
 
 // Single case: the sweep computes in the storage type T (FP32 storage uses
-// FP32 copies of the records and tables; moment sums stay FP64).
+// FP32 copies of the records and tables; moment sums stay FP64).  The FP32
+// body fits in half the registers; its bound asks for the occupancy that
+// hides the gathers' latency (measured: 7 waves per SIMD, no spills).
 template <int D, typename T>
-__global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
+__global__ __launch_bounds__(SWT, (D == 3 ? (sizeof(T) == 4 ? 6 : 4) : (sizeof(T) == 4 ? 4 : 2))) void k_sweep(
     FusedMesh fm, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
     const T* __restrict__ crec_d, const int32_t* __restrict__ vidx,
     const double* __restrict__ w, const T* __restrict__ cs, const T* __restrict__ frec,
@@ -476,9 +478,11 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep(
 // The fused sweep over a batch of cases: a persistent grid walks a list of
 // (case, cell, velocity block) work items; item w runs on block w mod the
 // grid size, and the host orders the list so that the blocks of one XCD
-// (block index mod 8) take whole tiles of one case.
+// (block index mod 8) take whole tiles of one case.  In 2-D (h and b) the
+// bound trades three spilled registers for a third wave per SIMD (measured
+// faster on the uneven 2-D batch).
 template <int D, typename T>
-__global__ __launch_bounds__(SWT, (D == 3 ? 4 : 2)) void k_sweep_b(BatchDev bd) {
+__global__ __launch_bounds__(SWT, (D == 3 ? 4 : 3)) void k_sweep_b(BatchDev bd) {
   __shared__ SweepLds<double> L;
   // The work list and the case table are read-only for the whole launch:
   // read through the constant address space they are scalar loads, so the
@@ -639,22 +643,52 @@ __global__ __launch_bounds__(SWT) void k_stage2_q(FusedMesh fm, int64_t nvp,
 }
 
 // Wall density with the wall cell's gradient evaluated in place.
+struct WallLds {
+  double ax[NAX];
+  double wx[3][NAX];  // axis factors of the wall Maxwellian, C_w folded into the first
+  double red[2 * 16];
+};
+
+// Wall density of one wall face: the incident free transport of the wall
+// cell (its gradient evaluated in place) against the re-emitted wall
+// Maxwellian, whose value at a tensor point is a product of three LDS
+// axis factors (no per-velocity exp).
 template <int D, typename T>
 __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const DevVel& v,
-                                            const GasP& g, const T* __restrict__ h,
-                                            double* __restrict__ frec, const int32_t* flag,
-                                            double* red) {
+                                            const FusedMesh& fm, const GasP& g,
+                                            const T* __restrict__ h, double* __restrict__ frec,
+                                            const int32_t* flag, WallLds& S) {
   if (*flag) return;
   const int f = m.walls[wi];
   const int64_t L = m.fL[f];
   const int64_t nvp = v.nvp;
   double* R = &frec[(int64_t)f * FREC];
   const double lamw = R[FR_LAM], Cw = R[FR_C0], dt = g.dt;
+  const int na = fm.na;
+  for (int t = threadIdx.x; t < D * na; t += blockDim.x) {
+    const int d = t / na, n = t % na;
+    const double c = fm.axis[n] - R[FR_U + d];
+    S.wx[d][n] = (d == 0 ? Cw : 1.0) * exp(-lamw * c * c);
+  }
+  for (int t = threadIdx.x; t < na; t += blockDim.x) S.ax[t] = fm.axis[t];
+  __syncthreads();
   const int nfc = m.nfc[L];
+  double nrm[3] = {0, 0, 0}, dxl[3] = {0, 0, 0};
+  for (int d = 0; d < D; ++d) {
+    nrm[d] = m.fnorm[f * 3 + d];
+    dxl[d] = m.fdxL[f * 3 + d];
+  }
   double acc[2] = {0.0, 0.0};
-  for (int64_t k = threadIdx.x; k < v.nv; k += SWT) {
+  for (int64_t k = threadIdx.x; k < v.nv; k += blockDim.x) {
+    const int pk = fm.vidx[k];
+    double u[3] = {0, 0, 0};
+    int id[3] = {0, 0, 0};
     double un = 0.0;
-    for (int d = 0; d < D; ++d) un += v.u[d * nvp + k] * m.fnorm[f * 3 + d];
+    for (int d = 0; d < D; ++d) {
+      id[d] = (pk >> (8 * d)) & 255;
+      u[d] = S.ax[id[d]];
+      un += u[d] * nrm[d];
+    }
     if (un > 0.0) {
       const double hl = ld(h, L * nvp + k);
       double gr[3] = {0, 0, 0};
@@ -671,7 +705,7 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
           const double* R2 = &frec[(int64_t)f2 * FREC];
           double c2 = 0.0;
           for (int d = 0; d < D; ++d) {
-            const double c = v.u[d * nvp + k] - R2[FR_GU + d];
+            const double c = u[d] - R2[FR_GU + d];
             c2 += c * c;
           }
           hj = R2[FR_GC] * exp(-R2[FR_GLAM] * c2);
@@ -681,30 +715,27 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
       }
       double hf = hl, ugh = 0.0;
       for (int d = 0; d < D; ++d) {
-        hf += m.fdxL[f * 3 + d] * gr[d];
-        ugh += v.u[d * nvp + k] * gr[d];
+        hf += dxl[d] * gr[d];
+        ugh += u[d] * gr[d];
       }
       acc[0] += v.w[k] * un * (dt * hf - 0.5 * dt * dt * ugh);
     } else if (un < 0.0) {
-      double c2 = 0.0;
-      for (int d = 0; d < D; ++d) {
-        double c = v.u[d * nvp + k] - R[FR_U + d];
-        c2 += c * c;
-      }
-      acc[1] += v.w[k] * un * Cw * exp(-lamw * c2);
+      double M = S.wx[0][id[0]];
+      for (int d = 1; d < D; ++d) M *= S.wx[d][id[d]];
+      acc[1] += v.w[k] * un * M;
     }
   }
-  block_sum<2>(acc, red);
+  block_sum<2>(acc, S.red);
   if (threadIdx.x == 0) R[FR_RHOW] = -acc[0] / (dt * acc[1]);
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(SWT) void k_wall_rho_inline(DevMesh m, DevVel v, GasP g,
+__global__ __launch_bounds__(SWT) void k_wall_rho_inline(DevMesh m, DevVel v, FusedMesh fm, GasP g,
                                                          const T* __restrict__ h,
                                                          double* __restrict__ frec,
                                                          const int32_t* flag) {
-  __shared__ double red[2 * 16];
-  wall_rho_at<D, T>(blockIdx.x, m, v, g, h, frec, flag, red);
+  __shared__ WallLds S;
+  wall_rho_at<D, T>(blockIdx.x, m, v, fm, g, h, frec, flag, S);
 }
 
 // Ghost rows of the far-field / outflow faces: the Maxwellian of the face's
@@ -812,11 +843,12 @@ __global__ __launch_bounds__(SWT) void k_ghost_rows_b(BatchDev bd) {
 // one block per wall face of the batch
 template <int D, typename T>
 __global__ __launch_bounds__(SWT) void k_wall_rho_b(BatchDev bd) {
-  __shared__ double red[2 * 16];
+  __shared__ WallLds S;
   const int64_t t = blockIdx.x;
   const int c = case_of(bd.wall_off, bd.n, t);
   const CaseDev& C = bd.cases[c];
-  wall_rho_at<D, T>(t - bd.wall_off[c], C.m, C.v, C.g, (const T*)C.B.h, C.B.frec, C.B.flag, red);
+  wall_rho_at<D, T>(t - bd.wall_off[c], C.m, C.v, C.fm, C.g, (const T*)C.B.h, C.B.frec, C.B.flag,
+                    S);
 }
 
 }  // namespace
@@ -908,11 +940,11 @@ hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v
 }
 
 hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
-                                  const GasP& g, const void* h, double* frec, const int32_t* flag,
-                                  hipStream_t s) {
+                                  const FusedMesh& fm, const GasP& g, const void* h, double* frec,
+                                  const int32_t* flag, hipStream_t s) {
   if (m.nwall == 0) return hipSuccess;
   UGKS_DISPATCH_DT(D, prec, k_wall_rho_inline<DD, TT><<<(unsigned)m.nwall, SWT, 0, s>>>(
-      m, v, g, (const TT*)h, frec, flag));
+      m, v, fm, g, (const TT*)h, frec, flag));
   return hipGetLastError();
 }
 
