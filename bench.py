@@ -19,6 +19,7 @@ The printed JSON line also carries
     measured by rocprofv3 counters when the committed summary matches the
     current kernel source;
   * ``fp32``: the same step in the FP32 form;
+  * ``batched``: the batched form on 64 uneven 2-D cases;
   * ``cpu_baseline``: the FP64 CPU oracle timed on one step of the same
     workload.
 """
@@ -98,6 +99,31 @@ def run_gpu(case, precision: int, steps: int, warmup: int):
     return dict(value=ups, ms_per_step=wall / steps * 1e3, info=info, prof=prof, residual=res,
                 sweep_ms=avg_s * 1e3, alg_bytes=alg_bytes, achieved=achieved, alg_flops=alg_flops,
                 tflops=tflops, mass=float(W[:, 0] @ case.mesh.cell_volume))
+
+
+def run_batched(steps: int, warmup: int):
+    """The batched form on the 64 uneven 2-D cases (one launch per phase,
+    persistent sweep, HIP-graph replay, autotuned schedule)."""
+    from paper_2606_15720_amd.ugks import Batch
+    import ugks_cases as uc
+
+    cases = uc.batch_cases()
+    ups = sum(c.mesh.n_cells * c.vel.nv for c in cases)
+    t = time.perf_counter()
+    b = Batch(cases)
+    create_s = time.perf_counter() - t
+    b.step(warmup)
+    t = time.perf_counter()
+    b.step(steps)
+    wall = time.perf_counter() - t
+    info = b.info
+    b.close()
+    return {"value": ups * steps / wall, "unit": "cell-velocity updates/s",
+            "ms_per_step": wall / steps * 1e3, "cases": len(cases), "updates_per_step": ups,
+            "create_and_tune_s": create_s, "lanes": info["threads"],
+            "work_items": info["work_items"], "graph": bool(info["graph"]),
+            "workload": "64 uneven 2-D cavity/Couette cases (16^2..96^2 cells, 16^2..40^2 "
+                        "velocities, Kn 1e-3..10), FP64"}
 
 
 def run_cpu_baseline(n: int):
@@ -198,6 +224,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=20,
                     help="hexes per edge of the oracle's sample (20 = the full workload)")
@@ -293,6 +320,8 @@ def main():
                        "hbm": {"achieved": r32["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": r32["achieved"] / HBM_PEAK_GBS},
                        "traffic": _traffic(32)}
+    if not args.no_batched:
+        out["batched"] = run_batched(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_n)
     print(json.dumps(out), flush=True)
