@@ -150,9 +150,9 @@ def run_warm_start(args):
     na, nr = (int(x) for x in args.ws_mesh.split(","))
     a = 3.0 * args.ws_mach  # velocity box half-width (units sqrt(2RT_inf))
     fine = uc.sphere_mach5(n_ang=na, n_rad=nr, nv=args.ws_nv, a=a, kn=args.ws_kn, mach=args.ws_mach,
-                           first=0.05)
+                           first=args.ws_first)
     coarse = uc.sphere_mach5(n_ang=na, n_rad=nr, nv=args.ws_nv_predictor, a=args.ws_a_predictor,
-                             kn=args.ws_kn, mach=args.ws_mach, first=0.05)
+                             kn=args.ws_kn, mach=args.ws_mach, first=args.ws_first)
     t0 = time.perf_counter()
 
     def log(*x):
@@ -160,7 +160,8 @@ def run_warm_start(args):
 
     out = WS.time_to_residual(fine, coarse, target=args.ws_target, max_steps=args.ws_max_steps,
                               predictor_target=args.ws_predictor_target, log=log,
-                              arms_run=tuple(args.ws_arms.split(",")))
+                              arms_run=tuple(args.ws_arms.split(",")),
+                              ref_out=args.ws_save_ref or None, ref_in=args.ws_ref or None)
     out["metric"] = "time to 1e-6 density residual (s)"
     out["reconstruction"] = "first order (no limiter: unlimited slopes fail at this Mach number)"
     out["mach"] = args.ws_mach
@@ -242,6 +243,10 @@ def main():
     ap.add_argument("--ws-target", type=float, default=1e-6)
     ap.add_argument("--ws-max-steps", type=int, default=60000)
     ap.add_argument("--ws-arms", default="plain64,maxwell32,learned32,learned64")
+    ap.add_argument("--ws-save-ref", default="", help="save the plain FP64 arm's final W (.npy)")
+    ap.add_argument("--ws-ref", default="", help="reference W (.npy) for the field errors when "
+                                                 "the plain arm is not run")
+    ap.add_argument("--ws-first", type=float, default=0.05, help="first layer thickness")
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the throughput line, the FP32 form's field errors against "
                          "FP64 on the 48k-tet cube with 28^3 velocities, and the mass drift")

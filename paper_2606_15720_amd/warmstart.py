@@ -222,7 +222,8 @@ def build_training_set(seed: int = 4, copies: int = 3, log=None):
 
 def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e-4,
                      max_steps=60000, chunk=1000, flags=16, train_seed=4, log=None,
-                     arms_run=("plain64", "maxwell32", "learned32", "learned64")):
+                     arms_run=("plain64", "maxwell32", "learned32", "learned64"),
+                     ref_out=None, ref_in=None):
     """Plain FP64 from the initial state against predictor + learned warm start.
 
     Arms (all to a density residual <= target, wall time from creation):
@@ -267,6 +268,14 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
         return W
 
     Wref = arm("plain64", U.UGKS_FP64) if "plain64" in arms_run else None
+    if Wref is not None and ref_out:
+        np.save(ref_out, Wref)
+    if Wref is None and ref_in:
+        Wref = np.load(ref_in)
+    if not any(a in arms_run for a in ("maxwell32", "learned32", "learned64")):
+        out["arms"] = arms
+        net.close()
+        return out
     t = time.perf_counter()
     p = U.Solver(case_coarse, precision=U.UGKS_FP32, flags=flags)
     psteps, pr, pok = run_to_residual(p, predictor_target, max_steps, chunk, log, "predictor")
