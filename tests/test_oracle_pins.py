@@ -8,6 +8,7 @@ of open points are listed in the oracle's header.
 """
 
 import math
+import os
 
 import mpmath as mp
 import numpy as np
@@ -423,6 +424,46 @@ def test_homogeneous_shakhov_heat_flux_decay(pr):
         assert q[n + 1] == pytest.approx(r * q[n], rel=1e-12)
     Wn = o.state(with_h=False)[0]
     np.testing.assert_allclose(Wn, case.W0, rtol=0, atol=1e-15)
+
+
+def _golden(name):
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].split()
+            if line:
+                vals[line[0]] = float(line[1])
+    return vals
+
+
+def test_cavity_velocity_set_matches_the_papers_worked_example():
+    # the paper's cavity set (Eqs. cavity_dvs_scaling ... cavity_dvs_tensor_product):
+    # its printed sizes, nodes from an independent Golub-Welsch eigen-solve of
+    # the Hermite recurrence, and exactness of the scaled weights on
+    # exp(-v^2/s^2) v^(2m) (closed form Gamma(m + 1/2) s^(2m+1)) up to degree 2N-1
+    g = _golden("cavity_dvs_gauss_hermite.txt")
+    n, umax = int(g["n_gh"]), g["u_max"]
+    vel = uc.gauss_hermite_grid(n, umax, 3)
+    assert vel.u.shape[0] == int(g["n_points"]) == n ** 3
+    k = np.arange(1, n)
+    J = np.diag(np.sqrt(k / 2), 1) + np.diag(np.sqrt(k / 2), -1)
+    xi = np.linalg.eigvalsh(J)
+    s = umax / xi.max()
+    assert s == pytest.approx(1.08101, abs=1e-5)
+    ax = np.unique(np.round(vel.u[:, 0], 12))
+    np.testing.assert_allclose(np.sort(ax), s * xi, rtol=0, atol=1e-11)
+    assert np.abs(vel.u).max() == pytest.approx(umax, abs=1e-14)
+    # 1-D weights: the marginal of the tensor weight over the other two axes
+    # (sum over j, k of w_i w_j w_k = w_i (sum w)^2, and the total is (sum w)^3)
+    w1 = np.array([vel.w[np.abs(vel.u[:, 0] - a) < 1e-9].sum() for a in ax])
+    w1 = w1 / vel.w.sum() ** (2.0 / 3.0)
+    for m in range(n):
+        exact = math.gamma(m + 0.5) * s ** (2 * m + 1)
+        got = np.sum(w1 * np.exp(-(ax / s) ** 2) * ax ** (2 * m))
+        assert got == pytest.approx(exact, rel=1e-10), m
+    # the 3-D weights are products of the 1-D ones
+    i = np.abs(vel.u[:, :, None] - ax).argmin(axis=2)
+    np.testing.assert_allclose(vel.w, w1[i[:, 0]] * w1[i[:, 1]] * w1[i[:, 2]], rtol=1e-12)
 
 
 def test_gauss_hermite_maxwellian_moments_exact():
