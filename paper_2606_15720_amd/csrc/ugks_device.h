@@ -290,6 +290,10 @@ __device__ __forceinline__ void time_coeffs(double dt, double tau, double* G) {
 //   2-D: 1 | x y   | xx yy xy          | xxx xxy xyy yyy
 // The even part is the constant and quadratic terms, the odd part the linear
 // and cubic terms, so P(-u) = E(u) - O(u) when P(u) = E(u) + O(u).
+// Every cubic term the scheme produces is of the form (w . u)|u|^2 (the
+// energy slope's u.grad part and the Shakhov factor): add_lin_u2 is the only
+// builder of cubic terms, so the coefficient of u_a^3 is the kappa_a of
+// P = c + l.u + u^T Q u + (kappa . u)|u|^2, which is how the sweeps read it.
 template <int D>
 struct Cubic {
   static constexpr int NQ = D == 3 ? 6 : 3;

@@ -61,22 +61,22 @@ __device__ __forceinline__ C ldo(grow_t* row, uint32_t off) {
   return static_cast<C>(*(const __attribute__((address_space(1))) T*)(row + off));
 }
 
-// Even and odd parts of a cubic (monomial order of Cubic<D>) at u by nested
-// Horner forms:  P(u) = E(u) + O(u),  P(-u) = E(u) - O(u).
+// Even and odd parts of a cubic P = c + l.u + u^T Q u + (kappa . u)|u|^2
+// (monomial order of Cubic<D>; kappa_a is the coefficient of u_a^3, the only
+// cubic form the scheme builds) at u, with v2 = |u|^2:
+//   E = c + u^T Q u,  O = l.u + (kappa . u) v2,  P(u) = E + O,  P(-u) = E - O.
 template <int D, typename C, typename PT>
-__device__ __forceinline__ void cubic_eo(PT P, const C* v, C& E, C& O) {
+__device__ __forceinline__ void cubic_eo(PT P, const C* v, C v2, C& E, C& O) {
   if constexpr (D == 3) {
     const C x = v[0], y = v[1], z = v[2];
-    // quadratics xx yy zz xy xz yz = P[4..9], cubics xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz = P[10..19]
+    // quadratics xx yy zz xy xz yz = P[4..9]; u_a^3 at P[10], P[16], P[19]
     E = P[0] + x * (P[4] * x + P[7] * y + P[8] * z) + y * (P[5] * y + P[9] * z) + P[6] * z * z;
-    O = x * (P[1] + x * (P[10] * x + P[11] * y + P[12] * z) + y * (P[13] * y + P[14] * z) +
-             P[15] * z * z) +
-        y * (P[2] + y * (P[16] * y + P[17] * z) + P[18] * z * z) + z * (P[3] + P[19] * z * z);
+    O = (P[1] * x + P[2] * y + P[3] * z) + (P[10] * x + P[16] * y + P[19] * z) * v2;
   } else {
     const C x = v[0], y = v[1];
-    // quadratics xx yy xy = P[3..5], cubics xxx xxy xyy yyy = P[6..9]
+    // quadratics xx yy xy = P[3..5]; u_a^3 at P[6], P[9]
     E = P[0] + x * (P[3] * x + P[5] * y) + P[4] * y * y;
-    O = x * (P[1] + x * (P[6] * x + P[7] * y) + P[8] * y * y) + y * (P[2] + P[9] * y * y);
+    O = (P[1] * x + P[2] * y) + (P[6] * x + P[9] * y) * v2;
   }
 }
 
@@ -373,7 +373,7 @@ __device__ __forceinline__ void sweep_item(
         e1 *= L.tab[p][d][im[d]];
       }
       C E, O;
-      cubic_eo<D>(R + FR_PH, vv, E, O);
+      cubic_eo<D>(R + FR_PH, vv, v2, E, O);
       const C q0 = e0 * (E + O), q1 = e1 * (E - O);
       const C eqm = fd[22];  // 0 on a wall: no equilibrium term going out
       const C eqo = eqm * (pos ? q0 : q1);
@@ -394,7 +394,7 @@ __device__ __forceinline__ void sweep_item(
         }
         ubj *= sgn_in;
         C Eb, Ob;
-        cubic_eo<D>(R + FR_PB, vv, Eb, Ob);
+        cubic_eo<D>(R + FR_PB, vv, v2, Eb, Ob);
         const C r0 = e0 * (Eb + Ob), r1 = e1 * (Eb - Ob);
         outb = as * (G1 * bfo + G2 * ubs + eqm * (pos ? r0 : r1));
         inb = -as * (G1 * bfj + G2 * ubj + (pos ? r1 : r0));
@@ -426,14 +426,14 @@ __device__ __forceinline__ void sweep_item(
       c1 *= L.ctab[d][im[d]];
     }
     C E, O;
-    cubic_eo<D>(cc + CS_SH, vv, E, O);
+    cubic_eo<D>(cc + CS_SH, vv, v2, E, O);
     const C ccoll = cc[CS_CC];
     T* __restrict__ hto = ht + ic * nvp;
     st(hto, k0, h0 - acc0 + ccoll * (c0 * (C(1) + E + O) - h0));
     if (k1 != k0) st(hto, k1, h1 - acc1 + ccoll * (c1 * (C(1) + E - O) - h1));
     if (B2) {
       C Eb, Ob;
-      cubic_eo<D>(cc + CS_SB, vv, Eb, Ob);
+      cubic_eo<D>(cc + CS_SB, vv, v2, Eb, Ob);
       const C kc = cc[CS_KAP];
       T* __restrict__ bto = bt + ic * nvp;
       st(bto, k0, b0 - accb0 + ccoll * (kc * c0 * (C(1) + Eb + Ob) - b0));
@@ -603,14 +603,15 @@ __device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, i
       vv[d] = ax[i];
       c0 *= ctab[d][i];
     }
+    const double v2 = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
     double E, O;
-    cubic_eo<D>(csh, vv, E, O);
+    cubic_eo<D>(csh, vv, v2, E, O);
     const double hn = (ld(hti, k) + A * c0 * (1.0 + E + O)) * inv;
     st(hi, k, hn);
     double bn = 0.0;
     if (D == 2) {
       double Eb, Ob;
-      cubic_eo<D>(csb, vv, Eb, Ob);
+      cubic_eo<D>(csb, vv, v2, Eb, Ob);
       bn = (ld(bt + ic * nvp, k) + A * kc * c0 * (1.0 + Eb + Ob)) * inv;
       st(b + ic * nvp, k, bn);
     }
