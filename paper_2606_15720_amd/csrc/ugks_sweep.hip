@@ -593,8 +593,8 @@ __device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, i
   const unsigned nv = (unsigned)fm.nv;
   crec_t<double>* csh = (crec_t<double>*)(cc + CS_SH);  // scalar loads of the uniform polynomials
   crec_t<double>* csb = (crec_t<double>*)(cc + CS_SB);
-  for (unsigned k = threadIdx.x; k < nv; k += SWT) {
-    const int pk = fm.vidx[k];
+  const T* __restrict__ bti = D == 2 ? bt + ic * nvp : nullptr;
+  auto body = [&](unsigned k, int pk, double htk, double btk, double wk) {
     double vv[3] = {0, 0, 0};
     double c0 = 1.0;
 #pragma unroll
@@ -606,13 +606,13 @@ __device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, i
     const double v2 = vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2];
     double E, O;
     cubic_eo<D>(csh, vv, v2, E, O);
-    const double hn = (ld(hti, k) + A * c0 * (1.0 + E + O)) * inv;
-    st(hi, k, hn);
+    const double hn = (htk + A * c0 * (1.0 + E + O)) * inv;
+    __builtin_nontemporal_store((T)hn, &hi[k]);
     double bn = 0.0;
     if (D == 2) {
       double Eb, Ob;
       cubic_eo<D>(csb, vv, v2, Eb, Ob);
-      bn = (ld(bt + ic * nvp, k) + A * kc * c0 * (1.0 + Eb + Ob)) * inv;
+      bn = (btk + A * kc * c0 * (1.0 + Eb + Ob)) * inv;
       st(b + ic * nvp, k, bn);
     }
     // heat flux of h^{n+1} about U^{n+1} (Eq. reduced_heat_flux)
@@ -620,10 +620,36 @@ __device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, i
     double c2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) c2 += c[d] * c[d];
-    const double s = w[k] * (c2 * hn + bn);
+    const double s = wk * (c2 * hn + bn);
 #pragma unroll
     for (int d = 0; d < D; ++d) acc[d] += s * c[d];
+  };
+  // four velocities per lane per pass, all their loads issued together, so
+  // each lane keeps several HBM reads in flight
+  constexpr unsigned UN = 4;
+  unsigned k = threadIdx.x;
+  for (; k + (UN - 1) * SWT < nv; k += UN * SWT) {
+    int pk[UN];
+    T hv[UN], bv[UN];
+    double wv[UN];
+#pragma unroll
+    for (unsigned u = 0; u < UN; ++u) {
+      hv[u] = __builtin_nontemporal_load(&hti[k + u * SWT]);
+      bv[u] = D == 2 ? bti[k + u * SWT] : T(0);
+    }
+    // the HBM reads go out first, the small cached arrays next, and no
+    // arithmetic is moved between them
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (unsigned u = 0; u < UN; ++u) {
+      pk[u] = fm.vidx[k + u * SWT];
+      wv[u] = w[k + u * SWT];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (unsigned u = 0; u < UN; ++u) body(k + u * SWT, pk[u], (double)hv[u], (double)bv[u], wv[u]);
   }
+  for (; k < nv; k += SWT) body(k, fm.vidx[k], ld(hti, k), D == 2 ? ld(bti, k) : 0.0, w[k]);
   block_sum<3>(acc, L.red);
   if (threadIdx.x == 0)
     for (int d = 0; d < 3; ++d) qn[ic * 3 + d] = d < D ? 0.5 * acc[d] : 0.0;
