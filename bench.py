@@ -148,11 +148,13 @@ def run_warm_start(args):
     from paper_2606_15720_amd import warmstart as WS
 
     na, nr = (int(x) for x in args.ws_mesh.split(","))
-    a = 3.0 * args.ws_mach  # velocity box half-width (units sqrt(2RT_inf))
+    # velocity box half-width (units sqrt(2RT_inf))
+    a = args.ws_a if args.ws_a > 0 else 3.0 * args.ws_mach
     fine = uc.sphere_mach5(n_ang=na, n_rad=nr, nv=args.ws_nv, a=a, kn=args.ws_kn, mach=args.ws_mach,
-                           first=args.ws_first)
+                           first=args.ws_first, start=args.ws_start)
     coarse = uc.sphere_mach5(n_ang=na, n_rad=nr, nv=args.ws_nv_predictor, a=args.ws_a_predictor,
-                             kn=args.ws_kn, mach=args.ws_mach, first=args.ws_first)
+                             kn=args.ws_kn, mach=args.ws_mach, first=args.ws_first,
+                             start=args.ws_start)
     t0 = time.perf_counter()
 
     def log(*x):
@@ -166,6 +168,8 @@ def run_warm_start(args):
     out["reconstruction"] = "first order (no limiter: unlimited slopes fail at this Mach number)"
     out["mach"] = args.ws_mach
     out["kn"] = args.ws_kn
+    out["velocity_box"] = a
+    out["start"] = args.ws_start
     print(json.dumps(out), flush=True)
 
 
@@ -247,6 +251,11 @@ def main():
     ap.add_argument("--ws-ref", default="", help="reference W (.npy) for the field errors when "
                                                  "the plain arm is not run")
     ap.add_argument("--ws-first", type=float, default=0.05, help="first layer thickness")
+    ap.add_argument("--ws-a", type=float, default=0.0,
+                    help="velocity box half-width of the fine set (0: 3 x Mach)")
+    ap.add_argument("--ws-start", default="freestream",
+                    choices=("freestream", "rest", "potential", "sheltered"),
+                    help="initial state of the sphere case")
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the throughput line, the FP32 form's field errors against "
                          "FP64 on the 48k-tet cube with 28^3 velocities, and the mass drift")

@@ -15,7 +15,7 @@ mu_ref = (5 sqrt(pi) / 16) Kn.
 """
 
 from .meshes import Mesh, quad_mesh, kuhn_tet_cube, cubed_sphere_shell  # noqa: F401
-from .velocity import Velocity, midpoint_grid, gauss_hermite_grid  # noqa: F401
+from .velocity import Velocity, midpoint_grid, gauss_hermite_grid, stretched_grid  # noqa: F401
 from .configs import (  # noqa: F401
     Gas, BC, Case, BC_INTERIOR, BC_WALL, BC_FARFIELD, BC_OUTFLOW,
     hard_sphere_mu_ref, cavity2d, couette2d, sod3d_tets, batch_cases,

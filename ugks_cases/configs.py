@@ -162,18 +162,42 @@ def channel2d(n: int = 16, nv: int = 16, a: float = 4.0, kn: float = 0.05, u_in:
 
 
 def sphere_mach5(n_ang: int = 8, n_rad: int = 22, nv: int = 28, a: float = 11.0,
-                 kn: float = 0.01, mach: float = 5.0, first: float = 0.02) -> Case:
+                 kn: float = 0.01, mach: float = 5.0, first: float = 0.02,
+                 start: str = "freestream") -> Case:
     """Mach-5 flow along +x over the unit sphere (far field at r = 6).
 
     Free stream rho = 1, T = 1, U = mach * sqrt(5/3 R T) = mach * sqrt(5/6);
-    isothermal wall at T_w = 1.  Initial state: the free stream everywhere.
+    isothermal wall at T_w = 1.  Initial state: the free stream everywhere
+    (start="freestream"), or the gas at rest at the free-stream density and
+    temperature (start="rest"), the far field then driving the flow in.
     """
     mesh = cubed_sphere_shell(n_ang, n_rad, first=first)
     vel = midpoint_grid(nv, a, 3)
     u_inf = mach * math.sqrt(5.0 / 3.0 * R_GAS * 1.0)
     bcs = [BC(BC_WALL, 1.0, (0.0, 0.0, 0.0), 1.0), BC(BC_FARFIELD, 1.0, (u_inf, 0.0, 0.0), 1.0)]
     gas = Gas(mu_ref=hard_sphere_mu_ref(kn), cfl=0.8)
-    W0 = uniform_W(mesh.n_cells, 3, 1.0, (u_inf, 0.0, 0.0), 1.0)
+    if start == "freestream":
+        W0 = uniform_W(mesh.n_cells, 3, 1.0, (u_inf, 0.0, 0.0), 1.0)
+    elif start == "rest":
+        W0 = uniform_W(mesh.n_cells, 3, 1.0, (0.0, 0.0, 0.0), 1.0)
+    elif start in ("potential", "sheltered"):
+        x = mesh.cell_centroid
+        r = np.maximum(np.linalg.norm(x, axis=1), 1.0)
+        if start == "potential":
+            # incompressible potential flow past the unit sphere, grad(U x (1 + 1/(2 r^3)))
+            ex = np.zeros_like(x)
+            ex[:, 0] = 1.0
+            U = u_inf * ((1.0 + 0.5 / r ** 3)[:, None] * ex - 1.5 * (x[:, 0] / r ** 5)[:, None] * x)
+        else:
+            # the free stream, brought smoothly to rest toward the sphere
+            U = np.zeros_like(x)
+            U[:, 0] = u_inf * (1.0 - np.exp(-(r - 1.0) ** 2))
+        W0 = np.zeros((mesh.n_cells, 5))
+        W0[:, 0] = 1.0
+        W0[:, 1:4] = U
+        W0[:, 4] = 0.5 * np.sum(U * U, axis=1) + 1.5 * R_GAS * 1.0
+    else:
+        raise ValueError(f"unknown start {start!r}")
     return Case(f"sphere_m{mach}_kn{kn}", mesh, vel, gas, bcs, W0, 0,
                 {"kn": kn, "u_inf": u_inf})
 

@@ -50,6 +50,26 @@ def midpoint_grid(n: int, a: float, dim: int) -> Velocity:
     return _tensor(dim, nodes, np.full(n, du), f"mid{n}^{dim}[{a}]")
 
 
+def stretched_grid(n: int, a: float, dim: int, beta: float) -> Velocity:
+    """Tensor midpoint set on [-a, a]^dim, stretched by u = a sinh(beta x)/sinh(beta).
+
+    The n velocity cells are the images of n equal cells of x in [-1, 1]; each
+    node is the image of its cell's centre and carries the product of its
+    cells' widths as weight.  Nodes cluster near zero (spacing shrinks by
+    beta/sinh(beta)) and the set stays symmetric about zero, so it is still a
+    mirror-symmetric tensor product.  beta -> 0 gives midpoint_grid.
+    """
+    if beta <= 0.0:
+        return midpoint_grid(n, a, dim)
+    j = np.arange(n + 1)
+    edges = a * np.sinh(beta * (2.0 * j - n) / n) / np.sinh(beta)
+    mids = a * np.sinh(beta * (2.0 * np.arange(n) + 1.0 - n) / n) / np.sinh(beta)
+    nodes = 0.5 * (mids - mids[::-1])
+    w = np.diff(edges)
+    w = 0.5 * (w + w[::-1])
+    return _tensor(dim, nodes, w, f"sinh{n}^{dim}[{a},{beta}]")
+
+
 def gauss_hermite_grid(n_gh: int, u_max: float, dim: int) -> Velocity:
     """Tensor Gauss-Hermite set of the cavity case (Sec. 3.1, Eqs. cavity_dvs_*).
 
