@@ -163,7 +163,8 @@ def run_warm_start(args):
     out = WS.time_to_residual(fine, coarse, target=args.ws_target, max_steps=args.ws_max_steps,
                               predictor_target=args.ws_predictor_target, log=log,
                               arms_run=tuple(args.ws_arms.split(",")),
-                              ref_out=args.ws_save_ref or None, ref_in=args.ws_ref or None)
+                              ref_out=args.ws_save_ref or None, ref_in=args.ws_ref or None,
+                              deep_target=args.ws_deep or None, deep_max_steps=args.ws_max_steps)
     out["metric"] = "time to 1e-6 density residual (s)"
     out["reconstruction"] = "first order (no limiter: unlimited slopes fail at this Mach number)"
     out["mach"] = args.ws_mach
@@ -253,6 +254,9 @@ def main():
     ap.add_argument("--ws-first", type=float, default=0.05, help="first layer thickness")
     ap.add_argument("--ws-a", type=float, default=0.0,
                     help="velocity box half-width of the fine set (0: 3 x Mach)")
+    ap.add_argument("--ws-deep", type=float, default=0.0,
+                    help="also continue every arm to this residual and compare the fields "
+                         "with the plain FP64 arm's there (0: off)")
     ap.add_argument("--ws-start", default="freestream",
                     choices=("freestream", "rest", "potential", "sheltered"),
                     help="initial state of the sphere case")

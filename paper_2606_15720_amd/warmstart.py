@@ -14,6 +14,8 @@ frame.  That lets flows computed cheaply in 2-D teach a network applied in 3-D.
 
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 from . import ugks as U
@@ -223,7 +225,7 @@ def build_training_set(seed: int = 4, copies: int = 3, log=None):
 def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e-4,
                      max_steps=60000, chunk=1000, flags=16, train_seed=4, log=None,
                      arms_run=("plain64", "maxwell32", "learned32", "learned64"),
-                     ref_out=None, ref_in=None):
+                     ref_out=None, ref_in=None, deep_target=None, deep_max_steps=200000):
     """Plain FP64 from the initial state against predictor + learned warm start.
 
     Arms (all to a density residual <= target, wall time from creation):
@@ -235,6 +237,12 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
     `predictor_target`; its time is charged to every arm that uses it.  The
     network is trained beforehand on snapshots of 2-D runs (its time is
     reported apart: it is trained once, not per case).
+
+    With `deep_target`, every arm then continues to that residual, and the
+    fields of each arm (at `target` and at `deep_target`) are compared with
+    the plain FP64 arm's at `deep_target`: at `target` the remaining error
+    of any run is about target * (decay time in steps), so a reference
+    converged further is what makes a field tolerance meaningful.
     """
     import time
     out = {"case": case_fine.name, "n_cells": case_fine.mesh.n_cells, "nv": case_fine.vel.nv,
@@ -260,18 +268,34 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
             nfall = U.ugks_warm_start(s.h, net)
         steps, r, ok = run_to_residual(s, target, max_steps, chunk, log, name)
         W = s.W()
-        s.close()
         dt = time.perf_counter() - t
         arms[name] = {"precision": precision, "steps": steps, "residual": r, "reached": ok,
                       "seconds": dt + extra_s, "seconds_without_predictor": dt,
                       "fallback_cells": nfall}
+        if deep_target:
+            ds, dr, dok = run_to_residual(s, deep_target, deep_max_steps, chunk, log, name + "-deep")
+            deep[name] = s.W()
+            arms[name]["deep"] = {"target": deep_target, "steps": steps + ds, "residual": dr,
+                                  "reached": dok, "seconds": time.perf_counter() - t + extra_s}
+        s.close()
         return W
 
+    deep = {}
+
     Wref = arm("plain64", U.UGKS_FP64) if "plain64" in arms_run else None
+    Wdeep = deep.get("plain64")
     if Wref is not None and ref_out:
         np.save(ref_out, Wref)
+        if Wdeep is not None:
+            np.save(ref_out.replace(".npy", "") + "_deep.npy", Wdeep)
     if Wref is None and ref_in:
         Wref = np.load(ref_in)
+        dp = ref_in.replace(".npy", "") + "_deep.npy"
+        if deep_target and os.path.exists(dp):
+            Wdeep = np.load(dp)
+    D = case_fine.mesh.dim
+    if Wdeep is not None and "plain64" in arms:
+        arms["plain64"]["field_error_vs_plain64_deep"] = field_errors(Wref, Wdeep, D)
     if not any(a in arms_run for a in ("maxwell32", "learned32", "learned64")):
         out["arms"] = arms
         net.close()
@@ -283,7 +307,6 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
     p.close()
     tp = time.perf_counter() - t
     out["predictor"] = {"steps": psteps, "residual": pr, "reached": pok, "seconds": tp}
-    D = case_fine.mesh.dim
     for name, prec, warm in (("maxwell32", U.UGKS_FP32, False), ("learned32", U.UGKS_FP32, True),
                              ("learned64", U.UGKS_FP64, True)):
         if name not in arms_run:
@@ -291,6 +314,10 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
         W = arm(name, prec, Wp, warm, tp)
         if Wref is not None:
             arms[name]["field_error_vs_plain64"] = field_errors(W, Wref, D)
+        if Wdeep is not None:
+            arms[name]["field_error_vs_plain64_deep"] = field_errors(W, Wdeep, D)
+            if name in deep:
+                arms[name]["deep"]["field_error_vs_plain64_deep"] = field_errors(deep[name], Wdeep, D)
     out["arms"] = arms
     net.close()
     return out
