@@ -68,6 +68,33 @@ def _traffic(precision: int):
     return None if rec is None else rec.get("bytes_per_launch")
 
 
+def _step_traffic(precision: int):
+    """HBM bytes of one whole step (every kernel) from the committed counter
+    summary, or None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sweep_source_sha256_16") != _source_hash():
+        return None
+    rec = t.get(f"step_fp{precision}")
+    return None if rec is None else rec.get("bytes_per_step")
+
+
+def _step_hbm(r, precision: int, updates: int):
+    """The whole step against HBM: algorithmic bytes (f read and written by
+    the sweep, read and written again by stage 2: 4 N_r P per update) and the
+    counters' bytes, over the measured step time."""
+    alg = 4 * (precision // 8) * updates
+    sec = r["ms_per_step"] * 1e-3
+    cnt = _step_traffic(precision)
+    return {"algorithmic_bytes_per_step": alg, "achieved": alg / sec / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": alg / sec / 1e9 / HBM_PEAK_GBS,
+            "counter_bytes_per_step": cnt,
+            "counter_GB_per_s": None if cnt is None else cnt / sec / 1e9}
+
+
 def run_gpu(case, precision: int, steps: int, warmup: int):
     import torch
     from paper_2606_15720_amd.ugks import Solver, ugks_profile_enable, ugks_profile_read
@@ -327,6 +354,7 @@ def main():
                     "frac": r64["achieved"] / HBM_PEAK_GBS,
                     "algorithmic_bytes_per_launch": r64["alg_bytes"]},
         },
+        "step_hbm": _step_hbm(r64, 64, case.mesh.n_cells * case.vel.nv),
         "kernels_ms_per_step": {k: v[1] / max(args.steps, 1) for k, v in r64["prof"].items()},
     }
     if not args.no_fp32:
@@ -337,7 +365,8 @@ def main():
                                "unit": "TFLOP/s", "frac": r32["tflops"] / FP32_PEAK_TFLOPS},
                        "hbm": {"achieved": r32["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": r32["achieved"] / HBM_PEAK_GBS},
-                       "traffic": _traffic(32)}
+                       "traffic": _traffic(32),
+                       "step_hbm": _step_hbm(r32, 32, case.mesh.n_cells * case.vel.nv)}
     if not args.no_batched:
         out["batched"] = run_batched(args.steps, args.warmup)
     if not args.no_cpu_baseline:

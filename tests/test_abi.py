@@ -78,6 +78,25 @@ def test_rejects_invalid_input(what):
     assert ugks.ugks_last_error(None)
 
 
+def test_rejects_empty_mesh_and_velocity_set():
+    import dataclasses
+    case = uc.cavity2d(n=4, nv=4)
+    m = case.mesh
+    empty = dataclasses.replace(
+        m, cell_volume=m.cell_volume[:0], cell_centroid=m.cell_centroid[:0],
+        face_cells=m.face_cells[:0], face_area=m.face_area[:0], face_normal=m.face_normal[:0],
+        face_centroid=m.face_centroid[:0], face_shift=m.face_shift[:0], face_bc=m.face_bc[:0],
+        face_bc_id=m.face_bc_id[:0])
+    with pytest.raises(ugks.UGKSError) as e:
+        ugks.ugks_create(empty, case.vel, case.gas, case.bcs, case.W0[:0])
+    assert e.value.code == ugks.UGKS_EINVAL
+    v = case.vel
+    novel = dataclasses.replace(v, u=v.u[:0], w=v.w[:0])
+    with pytest.raises(ugks.UGKSError) as e:
+        ugks.ugks_create(m, novel, case.gas, case.bcs, case.W0)
+    assert e.value.code == ugks.UGKS_EINVAL
+
+
 def test_autotune_cache_file_round_trip(tmp_path):
     """The tuning cache is host-side: save / load / clear need no GPU."""
     lib = ugks.load_library()

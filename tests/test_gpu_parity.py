@@ -107,6 +107,36 @@ def test_ragged_velocity_tail_and_tiny_mesh(flags):
 
 
 @pytest.mark.parametrize("flags", PATHS)
+def test_single_cell_mesh(flags):
+    # one quad, four wall faces: every stencil point is a mirror ghost
+    _compare_step(uc.cavity2d(n=1, nv=8, kn=0.5), 5, flags)
+
+
+@pytest.mark.parametrize("na,fused", [(64, 1), (65, 0)])
+def test_largest_fused_axis_and_the_first_beyond(na, fused):
+    # the fused sweep keeps a velocity axis of up to 64 nodes in LDS; a longer
+    # axis runs on the staged path, with the same results
+    case = uc.cavity2d(n=3, nv=na, kn=0.5)
+    s = Solver(case)
+    assert s.info["fused"] == fused
+    s.close()
+    _compare_step(case, 3, 0)
+
+
+def test_zero_steps_leave_the_state():
+    case = uc.cavity2d(n=4, nv=8)
+    s = Solver(case)
+    s.step(2)
+    W, h, b = s.state()
+    s.step(0)
+    W2, h2, b2 = s.state()
+    np.testing.assert_array_equal(W2, W)
+    np.testing.assert_array_equal(h2, h)
+    np.testing.assert_array_equal(b2, b)
+    s.close()
+
+
+@pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("kn", [1e-3, 10.0])
 def test_kn_extremes_parity(kn, flags):
     # continuum-like (dt/tau >> 1) and free-molecular-like (dt/tau << 1)
