@@ -539,3 +539,113 @@ def test_collisionless_linear_data_is_transported_exactly(dim):
     np.testing.assert_allclose(h1[deep], exact[deep], rtol=1e-13, atol=1e-13)
     # cells next to walls are not exact (ghost rows): confirms the test is sharp
     assert np.abs(h1 - exact).max() > 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Continuum limit (Sec. 2.1, Eqs. bgk_shakhov, shakhov_fp, interface_distribution):
+# with tau = mu/p, the Chapman-Enskog limit of the BGK-Shakhov model is the
+# Navier-Stokes-Fourier system with viscosity mu and conductivity
+# kappa = c_p mu / Pr (c_p = 5R/2).  A steady channel between two diffuse walls
+# at Kn = 0.01, resolved by 8 cells, must carry through its mid-channel faces
+# the shear stress mu du/dy and the heat flux kappa dT/dy of the gradients
+# across those faces.  This pins the whole time-integrated interface flux
+# (free transport, equilibrium, its space and time slopes and the Shakhov
+# term together): dropping or mis-weighting any of them changes the effective
+# mu or kappa by far more than the 3 % allowed for discretisation.
+def _channel(kn, pr, walls, W0_of_y, ny=8, nv=12):
+    m = uc.quad_mesh(2, ny, periodic_x=True, wall_ids=(0, -1, 1, -1))
+    vel = uc.midpoint_grid(nv, 4.5, 2)
+    bcs = [uc.BC(uc.BC_WALL, 1.0, U, T) for (U, T) in walls]
+    gas = uc.Gas(mu_ref=uc.hard_sphere_mu_ref(kn), Pr=pr)
+    return uc.Case("channel", m, vel, gas, bcs, W0_of_y(m.cell_centroid[:, 1]), 0)
+
+
+def _steady_mid_flux(case, col, chunk=250, max_chunks=60):
+    o = Oracle(case)
+    m = case.mesh
+    horiz = np.abs(m.face_normal[:, 1]) > 0.99
+    mid = horiz & (np.abs(m.face_centroid[:, 1] - 0.5) < 1e-12)
+    prev = None
+    for _ in range(max_chunks):
+        o.step(chunk)
+        F = o.faces()[0]
+        f = np.abs(F[horiz, col])
+        if prev is not None and np.abs(f - prev).max() < 1e-6 * f.max():
+            break
+        prev = f
+    else:
+        raise AssertionError("channel did not reach a steady state")
+    W = o.state(with_h=False)[0]
+    F = o.faces()[0]
+    # no net mass through the mid-channel faces of the closed channel
+    assert np.abs(F[mid, 0]).max() <= 1e-6 * np.abs(F[mid, col]).max()
+    return np.abs(F[mid, col]).mean() / o.dt, W
+
+
+def _mid_cells(y, ny=8):
+    return np.abs(y - (0.5 - 0.5 / ny)) < 1e-12, np.abs(y - (0.5 + 0.5 / ny)) < 1e-12
+
+
+def test_continuum_limit_shear_stress_is_navier_stokes():
+    Uw = 0.1
+    case = _channel(0.01, 2.0 / 3.0, [((0.0, 0.0, 0.0), 1.0), ((Uw, 0.0, 0.0), 1.0)],
+                    lambda y: uc.uniform_W(len(y), 2, 1.0, np.stack([Uw * y, 0 * y], 1), 1.0))
+    flux, W = _steady_mid_flux(case, 1)
+    y = case.mesh.cell_centroid[:, 1]
+    lo, hi = _mid_cells(y)
+    u = W[:, 1] / W[:, 0]
+    RT = (2.0 / 3.0) * (W[:, 3] / W[:, 0] - 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / W[:, 0] ** 2)
+    T = RT[lo | hi].mean() / case.gas.R
+    mu = case.gas.mu_ref * (T / case.gas.T_ref) ** case.gas.omega
+    dudy = (u[hi].mean() - u[lo].mean()) * 8
+    assert flux == pytest.approx(mu * dudy, rel=0.03), flux / (mu * dudy)
+
+
+@pytest.mark.parametrize("pr", [2.0 / 3.0, 1.0])
+def test_continuum_limit_heat_flux_is_fourier_with_the_shakhov_prandtl_number(pr):
+    T0, T1 = 0.95, 1.05
+    case = _channel(0.01, pr, [((0.0, 0.0, 0.0), T0), ((0.0, 0.0, 0.0), T1)],
+                    lambda y: uc.uniform_W(len(y), 2, 1.0 / (T0 + (T1 - T0) * y), (0.0, 0.0),
+                                           T0 + (T1 - T0) * y))
+    flux, W = _steady_mid_flux(case, 3)
+    y = case.mesh.cell_centroid[:, 1]
+    lo, hi = _mid_cells(y)
+    RT = (2.0 / 3.0) * (W[:, 3] / W[:, 0] - 0.5 * (W[:, 1] ** 2 + W[:, 2] ** 2) / W[:, 0] ** 2)
+    T = RT[lo | hi].mean() / case.gas.R
+    mu = case.gas.mu_ref * (T / case.gas.T_ref) ** case.gas.omega
+    kappa = 2.5 * case.gas.R * mu / pr
+    dTdy = (RT[hi].mean() - RT[lo].mean()) / case.gas.R * 8
+    assert flux == pytest.approx(kappa * dTdy, rel=0.03), flux / (kappa * dTdy)
+
+
+def test_continuum_limit_sound_wave_speed_and_damping():
+    # A small standing sound wave in a periodic box (wavelength 1, Kn = 0.002,
+    # dt/tau about 2.6): in the continuum limit its mode oscillates at c k with
+    # c = sqrt(gamma R T), gamma = 5/3 for the monatomic gas (the 2-D b
+    # equation carries the third degree of freedom), and decays at the
+    # Navier-Stokes-Fourier rate k^2 / (2 rho) (4/3 mu + kappa (1/c_v - 1/c_p))
+    # = 7/6 k^2 mu for Pr = 2/3.  Unsteady flow makes the time slope of the
+    # equilibrium non-zero, so this also pins the Gamma_5 term, which the
+    # steady channels cannot see.
+    from scipy.optimize import curve_fit
+
+    nx, eps = 32, 1e-3
+    m = uc.quad_mesh(nx, 2, periodic_x=True, periodic_y=True, wall_ids=(-1, -1, -1, -1))
+    gas = uc.Gas(mu_ref=uc.hard_sphere_mu_ref(0.002))
+    x = m.cell_centroid[:, 0]
+    rho = 1 + eps * np.cos(2 * np.pi * x)
+    W0 = uc.uniform_W(m.n_cells, 2, rho, (0.0, 0.0), rho ** (2.0 / 3.0))  # isentropic
+    o = Oracle(uc.Case("sound", m, uc.midpoint_grid(12, 4.5, 2), gas, [], W0, 0))
+    k = 2 * np.pi
+    c = math.sqrt(5.0 / 3.0 * gas.R * 1.0)
+    n = int(3 * (2 * np.pi / (c * k)) / o.dt)  # three periods
+    amp = np.empty(n)
+    for i in range(n):
+        o.step(1)
+        amp[i] = 2.0 / m.n_cells * np.sum(o.state(with_h=False)[0][:, 0] * np.cos(2 * np.pi * x))
+    t = o.dt * np.arange(1, n + 1)
+    p, _ = curve_fit(lambda t, A, al, w, ph: A * np.exp(-al * t) * np.cos(w * t + ph), t, amp,
+                     p0=[eps, 0.05, c * k, 0.0])
+    alpha_ns = 7.0 / 6.0 * k * k * gas.mu_ref
+    assert p[2] == pytest.approx(c * k, rel=0.01)
+    assert p[1] == pytest.approx(alpha_ns, rel=0.15), p[1] / alpha_ns
