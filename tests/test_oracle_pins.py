@@ -307,6 +307,33 @@ def test_moving_uniform_gas_between_comoving_walls_pr1():
     np.testing.assert_allclose(h, h0, rtol=0, atol=2e-14 * h0.max())
 
 
+@pytest.mark.parametrize("dim,kind", [(2, uc.BC_FARFIELD), (2, uc.BC_OUTFLOW), (3, uc.BC_FARFIELD)])
+def test_uniform_stream_through_open_boundaries_is_preserved(dim, kind):
+    # Reading R16: a far-field face takes the free stream where the flow
+    # enters and the cell's own state where it leaves; an outflow face takes
+    # the cell's own state.  A box open on every side and filled with the free
+    # stream itself therefore sees no net flux anywhere (Pr = 1: the small
+    # discrete heat flux of a moving Maxwellian is inert).
+    U = (0.3, -0.2, 0.1)[:dim]
+    if dim == 2:
+        mesh, nb, nv = uc.quad_mesh(6, 6, wall_ids=(0, 0, 0, 0)), 1, 16
+    else:
+        mesh, nb, nv = uc.kuhn_tet_cube(3, jitter=0.15), 6, 10
+    bnd = mesh.face_bc != uc.BC_INTERIOR
+    mesh.face_bc = np.where(bnd, kind, mesh.face_bc).astype(mesh.face_bc.dtype)
+    vel = uc.midpoint_grid(nv, 5.0, dim)
+    U3 = tuple(U) + (0.0,) * (3 - dim)
+    bcs = [uc.BC(kind, 1.0, U3, 1.0) for _ in range(nb)]
+    gas = uc.Gas(mu_ref=uc.hard_sphere_mu_ref(0.05), Pr=1.0)
+    case = uc.Case("stream", mesh, vel, gas, bcs, uc.uniform_W(mesh.n_cells, dim, 1.0, U, 1.0), 0)
+    o = Oracle(case)
+    W0, h0, _, _ = o.state()
+    o.step(10)
+    W, h, _, _ = o.state()
+    np.testing.assert_allclose(W, W0, rtol=0, atol=2e-14)
+    np.testing.assert_allclose(h, h0, rtol=0, atol=2e-14 * h0.max())
+
+
 @pytest.mark.parametrize("which", ["cavity", "sod3d"])
 def test_discrete_conservation_balance(which):
     if which == "cavity":
