@@ -51,8 +51,15 @@ SWEEP_SRC = os.path.join(ROOT, "paper_2606_15720_amd", "csrc", "ugks_sweep.hip")
 
 
 def _source_hash() -> str:
-    with open(SWEEP_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sweep source's code: comments and blank space are left out,
+    so a comment edit does not invalidate counters taken on the same kernels."""
+    import re
+    with open(SWEEP_SRC) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    code = " ".join(src.split())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def _traffic(precision: int):
@@ -62,7 +69,7 @@ def _traffic(precision: int):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("sweep_source_sha256_16") != _source_hash():
+    if t.get("sweep_code_sha256_16") != _source_hash():
         return None  # the kernel changed since the counters were taken
     rec = t.get(f"fp{precision}")
     return None if rec is None else rec.get("bytes_per_launch")
@@ -76,7 +83,7 @@ def _step_traffic(precision: int):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("sweep_source_sha256_16") != _source_hash():
+    if t.get("sweep_code_sha256_16") != _source_hash():
         return None
     rec = t.get(f"step_fp{precision}")
     return None if rec is None else rec.get("bytes_per_step")

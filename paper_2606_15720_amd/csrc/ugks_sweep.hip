@@ -1,29 +1,30 @@
 // Fused velocity sweep for tensor-product, mirror-symmetric velocity sets.
 //
-// One work-group owns one cell and sweeps its whole velocity space.  Each
-// lane owns a mirror pair of velocities (u, -u): for every face of the cell
+// A work item is one cell and one block of its velocity space.  Each lane
+// owns a mirror pair of velocities (u, -u): for every face of the cell
 // exactly one of the two leaves the cell, so the lane evaluates one
 // time-integrated flux from the cell's own reconstruction (outgoing) and one
 // from the neighbour's reconstruction (incoming), with no divergence between
-// lanes.  Face and cell data are wave-uniform and staged in LDS once per
-// work-group:
+// lanes.  The face and cell data are wave-uniform:
 //   * the Maxwellians g0, g_cell and the wall Maxwellian factor over the
-//     velocity axes, so exp(-lambda |u - U|^2) is a product of three LDS
-//     table entries;
+//     velocity axes and are staged in LDS once per work item, so
+//     exp(-lambda |u - U|^2) is a product of three table entries;
 //   * every equilibrium term of the interface distribution (Eqs.
-//     interface_distribution, c123, c45 integrated over the step) as g0(u)
-//     times a cubic polynomial, evaluated from the lane's monomials with the
-//     even/odd split P(-u) = E(u) - O(u);
-//   * the least-squares stencils of the cell and of each neighbour.
+//     interface_distribution, c123, c45 integrated over the step) is g0(u)
+//     times a cubic polynomial c + l.u + u^T Q u + (kappa . u)|u|^2, evaluated
+//     with the even/odd split P(-u) = E(u) - O(u);
+//   * those polynomials and the least-squares stencils of the cell and of
+//     each neighbour are read from the face and cell records through the
+//     scalar cache.
 // The conservative update needs, per cell, sum_j sigma_j S_j F_j / V with
 // F_j = sum_k w_k psi_k H_jk (Eqs. macro_update, macro_flux); the sweep
 // regroups that sum by velocity, sum_k w_k psi_k (sum_j sigma_j S_j H_jk / V),
-// accumulates it per lane and reduces it once per work-group, so there are
-// no atomics and the result is deterministic.  The first stage (Eq. f_tilde)
-// is applied in the same pass.  All loads of an iteration (the cell's
-// stencil at u and -u, each neighbour's stencil at the incoming member) are
-// issued before any arithmetic so their latency overlaps.  Stage 2 (Eq. f_final) and the
-// heat flux of the new distribution are fused in a second kernel.
+// accumulates it per lane and reduces it once per work item, so there are no
+// atomics and the result is deterministic.  The first stage (Eq. f_tilde) is
+// applied in the same pass.  All loads of an iteration (the cell's stencil at
+// u and -u, each neighbour's stencil at the incoming member) are issued
+// before any arithmetic so their latency overlaps.  Stage 2 (Eq. f_final)
+// and the heat flux of the new distribution are fused in a second kernel.
 #include "ugks_device.h"
 
 namespace ugks {
