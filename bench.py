@@ -290,6 +290,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="instead of the throughput line, only the batched form's record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=20,
                     help="hexes per edge of the oracle's sample (20 = the full workload)")
@@ -336,6 +338,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_per_launch": n * 8, "launches": 3}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(run_batched(args.steps, args.warmup)), flush=True)
         return
     if args.warm_start:
         run_warm_start(args)

@@ -195,16 +195,30 @@ __device__ __forceinline__ void sweep_item(
   const unsigned nthr = blockDim.x;  // lanes of the work-group, one mirror pair each
   const int na = fm.na;
   {
-    // stage this cell's face and cell tables in LDS (faces 0..3, then the cell)
-    const int per = D * na, n_all = 5 * per;
-    for (int t = threadIdx.x; t < n_all; t += nthr) {
-      const int p = t / per, r = t % per, d = r / na, n = r % na;
-      const int64_t e = p < 4 ? (int64_t)ci0[CRI_F0 + CRI_FS * p] : sc.nf + ic;
-      const C v = tabs[e * per + d * na + n];
-      if (p < 4) L.tab[p][d][n] = v;
-      else L.ctab[d][n] = v;
+    // Stage this cell's face and cell tables in LDS (faces 0..3, then the
+    // cell).  The five table entities are scalar loads; each wave copies
+    // whole (entity, axis) rows, one node per lane (na <= 64, and the
+    // work-group is 1, 2 or 4 waves), and with the row loop unrolled all of
+    // a wave's loads are in flight together.
+    const int64_t ent[5] = {(int64_t)ci0[CRI_F0], (int64_t)ci0[CRI_F0 + CRI_FS],
+                            (int64_t)ci0[CRI_F0 + 2 * CRI_FS], (int64_t)ci0[CRI_F0 + 3 * CRI_FS],
+                            sc.nf + ic};
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned wmask = (nthr >> 6) - 1;
+    if (lane < (unsigned)na) {
+      C v[5 * D];
+#pragma unroll
+      for (int row = 0; row < 5 * D; ++row)
+        if (((unsigned)row & wmask) == wv) v[row] = tabs[(ent[row / D] * D + row % D) * na + lane];
+#pragma unroll
+      for (int row = 0; row < 5 * D; ++row)
+        if (((unsigned)row & wmask) == wv) {
+          if (row / D < 4) L.tab[row / D][row % D][lane] = v[row];
+          else L.ctab[row % D][lane] = v[row];
+        }
+      if (wv == 0) L.ax[lane] = fm.axis[lane];
     }
-    for (int t = threadIdx.x; t < na; t += nthr) L.ax[t] = fm.axis[t];
     __syncthreads();
   }
   constexpr int NM = D + 2;
