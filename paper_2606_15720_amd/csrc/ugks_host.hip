@@ -614,10 +614,11 @@ void enqueue_step_fused(ugks_ctx* c) {
   // 4 macroscopic reconstruction; 6.1-6.6 interface equilibrium
   TIMED(KK_GRADW, launch_gradW(D, m, c->bcs, g, B.W, B.gW, B.flag, s));
   TIMED(KK_FACE_EQ, launch_face_eq(D, m, c->bcs, g, B.W, B.gW, B.q, B.frec, B.flag, s));
-  // 7 wall densities; far-field ghost rows
-  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, c->fmesh, g, B.h, B.frec, B.flag, s));
+  // 7 far-field ghost rows (the wall cells' stencils may read them), then
+  // the wall densities
   if (c->fmesh.nff)
     TIMED(KK_WALL, launch_ghost_rows(D, P, c->fmesh, v, B.frec, B.h, B.b, B.flag, s));
+  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, c->fmesh, g, B.h, B.frec, B.flag, s));
   // Maxwellian axis tables of every face and cell of this step
   TIMED(KK_TABLES, launch_tables(D, m, c->fmesh, g, B.frec, B.prim, B.cs, B.tabs, B.flag, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep
@@ -852,8 +853,8 @@ void enqueue_batch_step(ugks_batch* b, int par) {
   HIP_TRY(launch_gradW_b(D, bd, b->ncell, s));
   HIP_TRY(launch_face_eq_b(D, bd, b->nface, s));
   // 7 wall densities; far-field ghost rows
-  HIP_TRY(launch_wall_rho_b(D, P, bd, b->nwall, s));
   HIP_TRY(launch_ghost_rows_b(D, P, bd, b->nff, s));
+  HIP_TRY(launch_wall_rho_b(D, P, bd, b->nwall, s));
   // Maxwellian axis tables
   HIP_TRY(launch_tables_b(D, bd, b->ntab, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep, one persistent launch
@@ -1065,8 +1066,8 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
     HIP_TRY(launch_cell_prep_b(b->D, bd, b->ncell, 0, b->stream));
     HIP_TRY(launch_gradW_b(b->D, bd, b->ncell, b->stream));
     HIP_TRY(launch_face_eq_b(b->D, bd, b->nface, b->stream));
-    HIP_TRY(launch_wall_rho_b(b->D, b->prec, bd, b->nwall, b->stream));
     HIP_TRY(launch_ghost_rows_b(b->D, b->prec, bd, b->nff, b->stream));
+    HIP_TRY(launch_wall_rho_b(b->D, b->prec, bd, b->nwall, b->stream));
     HIP_TRY(launch_tables_b(b->D, bd, b->ntab, b->stream));
   }
   if (fixed_bv || fixed_tile) {

@@ -715,57 +715,95 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
   }
   for (int t = threadIdx.x; t < na; t += blockDim.x) S.ax[t] = fm.axis[t];
   __syncthreads();
-  const int nfc = m.nfc[L];
   double nrm[3] = {0, 0, 0}, dxl[3] = {0, 0, 0};
   for (int d = 0; d < D; ++d) {
     nrm[d] = m.fnorm[f * 3 + d];
     dxl[d] = m.fdxL[f * 3 + d];
   }
+  // The wall cell's padded stencil from its fused record: the row across
+  // each face (a neighbour, the zero row with coefficient 0 across a wall,
+  // the ghost row across a far-field or outflow face) and the least-squares
+  // coefficients, wave-uniform for the whole loop.
+  crec_i_t* ci = (crec_i_t*)(fm.crec_i + L * CRI);
+  crec_t<double>* cd = (crec_t<double>*)(fm.crec_d + L * CRD);
+  const T* __restrict__ hl_row = h + L * nvp;
+  const T* hs_row[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) hs_row[s] = h + (int64_t)ci[2 + s] * nvp;
   double acc[2] = {0.0, 0.0};
-  for (int64_t k = threadIdx.x; k < v.nv; k += blockDim.x) {
-    const int pk = fm.vidx[k];
-    double u[3] = {0, 0, 0};
-    int id[3] = {0, 0, 0};
-    double un = 0.0;
-    for (int d = 0; d < D; ++d) {
-      id[d] = (pk >> (8 * d)) & 255;
-      u[d] = S.ax[id[d]];
-      un += u[d] * nrm[d];
+  // Four velocities per lane per pass: their axis indices are loaded one
+  // pass ahead, and the rows of the incident ones (u.n > 0, the only ones
+  // that read f) are loaded together before any arithmetic.
+  constexpr unsigned UN = 4;
+  const unsigned nb = blockDim.x, nv = (unsigned)v.nv;
+  int pkn[UN];
+#pragma unroll
+  for (unsigned u = 0; u < UN; ++u) {
+    const unsigned kk = threadIdx.x + u * nb;
+    pkn[u] = kk < nv ? fm.vidx[kk] : 0;
+  }
+  for (unsigned k0 = threadIdx.x; k0 < nv; k0 += UN * nb) {
+    int pk[UN];
+#pragma unroll
+    for (unsigned u = 0; u < UN; ++u) {
+      pk[u] = pkn[u];
+      const unsigned kk = k0 + (UN + u) * nb;
+      pkn[u] = kk < nv ? fm.vidx[kk] : 0;
     }
-    if (un > 0.0) {
-      const double hl = ld(h, L * nvp + k);
-      double gr[3] = {0, 0, 0};
-      for (int p = 0; p < nfc; ++p) {
-        const int j = m.cnbr[L * MAXF + p];
-        double hj;
-        if (j >= 0) {
-          hj = ld(h, (int64_t)j * nvp + k);
-        } else {
-          // a wall row (the cell's own value) adds nothing; a far-field or
-          // outflow row is the ghost Maxwellian of that face
-          const int f2 = m.cface[L * MAXF + p];
-          if (m.fbc[f2] == UGKS_BC_WALL) continue;
-          const double* R2 = &frec[(int64_t)f2 * FREC];
-          double c2 = 0.0;
-          for (int d = 0; d < D; ++d) {
-            const double c = u[d] - R2[FR_GU + d];
-            c2 += c * c;
-          }
-          hj = R2[FR_GC] * exp(-R2[FR_GLAM] * c2);
+    double uu[UN][3], un[UN];
+    int id[UN][3];
+    bool inc[UN], out[UN];
+#pragma unroll
+    for (unsigned u = 0; u < UN; ++u) {
+      const bool valid = k0 + u * nb < nv;
+      un[u] = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        id[u][d] = (pk[u] >> (8 * d)) & 255;
+        uu[u][d] = d < D ? S.ax[id[u][d]] : 0.0;
+        if (d < D) un[u] += uu[u][d] * nrm[d];
+      }
+      inc[u] = valid && un[u] > 0.0;
+      out[u] = valid && un[u] < 0.0;
+    }
+    double hl[UN], hs[UN][4], wk[UN];
+#pragma unroll
+    for (unsigned u = 0; u < UN; ++u) {
+      const unsigned kk = k0 + u * nb;
+      hl[u] = 0.0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) hs[u][s] = 0.0;
+      if (inc[u]) {
+        hl[u] = ld(hl_row, kk);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) hs[u][s] = ld(hs_row[s], kk);
+      }
+      wk[u] = (inc[u] || out[u]) ? v.w[kk] : 0.0;
+    }
+#pragma unroll
+    for (unsigned u = 0; u < UN; ++u) {
+      if (inc[u]) {
+        // incident: free transport of the wall cell's reconstruction
+        double gr[3] = {0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double dh = hs[u][s] - hl[u];
+#pragma unroll
+          for (int d = 0; d < D; ++d) gr[d] += cd[d * 4 + s] * dh;
         }
-        const double dh = hj - hl;
-        for (int d = 0; d < D; ++d) gr[d] += m.lsG[(L * 3 + d) * MAXF + p] * dh;
+        double hf = hl[u], ugh = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          hf += dxl[d] * gr[d];
+          ugh += uu[u][d] * gr[d];
+        }
+        acc[0] += wk[u] * un[u] * (dt * hf - 0.5 * dt * dt * ugh);
+      } else if (out[u]) {
+        double M = S.wx[0][id[u][0]];
+#pragma unroll
+        for (int d = 1; d < D; ++d) M *= S.wx[d][id[u][d]];
+        acc[1] += wk[u] * un[u] * M;
       }
-      double hf = hl, ugh = 0.0;
-      for (int d = 0; d < D; ++d) {
-        hf += dxl[d] * gr[d];
-        ugh += u[d] * gr[d];
-      }
-      acc[0] += v.w[k] * un * (dt * hf - 0.5 * dt * dt * ugh);
-    } else if (un < 0.0) {
-      double M = S.wx[0][id[0]];
-      for (int d = 1; d < D; ++d) M *= S.wx[d][id[d]];
-      acc[1] += v.w[k] * un * M;
     }
   }
   block_sum<2>(acc, S.red);
