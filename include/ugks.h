@@ -144,6 +144,10 @@ typedef struct {
  *                     (Sec. 2.2 steps 4 and 5) is zero, so each face sees the
  *                     piecewise-constant states of its two cells; robust where
  *                     unlimited second-order slopes overshoot (strong shocks).
+ *              bit 5: replay each step from a HIP graph of its kernels
+ *                     (captured at the first step that can use it; not on the
+ *                     null stream, nor while profiling).  Same results as
+ *                     kernel-by-kernel launches.
  *   The fused sweep (one pass for reconstruction, interface flux, moment
  *   sums and the first stage) applies when the velocity set is a tensor
  *   product of one 1-D node set symmetric about zero, listed with the first

@@ -1140,11 +1140,51 @@ int ugks_create(const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas*
   return UGKS_OK;
 }
 
+namespace {
+
+// Capture one step per order of the q / q^{n+1} buffers as HIP graphs.  The
+// step records kernels only (no memset or copy), and two captures swap the
+// buffers twice, so the context ends as it started.
+void capture_step_graphs(ugks_ctx* c) {
+  c->graph_q0 = c->buf.q;
+  for (int par = 0; par < 2; ++par) {
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_step(c);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(c->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIP_TRY(hipStreamEndCapture(c->stream, &c->graph[par]));
+    HIP_TRY(hipGraphInstantiate(&c->graph_exec[par], c->graph[par], nullptr, nullptr, 0));
+  }
+}
+
+// One step: a graph replay where asked for (flags bit 5) and where one
+// applies (not profiling, the heat flux of the current f known, a stream
+// that can be captured), else the kernels one by one.  Both run the same
+// kernels with the same arguments.
+void run_step(ugks_ctx* c) {
+  const bool graphs = (c->flags & 32) && !c->profiling && c->stream != nullptr;
+  if (!graphs || !c->q_valid) {
+    enqueue_step(c);
+    return;
+  }
+  if (!c->graph_exec[0]) capture_step_graphs(c);
+  const int par = c->buf.q == c->graph_q0 ? 0 : 1;
+  HIP_TRY(hipGraphLaunch(c->graph_exec[par], c->stream));
+  if (c->fused) std::swap(c->buf.q, c->buf.qn);  // as the fused step does on the host
+}
+
+}  // namespace
+
 int ugks_step(ugks_ctx* c, int32_t n_steps, double* residual_out) {
   if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
   if (n_steps < 0) return set_err(c, UGKS_EINVAL, "n_steps < 0");
   try {
-    for (int32_t s = 0; s < n_steps; ++s) enqueue_step(c);
+    for (int32_t s = 0; s < n_steps; ++s) run_step(c);
     int32_t flag = 0;
     HIP_TRY(hipMemcpyAsync(&flag, c->buf.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     double res[2] = {0.0, 0.0};
@@ -1369,6 +1409,10 @@ int ugks_profile_read(ugks_ctx* c, ugks_kernel_time* out, int32_t max, int32_t* 
 void ugks_destroy(ugks_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int par = 0; par < 2; ++par) {
+    if (c->graph_exec[par]) (void)hipGraphExecDestroy(c->graph_exec[par]);
+    if (c->graph[par]) (void)hipGraphDestroy(c->graph[par]);
+  }
   for (auto& e : c->prof_events) {
     (void)hipEventDestroy(e.second.first);
     (void)hipEventDestroy(e.second.second);

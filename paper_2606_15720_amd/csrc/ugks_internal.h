@@ -259,6 +259,11 @@ struct ugks_ctx {
   int D = 0, kxi = 0, nr = 0, prec = 64, Bv = 64, flags = 0;
   bool fused = false;       // tensor-product symmetric velocity set, walls / interior only
   bool q_valid = false;     // buf.q holds the heat flux of the current h
+  // HIP graphs of one step, one per order of the q / q^{n+1} buffers (the
+  // step swaps them); graph_q0 is buf.q when graph 0 was captured
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  const double* graph_q0 = nullptr;
   ugks::FusedMesh fmesh{};  // static records of the fused sweep
   ugks::SweepSched sched{};
   int64_t nc = 0, nf = 0, nv = 0, nvp = 0;

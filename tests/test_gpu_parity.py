@@ -123,6 +123,41 @@ def test_largest_fused_axis_and_the_first_beyond(na, fused):
     _compare_step(case, 3, 0)
 
 
+GRAPH = 32  # ugks_options.flags bit: replay each step from a HIP graph
+
+
+@pytest.mark.parametrize("which,flags,prec", [("cavity2d", 0, 64), ("cavity2d", STAGED, 64),
+                                              ("sod3d", 0, 32)])
+def test_step_graph_replays_equal_eager_steps(which, flags, prec):
+    # steps replayed from HIP graphs against the same steps enqueued kernel
+    # by kernel, bit for bit; eager work (the
+    # moment and heat-flux readouts) runs between replays, and set_state
+    # forces an eager step before the graphs resume
+    from paper_2606_15720_amd.ugks import UGKS_FP32
+    case = uc.cavity2d(n=8, nv=12, kn=0.1) if which == "cavity2d" else uc.sod3d_tets(n=3, nv=10)
+    p = UGKS_FP32 if prec == 32 else 64
+    g = Solver(case, flags=flags | GRAPH, precision=p)
+    e = Solver(case, flags=flags, precision=p)
+    for n in (1, 3, 2, 5):
+        g.step(n)
+        e.step(n)
+        Wg, hg, bg = g.state()
+        We, he, be = e.state()
+        np.testing.assert_array_equal(Wg, We)
+        np.testing.assert_array_equal(hg, he)
+        np.testing.assert_array_equal(bg, be)
+        np.testing.assert_array_equal(g.moments(2), e.moments(2))
+        g.moments(1)
+    g.set_state(Wg, hg, bg)
+    e.set_state(We, he, be)
+    g.step(4)
+    e.step(4)
+    np.testing.assert_array_equal(g.state()[1], e.state()[1])
+    np.testing.assert_array_equal(g.W(), e.W())
+    g.close()
+    e.close()
+
+
 def test_zero_steps_leave_the_state():
     case = uc.cavity2d(n=4, nv=8)
     s = Solver(case)
