@@ -1135,6 +1135,12 @@ int ugks_create(const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas*
     ugks_destroy(c.release());
     int code = (e.e == hipErrorOutOfMemory) ? UGKS_ENOMEM : UGKS_EHIP;
     return set_err(nullptr, code, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    ugks_destroy(c.release());
+    return set_err(nullptr, UGKS_ENOMEM, "host memory allocation failed");
+  } catch (...) {
+    ugks_destroy(c.release());
+    return set_err(nullptr, UGKS_EHIP, "internal error");
   }
   *out = c.release();
   return UGKS_OK;
@@ -1204,7 +1210,7 @@ int ugks_step(ugks_ctx* c, int32_t n_steps, double* residual_out) {
     }
   } catch (const HipFail& e) {
     return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(set_err, c)
   return UGKS_OK;
 }
 
@@ -1240,7 +1246,7 @@ int ugks_moments(ugks_ctx* c, int32_t which, double* out, int32_t on_device) {
       std::memcpy(out, user.data(), user.size() * sizeof(double));
   } catch (const HipFail& e) {
     return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(set_err, c)
   return UGKS_OK;
 }
 
@@ -1274,7 +1280,7 @@ int ugks_get_state(ugks_ctx* c, double* W, double* h, double* b) {
     }
   } catch (const HipFail& e) {
     return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(set_err, c)
   return UGKS_OK;
 }
 
@@ -1312,7 +1318,7 @@ int ugks_set_state(ugks_ctx* c, const double* W, const double* h, const double* 
     HIP_TRY(hipMemset(c->buf.flag, 0, 4 * sizeof(int32_t)));
   } catch (const HipFail& e) {
     return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(set_err, c)
   return UGKS_OK;
 }
 
@@ -1338,7 +1344,7 @@ int ugks_face_data(ugks_ctx* c, double* F, double* rho_w) {
     }
   } catch (const HipFail& e) {
     return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(set_err, c)
   return UGKS_OK;
 }
 
@@ -1372,7 +1378,7 @@ int ugks_profile_enable(ugks_ctx* c, int32_t on) {
     c->profiling = on != 0;
   } catch (const HipFail& e) {
     return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(set_err, c)
   return UGKS_OK;
 }
 
@@ -1402,7 +1408,7 @@ int ugks_profile_read(ugks_ctx* c, ugks_kernel_time* out, int32_t max, int32_t* 
     if (n_out) *n_out = n;
   } catch (const HipFail& e) {
     return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(set_err, c)
   return UGKS_OK;
 }
 
@@ -1444,6 +1450,12 @@ int ugks_batch_create(const ugks_case* cases, int32_t n_cases, const ugks_option
     ugks_batch_destroy(b.release());
     int code = (e.e == hipErrorOutOfMemory) ? UGKS_ENOMEM : UGKS_EHIP;
     return batch_err(nullptr, code, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    ugks_batch_destroy(b.release());
+    return batch_err(nullptr, UGKS_ENOMEM, "host memory allocation failed");
+  } catch (...) {
+    ugks_batch_destroy(b.release());
+    return batch_err(nullptr, UGKS_EHIP, "internal error");
   }
   *out = b.release();
   return UGKS_OK;
@@ -1478,7 +1490,7 @@ int ugks_batch_step(ugks_batch* b, int32_t n_steps, double* residual_out) {
       }
   } catch (const HipFail& e) {
     return batch_err(b, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(batch_err, b)
   return UGKS_OK;
 }
 
@@ -1542,49 +1554,57 @@ const char* ugks_batch_last_error(const ugks_batch* b) {
 }
 
 int ugks_autotune_save(const char* path) {
-  if (!path) return UGKS_EINVAL;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  std::ofstream f(path);
-  if (!f) return UGKS_EINVAL;
-  f << "ugks-autotune 1\n";
-  for (auto& e : g_tune_case)
-    f << "case " << e.first << " : " << e.second.chunk_pairs << " " << e.second.tile << " "
-      << e.second.us << "\n";
-  for (auto& e : g_tune_batch) f << e.first << " : " << e.second << "\n";
-  return f.good() ? UGKS_OK : UGKS_EINVAL;
+  try {
+    if (!path) return UGKS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::ofstream f(path);
+    if (!f) return UGKS_EINVAL;
+    f << "ugks-autotune 1\n";
+    for (auto& e : g_tune_case)
+      f << "case " << e.first << " : " << e.second.chunk_pairs << " " << e.second.tile << " "
+        << e.second.us << "\n";
+    for (auto& e : g_tune_batch) f << e.first << " : " << e.second << "\n";
+    return f.good() ? UGKS_OK : UGKS_EINVAL;
+  } catch (...) {
+    return UGKS_EHIP;  // no exception crosses the ABI
+  }
 }
 
 int ugks_autotune_load(const char* path) {
-  if (!path) return UGKS_EINVAL;
-  std::ifstream f(path);
-  if (!f) return UGKS_EINVAL;
-  std::string line;
-  if (!std::getline(f, line) || line != "ugks-autotune 1") return UGKS_EINVAL;
-  std::map<std::string, TuneCase> cs;
-  std::map<std::string, int> bs;
-  while (std::getline(f, line)) {
-    if (line.empty()) continue;
-    const size_t sep = line.find(" : ");
-    if (sep == std::string::npos) return UGKS_EINVAL;
-    const std::string key = line.substr(0, sep);
-    std::istringstream val(line.substr(sep + 3));
-    if (key.rfind("case ", 0) == 0) {
-      TuneCase t;
-      if (!(val >> t.chunk_pairs >> t.tile >> t.us) || t.chunk_pairs < 1 || t.tile < 1)
+  try {
+    if (!path) return UGKS_EINVAL;
+    std::ifstream f(path);
+    if (!f) return UGKS_EINVAL;
+    std::string line;
+    if (!std::getline(f, line) || line != "ugks-autotune 1") return UGKS_EINVAL;
+    std::map<std::string, TuneCase> cs;
+    std::map<std::string, int> bs;
+    while (std::getline(f, line)) {
+      if (line.empty()) continue;
+      const size_t sep = line.find(" : ");
+      if (sep == std::string::npos) return UGKS_EINVAL;
+      const std::string key = line.substr(0, sep);
+      std::istringstream val(line.substr(sep + 3));
+      if (key.rfind("case ", 0) == 0) {
+        TuneCase t;
+        if (!(val >> t.chunk_pairs >> t.tile >> t.us) || t.chunk_pairs < 1 || t.tile < 1)
+          return UGKS_EINVAL;
+        cs[key.substr(5)] = t;
+      } else if (key.rfind("batch", 0) == 0) {
+        int th = 0;
+        if (!(val >> th) || (th != 64 && th != 128 && th != 256)) return UGKS_EINVAL;
+        bs[key] = th;
+      } else {
         return UGKS_EINVAL;
-      cs[key.substr(5)] = t;
-    } else if (key.rfind("batch", 0) == 0) {
-      int th = 0;
-      if (!(val >> th) || (th != 64 && th != 128 && th != 256)) return UGKS_EINVAL;
-      bs[key] = th;
-    } else {
-      return UGKS_EINVAL;
+      }
     }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& e : cs) g_tune_case[e.first] = e.second;
+    for (auto& e : bs) g_tune_batch[e.first] = e.second;
+    return UGKS_OK;
+  } catch (...) {
+    return UGKS_EHIP;  // no exception crosses the ABI
   }
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  for (auto& e : cs) g_tune_case[e.first] = e.second;
-  for (auto& e : bs) g_tune_batch[e.first] = e.second;
-  return UGKS_OK;
 }
 
 void ugks_autotune_clear(void) {

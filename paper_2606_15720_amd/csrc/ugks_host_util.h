@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -48,6 +50,23 @@ inline T* upload(ugks_ctx* c, const std::vector<T>& v) {
 inline void fail_if(bool cond, const std::string& msg) {
   if (cond) throw InvalidArg{msg};
 }
+
+// The remaining handlers of a C-ABI entry point, after its HipFail handler:
+// no exception crosses the ABI.  ERR(obj, code, msg) records the message
+// and returns the code.
+#define UGKS_CATCH_REST(ERR, OBJ)                                                   \
+  catch (const ::ugks::host::InvalidArg& e_) {                                     \
+    return ERR(OBJ, UGKS_EINVAL, e_.msg);                                           \
+  }                                                                                 \
+  catch (const std::bad_alloc&) {                                                   \
+    return ERR(OBJ, UGKS_ENOMEM, "host memory allocation failed");                  \
+  }                                                                                 \
+  catch (const std::exception& e_) {                                                \
+    return ERR(OBJ, UGKS_EHIP, std::string("internal error: ") + e_.what());        \
+  }                                                                                 \
+  catch (...) {                                                                     \
+    return ERR(OBJ, UGKS_EHIP, "internal error");                                   \
+  }
 
 }  // namespace host
 }  // namespace ugks

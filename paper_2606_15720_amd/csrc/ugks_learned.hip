@@ -605,6 +605,12 @@ int ugks_mlp_create(const float* params, const float* in_scale, const float* out
     ugks_mlp_destroy(n.release());
     return mlp_err(nullptr, e.e == hipErrorOutOfMemory ? UGKS_ENOMEM : UGKS_EHIP,
                    std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    ugks_mlp_destroy(n.release());
+    return mlp_err(nullptr, UGKS_ENOMEM, "host memory allocation failed");
+  } catch (...) {
+    ugks_mlp_destroy(n.release());
+    return mlp_err(nullptr, UGKS_EHIP, "internal error");
   }
   *out = n.release();
   return UGKS_OK;
@@ -617,7 +623,7 @@ int ugks_mlp_get_params(ugks_mlp* n, float* params) {
     HIP_TRY(hipStreamSynchronize(n->stream));
   } catch (const HipFail& e) {
     return mlp_err(n, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(mlp_err, n)
   return UGKS_OK;
 }
 
@@ -631,7 +637,7 @@ int ugks_mlp_set_box(ugks_mlp* n, const float* lo, const float* hi) {
     HIP_TRY(hipStreamSynchronize(n->stream));
   } catch (const HipFail& e) {
     return mlp_err(n, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(mlp_err, n)
   return UGKS_OK;
 }
 
@@ -648,7 +654,7 @@ int ugks_mlp_forward(ugks_mlp* n, const float* x, int64_t rows, float* y, int32_
     n->allocations.pop_back();
   } catch (const HipFail& e) {
     return mlp_err(n, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(mlp_err, n)
   return UGKS_OK;
 }
 
@@ -668,7 +674,7 @@ int ugks_mlp_loss_grad(ugks_mlp* n, const float* x, const float* t, int64_t rows
     n->allocations.erase(std::find(n->allocations.begin(), n->allocations.end(), (void*)td));
   } catch (const HipFail& e) {
     return mlp_err(n, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(mlp_err, n)
   return UGKS_OK;
 }
 
@@ -697,7 +703,7 @@ int ugks_mlp_train(ugks_mlp* n, const float* x, const float* t, int64_t rows, in
     n->allocations.erase(std::find(n->allocations.begin(), n->allocations.end(), (void*)td));
   } catch (const HipFail& e) {
     return mlp_err(n, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(mlp_err, n)
   return UGKS_OK;
 }
 
@@ -757,7 +763,7 @@ int ugks_snapshot(ugks_ctx* c, float* feat, float* targ) {
     }
   } catch (const HipFail& e) {
     return ctx_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(ctx_err, c)
   return UGKS_OK;
 }
 
@@ -807,7 +813,7 @@ int ugks_warm_start(ugks_ctx* c, const ugks_mlp* net, const double* W, int64_t* 
     c->bytes -= (int64_t)(2 * nc * FS * sizeof(float) + sizeof(int32_t));
   } catch (const HipFail& e) {
     return ctx_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
-  }
+  } UGKS_CATCH_REST(ctx_err, c)
   return UGKS_OK;
 }
 
