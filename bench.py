@@ -233,6 +233,24 @@ def run_warm_start(args):
     print(json.dumps(out), flush=True)
 
 
+def run_size_sweep(args):
+    """Step throughput of the Sod tet cube over velocity sets and mesh sizes
+    (FP64 and FP32), to show where the GPU is saturated."""
+    import ugks_cases as uc
+    out = {"metric": "cell-velocity updates/s", "steps": args.steps, "warmup": args.warmup,
+           "rows": []}
+    for n, nv in ((20, 16), (20, 20), (20, 24), (20, 28), (20, 32), (10, 24), (30, 24)):
+        case = uc.sod3d_tets(n=n, nv=nv)
+        row = {"cells": case.mesh.n_cells, "nv": case.vel.nv}
+        for prec in (64, 32):
+            r = run_gpu(case, prec, args.steps, args.warmup)
+            row[f"fp{prec}"] = {"ms_per_step": r["ms_per_step"], "value": r["value"],
+                                "sweep_ms": r["sweep_ms"]}
+        out["rows"].append(row)
+        print(json.dumps(row), flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def run_precision_report(args):
     """FP32 form against FP64 on the 48k-tet cube with 28^3 velocities."""
     import numpy as np
@@ -325,6 +343,9 @@ def main():
                     help="instead of the throughput line, the FP32 form's field errors against "
                          "FP64 on the 48k-tet cube with 28^3 velocities, and the mass drift")
     ap.add_argument("--pr-steps", type=int, default=500)
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="instead of the throughput line, the step rate of the Sod tet cube "
+                         "over velocity sets 16^3..32^3 and meshes of 6,000..162,000 tets")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="instead of the step, copy this many GiB device-to-device with a plain "
                          "copy kernel (calibrates HBM byte counters)")
@@ -338,6 +359,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_per_launch": n * 8, "launches": 3}), flush=True)
+        return
+    if args.size_sweep:
+        run_size_sweep(args)
         return
     if args.batched_only:
         print(json.dumps(run_batched(args.steps, args.warmup)), flush=True)
