@@ -256,3 +256,29 @@ def test_first_order_parity(which, flags):
     else:
         case, steps = uc.sphere_mach5(n_ang=2, n_rad=3, nv=10, first=0.5), 6
     _compare_step(case, steps, flags=flags)
+
+
+@pytest.mark.parametrize("which,prec,flags", [("sod3d", 64, 0), ("sod3d", 32, 0), ("cavity2d", 64, 0),
+                                              ("channel2d", 64, 0), ("cavity2d", 64, STAGED)])
+def test_device_memory_accounting(which, prec, flags):
+    # The device memory of a context is the distributions plus O(N_c + N_f)
+    # records: h and h~ (and b, b~ in 2-D) with rows padded to 64 velocities,
+    # h and b with one zero row and one ghost row per far-field / outflow face
+    # on the fused path; the staged path adds the microscopic gradients
+    # (3 N_r N_c N_v) and face fluxes (N_r N_f N_v) in FP64.
+    from paper_2606_15720_amd.ugks import UGKS_FP32
+    case = {"sod3d": lambda: uc.sod3d_tets(n=4, nv=12), "cavity2d": lambda: uc.cavity2d(n=16, nv=20),
+            "channel2d": lambda: uc.channel2d(n=12, nv=16)}[which]()
+    s = Solver(case, precision=UGKS_FP32 if prec == 32 else 64, flags=flags)
+    info = s.info
+    s.close()
+    nc, nf, nvp, nr = info["n_cells"], info["n_faces"], info["nv_padded"], info["n_r"]
+    P = prec // 8
+    nff = int(np.sum(case.mesh.face_bc >= uc.BC_FARFIELD)) if info["fused"] else 0
+    f_bytes = nr * ((nc + 1 + nff) + nc) * nvp * P
+    if not info["fused"]:
+        f_bytes += nr * (3 * nc + nf) * nvp * 8
+    extra = info["device_bytes"] - f_bytes
+    print(which, prec, "fused" if info["fused"] else "staged", "f bytes", f_bytes, "other", extra,
+          "per cell+face", extra / (nc + nf), flush=True)
+    assert 0 <= extra <= 8192 * (nc + nf) + 256 * nvp + (4 << 20)
