@@ -1122,6 +1122,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas*
                 const ugks_bc* bcs, int32_t n_bc, const double* W0, const ugks_options* opt,
                 ugks_ctx** out) {
   if (!out) return set_err(nullptr, UGKS_EINVAL, "out is NULL");
+  Range range("ugks_create");
   std::unique_ptr<ugks_ctx> c(new ugks_ctx());
   try {
     build(c.get(), mesh, vel, gas, bcs, n_bc, W0, opt);
@@ -1189,6 +1190,7 @@ void run_step(ugks_ctx* c) {
 int ugks_step(ugks_ctx* c, int32_t n_steps, double* residual_out) {
   if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
   if (n_steps < 0) return set_err(c, UGKS_EINVAL, "n_steps < 0");
+  Range range("ugks_step");
   try {
     for (int32_t s = 0; s < n_steps; ++s) run_step(c);
     int32_t flag = 0;
@@ -1437,6 +1439,7 @@ const char* ugks_last_error(const ugks_ctx* c) {
 int ugks_batch_create(const ugks_case* cases, int32_t n_cases, const ugks_options* opt,
                       ugks_batch** out) {
   if (!out) return batch_err(nullptr, UGKS_EINVAL, "out is NULL");
+  Range range("ugks_batch_create");
   std::unique_ptr<ugks_batch> b(new ugks_batch());
   try {
     batch_build(b.get(), cases, n_cases, opt);
@@ -1464,6 +1467,7 @@ int ugks_batch_create(const ugks_case* cases, int32_t n_cases, const ugks_option
 int ugks_batch_step(ugks_batch* b, int32_t n_steps, double* residual_out) {
   if (!b) return batch_err(nullptr, UGKS_EINVAL, "batch is NULL");
   if (n_steps < 0) return batch_err(b, UGKS_EINVAL, "n_steps < 0");
+  Range range("ugks_batch_step");
   const size_t n = b->cases.size();
   try {
     for (int32_t s = 0; s < n_steps; ++s) {

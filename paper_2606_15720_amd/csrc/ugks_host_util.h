@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <exception>
 #include <new>
@@ -23,6 +24,14 @@ struct HipFail {
     hipError_t _e = (call);                        \
     if (_e != hipSuccess) throw HipFail{_e, #call}; \
   } while (0)
+
+// A roctx range over one library call, shown by rocprofv3 --marker-trace.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 struct InvalidArg {
   std::string msg;

@@ -682,6 +682,7 @@ int ugks_mlp_train(ugks_mlp* n, const float* x, const float* t, int64_t rows, in
                    int32_t steps, float lr, int32_t on_device, double* loss_out) {
   if (!n || !x || !t || rows <= 0 || batch <= 0 || steps < 0 || !(lr > 0.0f))
     return mlp_err(n, UGKS_EINVAL, "bad argument");
+  Range range("ugks_mlp_train");
   try {
     float* xd = stage_rows(n, x, rows, on_device, &n->xdev, &n->xcap);
     int64_t tcap = 0;
@@ -770,6 +771,7 @@ int ugks_snapshot(ugks_ctx* c, float* feat, float* targ) {
 int ugks_warm_start(ugks_ctx* c, const ugks_mlp* net, const double* W, int64_t* n_fallback) {
   if (!c || !net) return ctx_err(c, UGKS_EINVAL, "null argument");
   const int D = c->D;
+  Range range("ugks_warm_start");
   try {
     StepBuffers& B = c->buf;
     hipStream_t s = c->stream;
