@@ -23,8 +23,13 @@
 // atomics and the result is deterministic.  The first stage (Eq. f_tilde) is
 // applied in the same pass.  All loads of an iteration (the cell's stencil at
 // u and -u, each neighbour's stencil at the incoming member) are issued
-// before any arithmetic so their latency overlaps.  Stage 2 (Eq. f_final)
-// and the heat flux of the new distribution are fused in a second kernel.
+// before any arithmetic so their latency overlaps.  In 2-D the b equation
+// (same transport and relaxation, its own equilibrium polynomials) runs as a
+// second pass over the block after h, except in the batched form, whose
+// short work items carry h and b in one pass.  Stage 2 (Eq. f_final) and
+// the heat flux of the new distribution are fused in a second kernel.
+#include <type_traits>
+
 #include "ugks_device.h"
 
 namespace ugks {
@@ -178,7 +183,7 @@ struct SweepLds {
 // Every read-only array is its own __restrict__ argument so that the
 // compiler can prove no store of the sweep clobbers it and serve the
 // wave-uniform reads from the scalar cache.
-template <int D, typename T, typename C>
+template <int D, typename T, typename C, bool SPLIT>
 __device__ __forceinline__ void sweep_item(
     const FusedMesh& fm, int64_t nvp, const SweepSched& sc, const int32_t* __restrict__ crec_i,
     const C* __restrict__ crec_d, const int32_t* __restrict__ vidx,
@@ -222,13 +227,17 @@ __device__ __forceinline__ void sweep_item(
     __syncthreads();
   }
   constexpr int NM = D + 2;
-  constexpr bool B2 = (D == 2);  // the b equation is carried in 2-D only
   const unsigned nv = (unsigned)fm.nv;
   const unsigned npairs = (nv + 1) / 2;
   const unsigned kbeg = (unsigned)(chunk * sc.chunk_pairs);
   const unsigned kend = (unsigned)min((int64_t)npairs, (chunk + 1) * sc.chunk_pairs);
-  const T* __restrict__ hi = h + ic * nvp;
-  const T* __restrict__ bi = B2 ? b + ic * nvp : nullptr;
+  // Row r of h (or b) starts r * rowb bytes in.  Row indices are 32-bit and
+  // non-negative, and a row is under 4 GiB, so the offset is one 32x32->64
+  // scalar multiply.
+  const uint32_t rowb = (uint32_t)nvp * (uint32_t)sizeof(T);
+  auto row_of = [rowb](const T* base, int32_t r) {
+    return srow((const char*)base + (uint64_t)(uint32_t)r * rowb);
+  };
   // per-lane moments sum_k w_k psi_k (net outflow of the cell at u_k): the
   // conservative update of the cell is W - sum (Eq. macro_update regrouped
   // by velocity: sum_j sigma S_j F_j / V = sum_k w_k psi_k sum_j sigma S_j H_jk / V)
@@ -236,224 +245,410 @@ __device__ __forceinline__ void sweep_item(
 #pragma unroll
   for (int x = 0; x < NM; ++x) mw[x] = 0.0;
 
-  // the packed axis indices of the next pair are loaded one iteration ahead
-  int pk_next = kbeg + threadIdx.x < kend ? vidx[kbeg + threadIdx.x] : 0;
-  for (unsigned kp = kbeg + threadIdx.x; kp < kend; kp += nthr) {
-    // The cell and face records are loop invariant but too large to keep in
-    // scalar registers for the whole loop: an opaque uniform zero added to
-    // their addresses makes them scalar re-loads (scalar cache) each
-    // iteration instead of hoisted, spilled registers.
-    int z;
-    __asm__ volatile("s_mov_b32 %0, 0" : "=s"(z));
-    crec_i_t* ci = ci0 + z;
-    crec_t<C>* cd = cd0 + z;
-    crec_t<C>* cc = cc0 + z;
-    const unsigned k0 = kp, k1 = nv - 1 - kp;
-    const int pk = pk_next;
-    pk_next = vidx[min(kp + nthr, kend - 1)];
-    int id[3], im[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      id[d] = (pk >> (8 * d)) & 255;
-      im[d] = na - 1 - id[d];
-    }
-    C vv[3] = {C(0), C(0), C(0)};
-#pragma unroll
-    for (int d = 0; d < D; ++d) vv[d] = L.ax[id[d]];
-    // orientation of u against every outward normal
-    C sp[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      C s = C(0);
-#pragma unroll
-      for (int d = 0; d < D; ++d) s += vv[d] * cd[CRD_F0 + CRD_FS * p + 0 + d];
-      sp[p] = s;
-    }
-    // ---- the cell's own stencil at u and -u (4 rows, padded) ----
-    const uint32_t o0 = k0 * (uint32_t)sizeof(T), o1 = k1 * (uint32_t)sizeof(T);
-    grow_t* rhi = srow(hi);
-    const C h0 = ldo<T, C>(rhi, o0), h1 = ldo<T, C>(rhi, o1);
-    C b0 = C(0), b1 = C(0);
-    if (B2) {
-      grow_t* rbi = srow(bi);
-      b0 = ldo<T, C>(rbi, o0);
-      b1 = ldo<T, C>(rbi, o1);
-    }
-    C os0[4], os1[4], ob0[4], ob1[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t cell = ci[2 + s];
-      grow_t* rh = srow(h + cell * nvp);
-      os0[s] = ldo<T, C>(rh, o0);
-      os1[s] = ldo<T, C>(rh, o1);
-      ob0[s] = ob1[s] = C(0);
+  // In 2-D, h and b run as two passes over the block (each pass's records
+  // and row addresses then fit the scalar registers, where h and b together
+  // spill them), except for the batched form: the items of its small cases
+  // run only a few iterations, whose dependent-load latency two passes would
+  // pay twice, so there one pass carries both.
+  if constexpr (D == 2 && !SPLIT) {
+    // (64-bit row arithmetic here: the 32-bit form costs this body scalar
+    // registers it does not have)
+    constexpr bool B2 = true;
+    const T* __restrict__ hi = h + ic * nvp;
+    const T* __restrict__ bi = b + ic * nvp;
+    // the packed axis indices of the next pair are loaded one iteration ahead
+    int pk_next = kbeg + threadIdx.x < kend ? vidx[kbeg + threadIdx.x] : 0;
+    for (unsigned kp = kbeg + threadIdx.x; kp < kend; kp += nthr) {
+      // The cell and face records are loop invariant but too large to keep in
+      // scalar registers for the whole loop: an opaque uniform zero added to
+      // their addresses makes them scalar re-loads (scalar cache) each
+      // iteration instead of hoisted, spilled registers.
+      int z;
+      __asm__ volatile("s_mov_b32 %0, 0" : "=s"(z));
+      crec_i_t* ci = ci0 + z;
+      crec_t<C>* cd = cd0 + z;
+      crec_t<C>* cc = cc0 + z;
+      const unsigned k0 = kp, k1 = nv - 1 - kp;
+      const int pk = pk_next;
+      pk_next = vidx[min(kp + nthr, kend - 1)];
+      int id[3], im[3];
+  #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        id[d] = (pk >> (8 * d)) & 255;
+        im[d] = na - 1 - id[d];
+      }
+      C vv[3] = {C(0), C(0), C(0)};
+  #pragma unroll
+      for (int d = 0; d < D; ++d) vv[d] = L.ax[id[d]];
+      // orientation of u against every outward normal
+      C sp[4];
+  #pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        C s = C(0);
+  #pragma unroll
+        for (int d = 0; d < D; ++d) s += vv[d] * cd[CRD_F0 + CRD_FS * p + 0 + d];
+        sp[p] = s;
+      }
+      // ---- the cell's own stencil at u and -u (4 rows, padded) ----
+      const uint32_t o0 = k0 * (uint32_t)sizeof(T), o1 = k1 * (uint32_t)sizeof(T);
+      grow_t* rhi = srow(hi);
+      const C h0 = ldo<T, C>(rhi, o0), h1 = ldo<T, C>(rhi, o1);
+      C b0 = C(0), b1 = C(0);
       if (B2) {
-        grow_t* rb = srow(b + cell * nvp);
-        ob0[s] = ldo<T, C>(rb, o0);
-        ob1[s] = ldo<T, C>(rb, o1);
+        grow_t* rbi = srow(bi);
+        b0 = ldo<T, C>(rbi, o0);
+        b1 = ldo<T, C>(rbi, o1);
       }
-    }
-    // ---- every neighbour's value and stencil at the incoming member ----
-    // Slot p of the own stencil is the row across face p, and slot 0 of
-    // neighbour p's stencil is this cell: both are already in registers.
-    C nh[4], nhs[4][4], nb[4], nbs[4][4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      crec_i_t* fi = ci + CRI_F0 + CRI_FS * p;
-      const bool in1 = sp[p] > C(0);  // the incoming member is -u
-      uint32_t oin = in1 ? o1 : o0;
-      __asm__("" : "+v"(oin));  // keep the select on the offset, not on 64-bit addresses
-      nh[p] = in1 ? os1[p] : os0[p];
-      nb[p] = B2 ? (in1 ? ob1[p] : ob0[p]) : C(0);
-      nhs[p][0] = in1 ? h1 : h0;
-      nbs[p][0] = B2 ? (in1 ? b1 : b0) : C(0);
-#pragma unroll
-      for (int r = 1; r < 4; ++r) {
-        const int64_t cell = fi[5 + r];
-        nhs[p][r] = ldo<T, C>(srow(h + cell * nvp), oin);
-        nbs[p][r] = B2 ? ldo<T, C>(srow(b + cell * nvp), oin) : C(0);
-      }
-    }
-    // ---- arithmetic ----
-    C g0[3] = {C(0), C(0), C(0)}, g1[3] = {C(0), C(0), C(0)}, gb0[3] = {C(0), C(0), C(0)}, gb1[3] = {C(0), C(0), C(0)};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const C d0 = os0[s] - h0, d1 = os1[s] - h1;
-      const C e0 = ob0[s] - b0, e1 = ob1[s] - b1;
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const C G = cd[d * 4 + s];
-        g0[d] += G * d0;
-        g1[d] += G * d1;
+      C os0[4], os1[4], ob0[4], ob1[4];
+  #pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t cell = ci[2 + s];
+        grow_t* rh = srow(h + cell * nvp);
+        os0[s] = ldo<T, C>(rh, o0);
+        os1[s] = ldo<T, C>(rh, o1);
+        ob0[s] = ob1[s] = C(0);
         if (B2) {
-          gb0[d] += G * e0;
-          gb1[d] += G * e1;
+          grow_t* rb = srow(b + cell * nvp);
+          ob0[s] = ldo<T, C>(rb, o0);
+          ob1[s] = ldo<T, C>(rb, o1);
         }
       }
-    }
-    C ug0 = C(0), ug1 = C(0), ub0 = C(0), ub1 = C(0);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      ug0 += vv[d] * g0[d];
-      ug1 -= vv[d] * g1[d];
-      if (B2) {
-        ub0 += vv[d] * gb0[d];
-        ub1 -= vv[d] * gb1[d];
+      // ---- every neighbour's value and stencil at the incoming member ----
+      // Slot p of the own stencil is the row across face p, and slot 0 of
+      // neighbour p's stencil is this cell: both are already in registers.
+      C nh[4], nhs[4][4], nb[4], nbs[4][4];
+  #pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        crec_i_t* fi = ci + CRI_F0 + CRI_FS * p;
+        const bool in1 = sp[p] > C(0);  // the incoming member is -u
+        uint32_t oin = in1 ? o1 : o0;
+        __asm__("" : "+v"(oin));  // keep the select on the offset, not on 64-bit addresses
+        nh[p] = in1 ? os1[p] : os0[p];
+        nb[p] = B2 ? (in1 ? ob1[p] : ob0[p]) : C(0);
+        nhs[p][0] = in1 ? h1 : h0;
+        nbs[p][0] = B2 ? (in1 ? b1 : b0) : C(0);
+  #pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          const int64_t cell = fi[5 + r];
+          nhs[p][r] = ldo<T, C>(srow(h + cell * nvp), oin);
+          nbs[p][r] = B2 ? ldo<T, C>(srow(b + cell * nvp), oin) : C(0);
+        }
       }
-    }
-    C v2 = C(0);
-#pragma unroll
-    for (int d = 0; d < D; ++d) v2 += vv[d] * vv[d];
-    C acc0 = C(0), acc1 = C(0), accb0 = C(0), accb1 = C(0);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      crec_t<C>* fd = cd + CRD_F0 + CRD_FS * p;
-      crec_t<C>* R = frc + (int64_t)ci[CRI_F0 + CRI_FS * p] * FREC;
-      const bool pos = sp[p] > C(0);
-      const C as = fabs(sp[p]);
-      const C G1 = R[FR_G], G2 = R[FR_G + 1];
-      // outgoing member: the cell's own reconstruction at the face
-      const C us = pos ? ug0 : ug1;
-      C hf = pos ? h0 : h1;
-#pragma unroll
-      for (int d = 0; d < D; ++d) hf += fd[4 + d] * (pos ? g0[d] : g1[d]);
-      // incoming member: the neighbour's reconstruction at the face (all
-      // zero rows on a wall)
-      const C sgn_in = pos ? -1.0 : 1.0;  // u_in = sgn_in * u
-      const C hj = nh[p], bj = nb[p];
-      C gj[3] = {C(0), C(0), C(0)}, gbj[3] = {C(0), C(0), C(0)};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const C dh = nhs[p][r] - hj, db = nbs[p][r] - bj;
-#pragma unroll
+      // ---- arithmetic ----
+      C g0[3] = {C(0), C(0), C(0)}, g1[3] = {C(0), C(0), C(0)}, gb0[3] = {C(0), C(0), C(0)}, gb1[3] = {C(0), C(0), C(0)};
+  #pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const C d0 = os0[s] - h0, d1 = os1[s] - h1;
+        const C e0 = ob0[s] - b0, e1 = ob1[s] - b1;
+  #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const C G = fd[10 + d * 4 + r];
-          gj[d] += G * dh;
-          if (B2) gbj[d] += G * db;
+          const C G = cd[d * 4 + s];
+          g0[d] += G * d0;
+          g1[d] += G * d1;
+          if (B2) {
+            gb0[d] += G * e0;
+            gb1[d] += G * e1;
+          }
         }
       }
-      C hfj = hj, ugj = C(0);
-#pragma unroll
+      C ug0 = C(0), ug1 = C(0), ub0 = C(0), ub1 = C(0);
+  #pragma unroll
       for (int d = 0; d < D; ++d) {
-        hfj += fd[7 + d] * gj[d];
-        ugj += vv[d] * gj[d];
+        ug0 += vv[d] * g0[d];
+        ug1 -= vv[d] * g1[d];
+        if (B2) {
+          ub0 += vv[d] * gb0[d];
+          ub1 -= vv[d] * gb1[d];
+        }
       }
-      ugj *= sgn_in;
-      // g0 (or the scaled wall Maxwellian) at u and -u from the axis tables,
-      // times the equilibrium polynomial (constant on a wall)
-      C e0 = L.tab[p][0][id[0]], e1 = L.tab[p][0][im[0]];
-#pragma unroll
+      C v2 = C(0);
+  #pragma unroll
+      for (int d = 0; d < D; ++d) v2 += vv[d] * vv[d];
+      C acc0 = C(0), acc1 = C(0), accb0 = C(0), accb1 = C(0);
+  #pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        crec_t<C>* fd = cd + CRD_F0 + CRD_FS * p;
+        crec_t<C>* R = frc + (int64_t)ci[CRI_F0 + CRI_FS * p] * FREC;
+        const bool pos = sp[p] > C(0);
+        const C as = fabs(sp[p]);
+        const C G1 = R[FR_G], G2 = R[FR_G + 1];
+        // outgoing member: the cell's own reconstruction at the face
+        const C us = pos ? ug0 : ug1;
+        C hf = pos ? h0 : h1;
+  #pragma unroll
+        for (int d = 0; d < D; ++d) hf += fd[4 + d] * (pos ? g0[d] : g1[d]);
+        // incoming member: the neighbour's reconstruction at the face (all
+        // zero rows on a wall)
+        const C sgn_in = pos ? -1.0 : 1.0;  // u_in = sgn_in * u
+        const C hj = nh[p], bj = nb[p];
+        C gj[3] = {C(0), C(0), C(0)}, gbj[3] = {C(0), C(0), C(0)};
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const C dh = nhs[p][r] - hj, db = nbs[p][r] - bj;
+  #pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const C G = fd[10 + d * 4 + r];
+            gj[d] += G * dh;
+            if (B2) gbj[d] += G * db;
+          }
+        }
+        C hfj = hj, ugj = C(0);
+  #pragma unroll
+        for (int d = 0; d < D; ++d) {
+          hfj += fd[7 + d] * gj[d];
+          ugj += vv[d] * gj[d];
+        }
+        ugj *= sgn_in;
+        // g0 (or the scaled wall Maxwellian) at u and -u from the axis tables,
+        // times the equilibrium polynomial (constant on a wall)
+        C e0 = L.tab[p][0][id[0]], e1 = L.tab[p][0][im[0]];
+  #pragma unroll
+        for (int d = 1; d < D; ++d) {
+          e0 *= L.tab[p][d][id[d]];
+          e1 *= L.tab[p][d][im[d]];
+        }
+        C E, O;
+        cubic_eo<D>(R + FR_PH, vv, v2, E, O);
+        const C q0 = e0 * (E + O), q1 = e1 * (E - O);
+        const C eqm = fd[22];  // 0 on a wall: no equilibrium term going out
+        const C eqo = eqm * (pos ? q0 : q1);
+        const C eqi = pos ? q1 : q0;
+        const C out = as * (G1 * hf + G2 * us + eqo);
+        const C in = -as * (G1 * hfj + G2 * ugj + eqi);
+        C outb = 0.0, inb = 0.0;
+        if (B2) {
+          C bfo = pos ? b0 : b1;
+          const C ubs = pos ? ub0 : ub1;
+  #pragma unroll
+          for (int d = 0; d < D; ++d) bfo += fd[4 + d] * (pos ? gb0[d] : gb1[d]);
+          C bfj = bj, ubj = C(0);
+  #pragma unroll
+          for (int d = 0; d < D; ++d) {
+            bfj += fd[7 + d] * gbj[d];
+            ubj += vv[d] * gbj[d];
+          }
+          ubj *= sgn_in;
+          C Eb, Ob;
+          cubic_eo<D>(R + FR_PB, vv, v2, Eb, Ob);
+          const C r0 = e0 * (Eb + Ob), r1 = e1 * (Eb - Ob);
+          outb = as * (G1 * bfo + G2 * ubs + eqm * (pos ? r0 : r1));
+          inb = -as * (G1 * bfj + G2 * ubj + (pos ? r1 : r0));
+        }
+        // fluxes at u and at -u along this cell's outward normal, times S/V
+        const C sv = fd[3];
+        acc0 += sv * (pos ? out : in);
+        acc1 += sv * (pos ? in : out);
+        if (B2) {
+          accb0 += sv * (pos ? outb : inb);
+          accb1 += sv * (pos ? inb : outb);
+        }
+      }
+      // moments of the net outflow (the zero velocity of an odd grid once)
+      {
+        const double a0 = w[k0] * (double)acc0, a1 = (k1 != k0) ? w[k1] * (double)acc1 : 0.0;
+        mw[0] += a0 + a1;
+  #pragma unroll
+        for (int d = 0; d < D; ++d) mw[1 + d] += (double)vv[d] * (a0 - a1);
+        double e = 0.5 * (double)v2 * (a0 + a1);
+        if (B2) e += 0.5 * (w[k0] * (double)accb0 + ((k1 != k0) ? w[k1] * (double)accb1 : 0.0));
+        mw[D + 1] += e;
+      }
+      // first stage with the cell's BGK-Shakhov equilibrium at u and -u
+      C c0 = L.ctab[0][id[0]], c1 = L.ctab[0][im[0]];
+  #pragma unroll
       for (int d = 1; d < D; ++d) {
-        e0 *= L.tab[p][d][id[d]];
-        e1 *= L.tab[p][d][im[d]];
+        c0 *= L.ctab[d][id[d]];
+        c1 *= L.ctab[d][im[d]];
       }
       C E, O;
-      cubic_eo<D>(R + FR_PH, vv, v2, E, O);
-      const C q0 = e0 * (E + O), q1 = e1 * (E - O);
-      const C eqm = fd[22];  // 0 on a wall: no equilibrium term going out
-      const C eqo = eqm * (pos ? q0 : q1);
-      const C eqi = pos ? q1 : q0;
-      const C out = as * (G1 * hf + G2 * us + eqo);
-      const C in = -as * (G1 * hfj + G2 * ugj + eqi);
-      C outb = 0.0, inb = 0.0;
+      cubic_eo<D>(cc + CS_SH, vv, v2, E, O);
+      const C ccoll = cc[CS_CC];
+      T* __restrict__ hto = ht + ic * nvp;
+      st(hto, k0, h0 - acc0 + ccoll * (c0 * (C(1) + E + O) - h0));
+      if (k1 != k0) st(hto, k1, h1 - acc1 + ccoll * (c1 * (C(1) + E - O) - h1));
       if (B2) {
-        C bfo = pos ? b0 : b1;
-        const C ubs = pos ? ub0 : ub1;
+        C Eb, Ob;
+        cubic_eo<D>(cc + CS_SB, vv, v2, Eb, Ob);
+        const C kc = cc[CS_KAP];
+        T* __restrict__ bto = bt + ic * nvp;
+        st(bto, k0, b0 - accb0 + ccoll * (kc * c0 * (C(1) + Eb + Ob) - b0));
+        if (k1 != k0) st(bto, k1, b1 - accb1 + ccoll * (kc * c1 * (C(1) + Eb - Ob) - b1));
+      }
+    }
+  } else {
+    // One pass over the block's mirror pairs for one reduced distribution:
+    // X = 0 is h (mass, momentum and its share of the energy), X = 1 is b
+    // (2-D only: the rest of the energy).  The b equation has the same
+    // transport and relaxation as h with its own equilibrium polynomials.
+    auto pass = [&](auto xtag) {
+      constexpr int X = decltype(xtag)::value;
+      const T* __restrict__ f = X ? b : h;
+      T* __restrict__ fto = (X ? bt : ht) + ic * nvp;
+      grow_t* rfi = srow(f + ic * nvp);
+      // the packed axis indices of the next pair are loaded one iteration ahead
+      int pk_next = kbeg + threadIdx.x < kend ? vidx[kbeg + threadIdx.x] : 0;
+      for (unsigned kp = kbeg + threadIdx.x; kp < kend; kp += nthr) {
+        // The cell and face records are loop invariant but too large to keep
+        // in scalar registers for the whole loop: an opaque uniform zero
+        // added to their addresses makes them scalar re-loads (scalar cache)
+        // each iteration instead of hoisted, spilled registers.
+        int z;
+        __asm__ volatile("s_mov_b32 %0, 0" : "=s"(z));
+        crec_i_t* ci = ci0 + z;
+        crec_t<C>* cd = cd0 + z;
+        crec_t<C>* cc = cc0 + z;
+        const unsigned k0 = kp, k1 = nv - 1 - kp;
+        const int pk = pk_next;
+        pk_next = vidx[min(kp + nthr, kend - 1)];
+        int id[3], im[3];
 #pragma unroll
-        for (int d = 0; d < D; ++d) bfo += fd[4 + d] * (pos ? gb0[d] : gb1[d]);
-        C bfj = bj, ubj = C(0);
+        for (int d = 0; d < 3; ++d) {
+          id[d] = (pk >> (8 * d)) & 255;
+          im[d] = na - 1 - id[d];
+        }
+        C vv[3] = {C(0), C(0), C(0)};
+#pragma unroll
+        for (int d = 0; d < D; ++d) vv[d] = L.ax[id[d]];
+        // orientation of u against every outward normal
+        C sp[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          C s = C(0);
+#pragma unroll
+          for (int d = 0; d < D; ++d) s += vv[d] * cd[CRD_F0 + CRD_FS * p + 0 + d];
+          sp[p] = s;
+        }
+        // ---- the cell's own stencil at u and -u (4 rows, padded) ----
+        const uint32_t o0 = k0 * (uint32_t)sizeof(T), o1 = k1 * (uint32_t)sizeof(T);
+        const C f0 = ldo<T, C>(rfi, o0), f1 = ldo<T, C>(rfi, o1);
+        C os0[4], os1[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          grow_t* rs = row_of(f, ci[2 + s]);
+          os0[s] = ldo<T, C>(rs, o0);
+          os1[s] = ldo<T, C>(rs, o1);
+        }
+        // ---- every neighbour's value and stencil at the incoming member ----
+        // Slot p of the own stencil is the row across face p, and slot 0 of
+        // neighbour p's stencil is this cell: both are already in registers.
+        C nh[4], nhs[4][4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          crec_i_t* fi = ci + CRI_F0 + CRI_FS * p;
+          const bool in1 = sp[p] > C(0);  // the incoming member is -u
+          uint32_t oin = in1 ? o1 : o0;
+          __asm__("" : "+v"(oin));  // keep the select on the offset, not on 64-bit addresses
+          nh[p] = in1 ? os1[p] : os0[p];
+          nhs[p][0] = in1 ? f1 : f0;
+#pragma unroll
+          for (int r = 1; r < 4; ++r) nhs[p][r] = ldo<T, C>(row_of(f, fi[5 + r]), oin);
+        }
+        // ---- arithmetic ----
+        C g0[3] = {C(0), C(0), C(0)}, g1[3] = {C(0), C(0), C(0)};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const C d0 = os0[s] - f0, d1 = os1[s] - f1;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const C G = cd[d * 4 + s];
+            g0[d] += G * d0;
+            g1[d] += G * d1;
+          }
+        }
+        C ug0 = C(0), ug1 = C(0);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          bfj += fd[7 + d] * gbj[d];
-          ubj += vv[d] * gbj[d];
+          ug0 += vv[d] * g0[d];
+          ug1 -= vv[d] * g1[d];
         }
-        ubj *= sgn_in;
-        C Eb, Ob;
-        cubic_eo<D>(R + FR_PB, vv, v2, Eb, Ob);
-        const C r0 = e0 * (Eb + Ob), r1 = e1 * (Eb - Ob);
-        outb = as * (G1 * bfo + G2 * ubs + eqm * (pos ? r0 : r1));
-        inb = -as * (G1 * bfj + G2 * ubj + (pos ? r1 : r0));
-      }
-      // fluxes at u and at -u along this cell's outward normal, times S/V
-      const C sv = fd[3];
-      acc0 += sv * (pos ? out : in);
-      acc1 += sv * (pos ? in : out);
-      if (B2) {
-        accb0 += sv * (pos ? outb : inb);
-        accb1 += sv * (pos ? inb : outb);
-      }
-    }
-    // moments of the net outflow (the zero velocity of an odd grid once)
-    {
-      const double a0 = w[k0] * (double)acc0, a1 = (k1 != k0) ? w[k1] * (double)acc1 : 0.0;
-      mw[0] += a0 + a1;
+        C v2 = C(0);
 #pragma unroll
-      for (int d = 0; d < D; ++d) mw[1 + d] += (double)vv[d] * (a0 - a1);
-      double e = 0.5 * (double)v2 * (a0 + a1);
-      if (B2) e += 0.5 * (w[k0] * (double)accb0 + ((k1 != k0) ? w[k1] * (double)accb1 : 0.0));
-      mw[D + 1] += e;
-    }
-    // first stage with the cell's BGK-Shakhov equilibrium at u and -u
-    C c0 = L.ctab[0][id[0]], c1 = L.ctab[0][im[0]];
+        for (int d = 0; d < D; ++d) v2 += vv[d] * vv[d];
+        C acc0 = C(0), acc1 = C(0);
 #pragma unroll
-    for (int d = 1; d < D; ++d) {
-      c0 *= L.ctab[d][id[d]];
-      c1 *= L.ctab[d][im[d]];
-    }
-    C E, O;
-    cubic_eo<D>(cc + CS_SH, vv, v2, E, O);
-    const C ccoll = cc[CS_CC];
-    T* __restrict__ hto = ht + ic * nvp;
-    st(hto, k0, h0 - acc0 + ccoll * (c0 * (C(1) + E + O) - h0));
-    if (k1 != k0) st(hto, k1, h1 - acc1 + ccoll * (c1 * (C(1) + E - O) - h1));
-    if (B2) {
-      C Eb, Ob;
-      cubic_eo<D>(cc + CS_SB, vv, v2, Eb, Ob);
-      const C kc = cc[CS_KAP];
-      T* __restrict__ bto = bt + ic * nvp;
-      st(bto, k0, b0 - accb0 + ccoll * (kc * c0 * (C(1) + Eb + Ob) - b0));
-      if (k1 != k0) st(bto, k1, b1 - accb1 + ccoll * (kc * c1 * (C(1) + Eb - Ob) - b1));
-    }
+        for (int p = 0; p < 4; ++p) {
+          crec_t<C>* fd = cd + CRD_F0 + CRD_FS * p;
+          crec_t<C>* R = frc + (uint64_t)(uint32_t)ci[CRI_F0 + CRI_FS * p] * FREC;
+          const bool pos = sp[p] > C(0);
+          const C as = fabs(sp[p]);
+          const C G1 = R[FR_G], G2 = R[FR_G + 1];
+          // outgoing member: the cell's own reconstruction at the face
+          const C us = pos ? ug0 : ug1;
+          C ff = pos ? f0 : f1;
+#pragma unroll
+          for (int d = 0; d < D; ++d) ff += fd[4 + d] * (pos ? g0[d] : g1[d]);
+          // incoming member: the neighbour's reconstruction at the face (all
+          // zero rows on a wall)
+          const C sgn_in = pos ? -1.0 : 1.0;  // u_in = sgn_in * u
+          const C fj = nh[p];
+          C gj[3] = {C(0), C(0), C(0)};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const C df = nhs[p][r] - fj;
+#pragma unroll
+            for (int d = 0; d < D; ++d) gj[d] += fd[10 + d * 4 + r] * df;
+          }
+          C ffj = fj, ugj = C(0);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            ffj += fd[7 + d] * gj[d];
+            ugj += vv[d] * gj[d];
+          }
+          ugj *= sgn_in;
+          // g0 (or the scaled wall Maxwellian) at u and -u from the axis
+          // tables, times the equilibrium polynomial (constant on a wall)
+          C e0 = L.tab[p][0][id[0]], e1 = L.tab[p][0][im[0]];
+#pragma unroll
+          for (int d = 1; d < D; ++d) {
+            e0 *= L.tab[p][d][id[d]];
+            e1 *= L.tab[p][d][im[d]];
+          }
+          C E, O;
+          cubic_eo<D>(R + (X ? FR_PB : FR_PH), vv, v2, E, O);
+          const C q0 = e0 * (E + O), q1 = e1 * (E - O);
+          const C eqm = fd[22];  // 0 on a wall: no equilibrium term going out
+          const C eqo = eqm * (pos ? q0 : q1);
+          const C eqi = pos ? q1 : q0;
+          const C out = as * (G1 * ff + G2 * us + eqo);
+          const C in = -as * (G1 * ffj + G2 * ugj + eqi);
+          // fluxes at u and at -u along this cell's outward normal, times S/V
+          const C sv = fd[3];
+          acc0 += sv * (pos ? out : in);
+          acc1 += sv * (pos ? in : out);
+        }
+        // moments of the net outflow (the zero velocity of an odd grid once)
+        {
+          const double a0 = w[k0] * (double)acc0, a1 = (k1 != k0) ? w[k1] * (double)acc1 : 0.0;
+          if constexpr (X == 0) {
+            mw[0] += a0 + a1;
+#pragma unroll
+            for (int d = 0; d < D; ++d) mw[1 + d] += (double)vv[d] * (a0 - a1);
+            mw[D + 1] += 0.5 * (double)v2 * (a0 + a1);
+          } else {
+            mw[D + 1] += 0.5 * (a0 + a1);
+          }
+        }
+        // first stage with the cell's BGK-Shakhov equilibrium at u and -u
+        C c0 = L.ctab[0][id[0]], c1 = L.ctab[0][im[0]];
+#pragma unroll
+        for (int d = 1; d < D; ++d) {
+          c0 *= L.ctab[d][id[d]];
+          c1 *= L.ctab[d][im[d]];
+        }
+        if constexpr (X == 1) {  // the b equilibrium carries the internal-energy factor
+          const C kc = cc[CS_KAP];
+          c0 = kc * c0;
+          c1 = kc * c1;
+        }
+        C E, O;
+        cubic_eo<D>(cc + (X ? CS_SB : CS_SH), vv, v2, E, O);
+        const C ccoll = cc[CS_CC];
+        st(fto, k0, f0 - acc0 + ccoll * (c0 * (C(1) + E + O) - f0));
+        if (k1 != k0) st(fto, k1, f1 - acc1 + ccoll * (c1 * (C(1) + E - O) - f1));
+      }
+    };
+    pass(std::integral_constant<int, 0>{});
+    if constexpr (D == 2) pass(std::integral_constant<int, 1>{});
   }
   block_sum<NM>(mw, L.red);
   if (threadIdx.x == 0)
@@ -466,7 +661,7 @@ __device__ __forceinline__ void sweep_item(
 // body fits in half the registers; its bound asks for the occupancy that
 // hides the gathers' latency (measured: 7 waves per SIMD, no spills).
 template <int D, typename T>
-__global__ __launch_bounds__(SWT, (D == 3 ? (sizeof(T) == 4 ? 6 : 4) : (sizeof(T) == 4 ? 4 : 2))) void k_sweep(
+__global__ __launch_bounds__(SWT, (sizeof(T) == 4 ? 6 : 4)) void k_sweep(
     FusedMesh fm, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
     const T* __restrict__ crec_d, const int32_t* __restrict__ vidx,
     const double* __restrict__ w, const T* __restrict__ cs, const T* __restrict__ frec,
@@ -486,16 +681,16 @@ __global__ __launch_bounds__(SWT, (D == 3 ? (sizeof(T) == 4 ? 6 : 4) : (sizeof(T
   const int64_t chunk = rem / sc.tile;
   const int64_t ic = tile * sc.tile + rem % sc.tile;
   if (ic >= fm.nc) return;
-  sweep_item<D, T, T>(fm, nvp, sc, crec_i, crec_d, vidx, w, cs, frec, tabs, h, b, ht, bt, dWp,
+  sweep_item<D, T, T, true>(fm, nvp, sc, crec_i, crec_d, vidx, w, cs, frec, tabs, h, b, ht, bt, dWp,
                       flag, ic, chunk, L);
 }
 
 // The fused sweep over a batch of cases: a persistent grid walks a list of
 // (case, cell, velocity block) work items; item w runs on block w mod the
 // grid size, and the host orders the list so that the blocks of one XCD
-// (block index mod 8) take whole tiles of one case.  In 2-D (h and b) the
-// bound trades three spilled registers for a third wave per SIMD (measured
-// faster on the uneven 2-D batch).
+// (block index mod 8) take whole tiles of one case.  In 2-D, where one pass
+// carries h and b, the bound trades a few spilled scalar registers for a
+// third wave per SIMD.
 template <int D, typename T>
 __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 3)) void k_sweep_b(BatchDev bd) {
   __shared__ SweepLds<double> L;
@@ -535,7 +730,7 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 3)) void k_sweep_b(BatchDev bd) 
     double* dW = cases[c].B.dW;
     const int32_t* flag = cases[c].B.flag;
     __syncthreads();  // the previous item's readers of L are done
-    sweep_item<D, T, double>(fm, nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, w, cs, frec, tabs, h, b, ht, bt,
+    sweep_item<D, T, double, false>(fm, nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, w, cs, frec, tabs, h, b, ht, bt,
                      dW, flag, ic, chunk, L);
   }
 }
