@@ -488,6 +488,10 @@ __device__ __forceinline__ void sweep_item(
       // the packed axis indices of the next pair are loaded one iteration ahead
       int pk_next = kbeg + threadIdx.x < kend ? vidx[kbeg + threadIdx.x] : 0;
       for (unsigned kp = kbeg + threadIdx.x; kp < kend; kp += nthr) {
+        // FP32: the wave takes a higher issue priority while it issues the
+        // iteration's gathers, so that they start early (measured 2-6 %
+        // faster in FP32, slower in FP64)
+        if constexpr (sizeof(C) == 4) __builtin_amdgcn_s_setprio(1);
         // The cell and face records are loop invariant but too large to keep
         // in scalar registers for the whole loop: an opaque uniform zero
         // added to their addresses makes them scalar re-loads (scalar cache)
@@ -543,6 +547,7 @@ __device__ __forceinline__ void sweep_item(
 #pragma unroll
           for (int r = 1; r < 4; ++r) nhs[p][r] = ldo<T, C>(row_of(f, fi[5 + r]), oin);
         }
+        if constexpr (sizeof(C) == 4) __builtin_amdgcn_s_setprio(0);
         // ---- arithmetic ----
         C g0[3] = {C(0), C(0), C(0)}, g1[3] = {C(0), C(0), C(0)};
 #pragma unroll
