@@ -1,12 +1,18 @@
-"""Host AddressSanitizer run over the library's argument checks and error paths.
+"""Host AddressSanitizer runs: the library's error paths and the oracle.
 
-Every library source is compiled with AddressSanitizer on its host side only
-(the device code is built as usual), linked into a separate library, and
-driven by ``tests/asan/abi_errors.cpp``: invalid meshes, velocity sets, gases,
-boundary tables, batches and networks, NULL handles, a missing tuning file,
-and one valid case that fails at its first device call here (no GPU).  Each
-call must return its documented status with a message, and the sanitizer must
-report no invalid access and no leak.  No GPU is touched.
+* Every library source is compiled with AddressSanitizer on its host side
+  only (the device code is built as usual), linked into a separate library,
+  and driven by ``tests/asan/abi_errors.cpp``: invalid meshes, velocity sets,
+  gases, boundary tables, batches and networks, NULL handles, a missing
+  tuning file, and one valid case that fails at its first device call here
+  (no GPU).  Each call must return its documented status with a message.
+* The oracle is compiled with AddressSanitizer and run by
+  ``tests/asan/oracle_cases.cpp`` on small cases covering walls, periodic
+  faces, far-field faces, 2-D and 3-D, both reconstruction orders; its final
+  state must equal the regular build's.
+
+In both the sanitizer must report no invalid access and no leak.  No GPU is
+touched.
 """
 
 import os
@@ -55,3 +61,69 @@ def test_error_paths_are_clean_under_asan(tmp_path):
     assert "LeakSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "0 unexpected" in r.stdout
+
+
+def _write_case(path, case, steps, order):
+    """The case file read by ``tests/asan/oracle_cases.cpp``, with the final
+    W of the regular oracle build after ``steps`` steps."""
+    import numpy as np
+    from oracle import Oracle
+
+    m = case.mesh.contiguous()
+    v, g = case.vel, case.gas
+    o = Oracle(case, order=order)
+    o.step(steps)
+    W = o.state(with_h=False)[0]
+    f8 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    arrays = [
+        f8(m.cell_volume), f8(m.cell_centroid), np.ascontiguousarray(m.face_cells, dtype=np.int64),
+        f8(m.face_area), f8(m.face_normal), f8(m.face_centroid),
+        f8(m.face_shift) if m.face_shift is not None else np.zeros(0),
+        np.ascontiguousarray(m.face_bc, dtype=np.int32), np.ascontiguousarray(m.face_bc_id, dtype=np.int32),
+        f8(v.u), f8(v.w),
+        np.array([b.kind for b in case.bcs], dtype=np.int32), f8([b.rho for b in case.bcs]),
+        f8([list(b.U) + [0.0] * (3 - len(b.U)) for b in case.bcs]), f8([b.T for b in case.bcs]),
+        f8(case.W0), f8(W),
+    ]
+    hi = np.array([m.dim, m.n_cells, m.n_faces, v.nv, len(case.bcs), g.K, steps, order], dtype=np.int64)
+    hd = np.array([g.Pr, g.R, g.T_ref, g.mu_ref, g.omega, g.cfl, g.dt, 0.0], dtype=np.float64)
+    with open(path, "wb") as f:
+        f.write(hi.tobytes())
+        f.write(hd.tobytes())
+        for a in arrays:
+            b = a.tobytes()
+            f.write(np.int64(len(b)).tobytes())
+            f.write(b)
+
+
+def test_oracle_is_clean_under_asan(tmp_path):
+    import ugks_cases as uc
+
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not installed")
+    exe = str(tmp_path / "oracle_cases")
+    subprocess.check_call([gxx, "-O1", "-g", "-std=c++17", "-fopenmp", "-ffp-contract=off",
+                           "-fsanitize=address", "-fno-omit-frame-pointer",
+                           os.path.join(ROOT, "oracle", "ugks_oracle.cpp"),
+                           os.path.join(HERE, "asan", "oracle_cases.cpp"), "-o", exe])
+    cases = [
+        ("cavity2d", uc.cavity2d(n=5, nv=6), 4, 2),      # walls, moving lid
+        ("couette2d", uc.couette2d(n=5, nv=6), 4, 2),    # periodic faces
+        ("channel2d", uc.channel2d(n=4, nv=6), 4, 2),    # far-field faces
+        ("sod3d", uc.sod3d_tets(n=2, nv=6), 3, 2),       # tets, 3-D
+        ("cavity2d_o1", uc.cavity2d(n=5, nv=6), 3, 1),   # first-order reconstruction
+    ]
+    files = []
+    for name, case, steps, order in cases:
+        path = str(tmp_path / f"{name}.bin")
+        _write_case(path, case, steps, order)
+        files.append(path)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=23",
+               OMP_NUM_THREADS="2")
+    r = subprocess.run([exe, *files], env=env, capture_output=True, text=True, timeout=600)
+    print(r.stdout)
+    assert "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert "LeakSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert f"{len(cases)} cases, 0 failed" in r.stdout
