@@ -1,18 +1,19 @@
-"""Host AddressSanitizer runs: the library's error paths and the oracle.
+"""Host AddressSanitizer and UndefinedBehaviorSanitizer runs: the library's
+error paths and the oracle.
 
-* Every library source is compiled with AddressSanitizer on its host side
+* Every library source is compiled with both sanitizers on its host side
   only (the device code is built as usual), linked into a separate library,
   and driven by ``tests/asan/abi_errors.cpp``: invalid meshes, velocity sets,
   gases, boundary tables, batches and networks, NULL handles, a missing
   tuning file, and one valid case that fails at its first device call here
   (no GPU).  Each call must return its documented status with a message.
-* The oracle is compiled with AddressSanitizer and run by
+* The oracle is compiled with both sanitizers and run by
   ``tests/asan/oracle_cases.cpp`` on small cases covering walls, periodic
   faces, far-field faces, 2-D and 3-D, both reconstruction orders; its final
   state must equal the regular build's.
 
-In both the sanitizer must report no invalid access and no leak.  No GPU is
-touched.
+In both the sanitizers must report no invalid access, no leak and no
+undefined behaviour.  No GPU is touched.
 """
 
 import os
@@ -33,7 +34,8 @@ CLANG = "/opt/rocm/llvm/bin/clang++"
 def test_error_paths_are_clean_under_asan(tmp_path):
     flags = [f for f in B.FLAGS if f not in ("-O3",)] + [
         "-O1", "-g", f"-I{os.path.join(ROOT, 'include')}",
-        "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+        "-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=undefined",
+        "-Xarch_host", "-fno-omit-frame-pointer"]
     procs, objs = [], []
     for src in B.SOURCES:
         obj = str(tmp_path / src.replace(".hip", ".o"))
@@ -45,10 +47,10 @@ def test_error_paths_are_clean_under_asan(tmp_path):
         assert p.returncode == 0, out.decode()[-2000:]
     lib = str(tmp_path / "libugks_asan.so")
     subprocess.check_call([B.HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC",
-                           "-Xarch_host", "-fsanitize=address", *objs, "-o", lib,
+                           "-Xarch_host", "-fsanitize=address,undefined", *objs, "-o", lib,
                            "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     exe = str(tmp_path / "abi_errors")
-    subprocess.check_call([CLANG, "-std=c++17", "-g", "-fsanitize=address",
+    subprocess.check_call([CLANG, "-std=c++17", "-g", "-fsanitize=address,undefined",
                            f"-I{os.path.join(ROOT, 'include')}", "-I/opt/rocm/include",
                            "-D__HIP_PLATFORM_AMD__", os.path.join(HERE, "asan", "abi_errors.cpp"),
                            f"-L{tmp_path}", "-lugks_asan", f"-Wl,-rpath,{tmp_path}",
@@ -59,6 +61,7 @@ def test_error_paths_are_clean_under_asan(tmp_path):
     print(r.stdout)
     assert "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
     assert "LeakSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert "runtime error" not in r.stderr, r.stderr[-4000:]  # UndefinedBehaviorSanitizer
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "0 unexpected" in r.stdout
 
@@ -104,8 +107,8 @@ def test_oracle_is_clean_under_asan(tmp_path):
         pytest.skip("g++ not installed")
     exe = str(tmp_path / "oracle_cases")
     subprocess.check_call([gxx, "-O1", "-g", "-std=c++17", "-fopenmp", "-ffp-contract=off",
-                           "-fsanitize=address", "-fno-omit-frame-pointer",
-                           os.path.join(ROOT, "oracle", "ugks_oracle.cpp"),
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-fno-omit-frame-pointer", os.path.join(ROOT, "oracle", "ugks_oracle.cpp"),
                            os.path.join(HERE, "asan", "oracle_cases.cpp"), "-o", exe])
     cases = [
         ("cavity2d", uc.cavity2d(n=5, nv=6), 4, 2),      # walls, moving lid
@@ -125,5 +128,6 @@ def test_oracle_is_clean_under_asan(tmp_path):
     print(r.stdout)
     assert "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
     assert "LeakSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert "runtime error" not in r.stderr, r.stderr[-4000:]  # UndefinedBehaviorSanitizer
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert f"{len(cases)} cases, 0 failed" in r.stdout
