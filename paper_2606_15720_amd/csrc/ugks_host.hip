@@ -58,8 +58,10 @@ bool chol_inverse(int D, const double* N, double* Ninv) {
 }
 
 
-void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas* gas,
-           const ugks_bc* bcs, int32_t n_bc, const double* W0, const ugks_options* opt) {
+// The checks of a case's arguments that need no mesh traversal: pointers,
+// sizes, dimension and gas constants.
+void check_case_args(const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas* gas,
+                     const double* W0) {
   fail_if(!mesh || !vel || !gas || !W0, "null argument");
   const int D = mesh->dim;
   fail_if(D != 2 && D != 3, "mesh.dim must be 2 or 3");
@@ -73,6 +75,13 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
           "null mesh or velocity array");
   fail_if(!(gas->Pr > 0.0) || !(gas->R > 0.0) || !(gas->T_ref > 0.0) || !(gas->mu_ref > 0.0),
           "gas constants must be positive");
+}
+
+void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas* gas,
+           const ugks_bc* bcs, int32_t n_bc, const double* W0, const ugks_options* opt) {
+  check_case_args(mesh, vel, gas, W0);
+  const int D = mesh->dim;
+  const int64_t nc = mesh->n_cells, nf = mesh->n_faces, nv = vel->nv;
   int prec = opt && opt->precision ? opt->precision : UGKS_FP64;
   fail_if(prec != UGKS_FP64 && prec != UGKS_FP32, "precision must be 64 or 32");
   int Bv = opt && opt->block_v ? opt->block_v : 0;
@@ -985,6 +994,19 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
   const int fixed_bv = opt ? opt->block_v : 0, fixed_tile = opt ? opt->tile_cells : 0;
   fail_if(fixed_bv < 0 || fixed_bv % WAVE != 0, "block_v must be 0 or a positive multiple of 64");
   fail_if(fixed_tile < 0, "tile_cells must be >= 0");
+  // every case's arguments, and one dimension for all, before any device work
+  for (int32_t i = 0; i < n; ++i) {
+    const ugks_case& k = cases[i];
+    try {
+      check_case_args(k.mesh, k.vel, k.gas, k.W0);
+    } catch (InvalidArg& e) {
+      throw InvalidArg{"case " + std::to_string(i) + ": " + e.msg};
+    } catch (std::pair<int, std::string>& e) {
+      throw std::pair<int, std::string>(e.first, "case " + std::to_string(i) + ": " + e.second);
+    }
+    fail_if(k.mesh->dim != cases[0].mesh->dim,
+            "case " + std::to_string(i) + ": every case needs the same dimension");
+  }
   b->prec = prec;
   b->flags = opt ? opt->flags : 0;
   b->use_graph = !(b->flags & 8);

@@ -63,8 +63,7 @@ int main() {
   ugks_batch* b = nullptr;
   expect("batch of none", ugks_batch_create(nullptr, 0, nullptr, &b), UGKS_EINVAL,
          ugks_batch_last_error(nullptr));
-  // the batch checks its options before any device call; its cases are
-  // checked after the shared device buffers exist
+  // the batch checks its options before any device call
   ugks_case cs[2] = {{&m, &v, &g, &bc, 1, W0}, {&m, &v, &g, &bc, 1, W0}};
   ugks_options o{};
   o.precision = 7;
@@ -74,6 +73,23 @@ int main() {
   o.block_v = 100;
   expect("batch, bad block_v", ugks_batch_create(cs, 2, &o, &b), UGKS_EINVAL,
          ugks_batch_last_error(nullptr));
+  // each case's arguments are checked before any device call too
+  cs[1].mesh = nullptr;
+  expect("batch, case without mesh", ugks_batch_create(cs, 2, nullptr, &b), UGKS_EINVAL,
+         ugks_batch_last_error(nullptr));
+  cs[1].mesh = &m;
+  ugks_gas g2 = g;
+  g2.K = 2;
+  cs[1].gas = &g2;
+  expect("batch, case with K > 0", ugks_batch_create(cs, 2, nullptr, &b), UGKS_EUNSUPPORTED,
+         ugks_batch_last_error(nullptr));
+  cs[1].gas = &g;
+  ugks_mesh m3 = m;
+  m3.dim = 3;
+  cs[1].mesh = &m3;
+  expect("batch, mixed dimension", ugks_batch_create(cs, 2, nullptr, &b), UGKS_EINVAL,
+         ugks_batch_last_error(nullptr));
+  cs[1].mesh = &m;
   ugks_mlp* net = nullptr;
   expect("mlp params NULL", ugks_mlp_create(nullptr, nullptr, nullptr, nullptr, &net), UGKS_EINVAL,
          ugks_mlp_last_error(nullptr));
