@@ -45,12 +45,22 @@ def test_batch_cases_follow_the_oracle():
     for i, c in enumerate(cases):
         assert b.case_info(i)["dt"] == pytest.approx(oracles[i].dt, rel=1e-14)
     steps_done = 0
+    r1_first = [0.0] * len(cases)
     for n in (1, 4):
         res = b.step(n)
         steps_done += n
         assert res.shape == (len(cases), 2)
         for i, (c, o) in enumerate(zip(cases, oracles)):
-            o.step(n)
+            ro = o.step(n)
+            if steps_done == 1:
+                r1_first[i] = ro[1]
+            # density residuals (reading R20); the bounds follow from the W bound
+            # as in the single-case parity tests
+            rg = res[i]
+            assert abs(rg[1] - ro[1]) <= max(1e-12 * ro[1], 2.0 * TOL), (i, rg, ro)
+            if r1_first[i] > 1e-10 and ro[1] > 0.0:
+                bound = 2.0 * TOL * ro[0] * (1.0 / ro[1] + 1.0 / r1_first[i])
+                assert abs(rg[0] - ro[0]) <= max(1e-12 * ro[0], bound), (i, rg, ro)
             Wo, ho, bo, qo = o.state()
             Wg, hg, bg = b.state(i)
             err = np.abs(Wg - Wo).max(axis=0) / _scales(Wo)

@@ -30,6 +30,10 @@ def test_sod3d_full_size_first_step_matches_oracle():
     err = np.abs(Wg - Wo).max(axis=0) / scale
     print("W normwise error", err, flush=True)
     assert np.all(err <= 1e-12), err
+    # per cell, relative to the cell's own rho and rho E
+    pc = np.array([np.max(np.abs(Wg[:, 0] - rho) / rho), np.max(np.abs(Wg[:, D + 1] - rE) / rE)])
+    print("per-cell relative error of rho, rho E", pc, flush=True)
+    assert np.all(pc <= 1e-12), pc
     rows = np.random.default_rng(0).choice(case.mesh.n_cells, 400, replace=False)
     herr = np.abs(hg[rows] - ho[rows]).max() / np.abs(ho).max()
     print("h error on 400 sampled cells", herr, flush=True)

@@ -9,7 +9,14 @@ tol = 1e-12 and scale_c the component's natural magnitude: max_i rho_i for
 rho, max_i rho_i sqrt(2 E_i) (density times a speed that includes the
 thermal speed) for each momentum component, max_i rho_i E_i for energy.  A
 momentum component that is zero up to round-off is thus not divided by its
-own noise.
+own noise.  Per cell the same bound holds relative to the cell's own
+magnitudes (rho_i, rho_i sqrt(2 E_i), rho_i E_i), which is the relative
+1e-12 on rho, rho U and rho E asked of the FP64 path.
+
+The step's two density residuals (reading R20) are compared too.  They are
+norms of the density change of one step, so an error e in the densities
+moves resid[1] = |d rho|/|rho| by about e and resid[0] = |d rho|/|d rho_1|
+by e |rho|/|d rho_1|: the bounds below follow from the W bound that way.
 """
 
 import numpy as np
@@ -36,6 +43,44 @@ def _normwise(a, b):
     return np.abs(a - b).max(axis=0) / _scales(b)
 
 
+def _percell(a, b):
+    """max_i |a_i - b_i| / own scale of cell i (rho_i, rho_i sqrt(2 E_i), rho_i E_i)."""
+    D = b.shape[1] - 2
+    rho, rE = b[:, 0], b[:, D + 1]
+    sc = np.empty_like(b)
+    sc[:, 0] = rho
+    sc[:, 1:1 + D] = np.sqrt(2.0 * rho * rE)[:, None]
+    sc[:, D + 1] = np.abs(rE)
+    return (np.abs(a - b) / sc).max(axis=0)
+
+
+def _psi_moments(h, b, vel, D):
+    """sum_k w_k psi_k f_ik of the oracle's distributions (Eq. macro_W)."""
+    w, u = vel.w, vel.u
+    out = np.zeros((h.shape[0], D + 2))
+    out[:, 0] = h @ w
+    out[:, 1:1 + D] = (h * w) @ u
+    out[:, D + 1] = 0.5 * ((h * w) @ (u * u).sum(axis=1))
+    if D == 2:
+        out[:, D + 1] += 0.5 * (b @ w)
+    return out
+
+
+def _check_residuals(rg, ro, r1_first, tol):
+    """Both residuals of the last step against the oracle's.
+
+    An error e |rho| in the densities moves resid[1] = |d rho_n| / |rho| by
+    about e, and resid[0] = |d rho_n| / |d rho_1| by about
+    e resid[0] (1 / resid[1] + 1 / r1_first), r1_first being resid[1] of the
+    first step.  resid[0] is compared only when that first change is far above
+    round-off (its unit is otherwise a rounding decision).
+    """
+    assert abs(rg[1] - ro[1]) <= max(1e-12 * ro[1], 2.0 * tol), (rg, ro)
+    if r1_first > 1e-10 and ro[1] > 0.0:
+        bound = 2.0 * tol * ro[0] * (1.0 / ro[1] + 1.0 / r1_first)
+        assert abs(rg[0] - ro[0]) <= max(1e-12 * ro[0], bound), (rg, ro)
+
+
 def _normwise_F(a, b):
     """Face fluxes: relative to the largest flux magnitude over all components."""
     return np.abs(a - b).max(axis=0) / max(np.abs(b).max(), 1e-300)
@@ -50,16 +95,29 @@ def _compare_step(case, steps, flags=0, tol=TOL):
     s = Solver(case, flags=flags)
     assert s.dt == pytest.approx(o.dt, rel=1e-14)
     done = 0
+    r1_first = 0.0
     while done < steps:
         n = 1 if done == 0 else (steps - done)
-        o.step(n)
-        s.step(n)
+        ro = o.step(n)
+        rg = s.step(n)
+        if done == 0:
+            r1_first = ro[1]
         done += n
         Wo, ho, bo, qo = o.state()
         Wg, hg, bg = s.state()
         err = _normwise(Wg, Wo)
-        print(f"{case.name} step {done}: W normwise err {err}", flush=True)
+        pc = _percell(Wg, Wo)
+        print(f"{case.name} step {done}: W normwise err {err} per-cell {pc} resid gpu {rg} oracle {ro}",
+              flush=True)
         assert np.all(err <= tol), err
+        if tol <= TOL:
+            assert pc[0] <= tol and pc[-1] <= tol, pc
+            assert np.all(pc <= 4 * tol), pc
+        _check_residuals(rg, ro, r1_first, tol)
+        # sum_k w_k psi_k f_k of the state against the same sums of the oracle's f
+        Mo = _psi_moments(ho, bo, case.vel, case.mesh.dim)
+        Mg = s.moments(1)
+        assert np.all(_normwise(Mg, Mo) <= tol), _normwise(Mg, Mo)
         herr = np.abs(hg - ho).max() / np.abs(ho).max()
         assert herr <= tol, herr
         if case.mesh.dim == 2:
@@ -282,3 +340,52 @@ def test_device_memory_accounting(which, prec, flags):
     print(which, prec, "fused" if info["fused"] else "staged", "f bytes", f_bytes, "other", extra,
           "per cell+face", extra / (nc + nf), flush=True)
     assert 0 <= extra <= 8192 * (nc + nf) + 256 * nvp + (4 << 20)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nontensor_locally_refined_velocity_set_parity(dim):
+    """A velocity set refined around one velocity (the paper's locally refined
+    sets, Sec. 3.3) is no tensor product: the library runs it on the staged
+    sweep, whatever velocity set it is given."""
+    if dim == 2:
+        vel = uc.locally_refined_grid(10, 4.0, 2, (0.6, 0.2), 1.3)
+        case = uc.cavity2d(n=6, kn=0.1, velocity=vel)
+        steps = 10
+    else:
+        case = uc.sod3d_tets(n=2, nv=6, jitter=0.15, seed=4)
+        case.vel = uc.locally_refined_grid(6, 4.0, 3, (0.9, 0.0, -0.3), 1.2)
+        steps = 4
+    assert case.vel.nv not in [n ** dim for n in range(2, 80)]
+    s = Solver(case)
+    assert s.info["fused"] == 0
+    s.close()
+    _compare_step(case, steps)
+
+
+def test_gauss_hermite_velocity_set_fused_parity():
+    """The cavity's Gauss-Hermite velocity set (Sec. 3.1) is a symmetric
+    tensor product: the fused sweep runs it."""
+    case = uc.cavity2d(n=8, kn=0.075, velocity=uc.gauss_hermite_grid(12, 4.5, 2))
+    s = Solver(case)
+    assert s.info["fused"] == 1
+    s.close()
+    _compare_step(case, 20)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_hexahedral_mesh_six_faces_per_cell_parity(periodic):
+    """Cells of six faces (graded hexahedra) run on the staged sweep."""
+    mesh = uc.hex_box(4, 3, 3, grading=0.4, seed=6)
+    nb = 6
+    vel = uc.midpoint_grid(6, 4.0, 3)
+    gas = uc.Gas(mu_ref=uc.hard_sphere_mu_ref(0.05))
+    left = mesh.cell_centroid[:, 0] < 0.5
+    W0 = uc.uniform_W(mesh.n_cells, 3, np.where(left, 1.0, 0.3), (0.0, 0.0, 0.0),
+                      np.where(left, 1.0, 0.8))
+    bcs = [uc.BC(uc.BC_WALL, 1.0, (0.0, 0.0, 0.0), 1.0) for _ in range(nb)]
+    bcs[3] = uc.BC(uc.BC_WALL, 1.0, (0.2, 0.0, 0.1), 1.1)  # a moving, warmer y=1 wall
+    case = uc.Case("hexbox", mesh, vel, gas, bcs, W0, 0)
+    s = Solver(case)
+    assert s.info["fused"] == 0
+    s.close()
+    _compare_step(case, 5)

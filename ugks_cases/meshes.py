@@ -167,6 +167,70 @@ def quad_mesh(nx: int, ny: int | None = None, *, lx: float = 1.0, ly: float = 1.
     return m
 
 
+def hex_box(nx: int, ny: int | None = None, nz: int | None = None, *, grading: float = 0.0,
+            seed: int = 0, name: str = "") -> Mesh:
+    """Rectilinear hexahedral mesh of the unit cube, stored as a face list.
+
+    Each axis is cut at nodes 0 < x_1 < ... < 1 whose spacings are
+    (1 + grading * U(-1, 1)) times uniform, renormalised (numpy
+    ``default_rng(seed)``), so cell volumes differ.  Every cell has six faces
+    (rectangles).  Walls get boundary-table rows 0..5 for the sides x=0,
+    x=1, y=0, y=1, z=0, z=1, as in kuhn_tet_cube.  Cell (i, j, k) has index
+    i + nx (j + ny k).
+    """
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    rng = np.random.default_rng(seed)
+
+    def nodes(n):
+        w = 1.0 + grading * rng.uniform(-1.0, 1.0, n)
+        return np.concatenate([[0.0], np.cumsum(w / w.sum())[:-1], [1.0]])
+
+    ax = [nodes(nx), nodes(ny), nodes(nz)]
+    nn = (nx, ny, nz)
+    cid = lambda i, j, k: i + nx * (j + ny * k)  # noqa: E731
+    I, J, K = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    order = np.argsort(cid(I, J, K).ravel())
+    lo = [ax[d][g.ravel()[order]] for d, g in enumerate((I, J, K))]
+    hi = [ax[d][g.ravel()[order] + 1] for d, g in enumerate((I, J, K))]
+    cen = np.stack([(lo[d] + hi[d]) / 2.0 for d in range(3)], axis=1)
+    vol = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
+    fc, fa, fn, fx, fb, fi = [], [], [], [], [], []
+    for d in range(3):
+        e1, e2 = [a for a in range(3) if a != d]
+        for t in range(nn[d] + 1):
+            for b in range(nn[e2]):
+                for a in range(nn[e1]):
+                    ijk_l = [0, 0, 0]
+                    ijk_l[d] = t - 1
+                    ijk_l[e1] = a
+                    ijk_l[e2] = b
+                    ijk_r = list(ijk_l)
+                    ijk_r[d] = t
+                    x = np.zeros(3)
+                    x[d] = ax[d][t]
+                    x[e1] = 0.5 * (ax[e1][a] + ax[e1][a + 1])
+                    x[e2] = 0.5 * (ax[e2][b] + ax[e2][b + 1])
+                    area = (ax[e1][a + 1] - ax[e1][a]) * (ax[e2][b + 1] - ax[e2][b])
+                    n = np.zeros(3)
+                    if t == 0:
+                        n[d] = -1.0
+                        fc.append((cid(*ijk_r), -1)); fb.append(BC_WALL); fi.append(2 * d)
+                    elif t == nn[d]:
+                        n[d] = 1.0
+                        fc.append((cid(*ijk_l), -1)); fb.append(BC_WALL); fi.append(2 * d + 1)
+                    else:
+                        n[d] = 1.0
+                        fc.append((cid(*ijk_l), cid(*ijk_r))); fb.append(BC_INTERIOR); fi.append(-1)
+                    fa.append(area); fn.append(n); fx.append(x)
+    m = Mesh(3, vol, cen, np.array(fc), np.array(fa), np.array(fn), np.array(fx),
+             np.zeros((len(fa), 3)), np.array(fb), np.array(fi),
+             name=name or f"hex{nx}x{ny}x{nz}_g{grading}_s{seed}")
+    m = m.contiguous()
+    m.validate()
+    return m
+
+
 def _tri_geometry(a, b, c):
     cr = np.cross(b - a, c - a)
     area2 = np.linalg.norm(cr, axis=1)

@@ -84,3 +84,40 @@ def gauss_hermite_grid(n_gh: int, u_max: float, dim: int) -> Velocity:
     wgh = 0.5 * (wgh + wgh[::-1])
     s = u_max / np.max(np.abs(xi))
     return _tensor(dim, s * xi, s * wgh * np.exp(xi ** 2), f"gh{n_gh}^{dim}[{u_max}]")
+
+
+def locally_refined_grid(n: int, a: float, dim: int, center, half_width: float,
+                         levels: int = 1) -> Velocity:
+    """A non-tensor velocity set: the midpoint grid of n cells per axis on
+    [-a, a]^dim, with every velocity cell whose centre lies in the box
+    |u - center|_inf < half_width split 2^dim-fold, ``levels`` times over.
+
+    This stands in for the locally refined velocity meshes of the paper's
+    sphere and X38 cases (Sec. 3.3, 3.4), refined around chosen velocities.
+    Each point is a cell centre and carries its cell's volume (Eq. omega_k),
+    so the weights are uneven and the set is no tensor product; it is
+    mirror-symmetric only if the refinement box is.  Points are sorted
+    lexicographically by (u_0, u_1, ...).
+    """
+    c = np.asarray(center, dtype=np.float64)[:dim]
+    du = 2.0 * a / n
+    base = (np.arange(n) + 0.5 - 0.5 * n) * du
+    grids = np.meshgrid(*([base] * dim), indexing="ij")
+    pts = np.stack([g.ravel() for g in grids], axis=1)
+    size = np.full(pts.shape[0], du)
+    for _ in range(levels):
+        inside = np.max(np.abs(pts - c[None, :]), axis=1) < half_width
+        keep_p, keep_s = pts[~inside], size[~inside]
+        sub_p, sub_s = [], []
+        offs = np.stack(np.meshgrid(*([np.array([-0.25, 0.25])] * dim), indexing="ij"),
+                        axis=-1).reshape(-1, dim)
+        for p, s in zip(pts[inside], size[inside]):
+            sub_p.append(p[None, :] + offs * s)
+            sub_s.append(np.full(offs.shape[0], 0.5 * s))
+        if sub_p:
+            pts = np.concatenate([keep_p] + sub_p)
+            size = np.concatenate([keep_s] + sub_s)
+    order = np.lexsort(tuple(pts[:, d] for d in reversed(range(dim))))
+    pts, size = pts[order], size[order]
+    return Velocity(dim, np.ascontiguousarray(pts), np.ascontiguousarray(size ** dim),
+                    (), (), f"refined{n}^{dim}[{a}]L{levels}")
