@@ -54,6 +54,9 @@ extern "C" {
 #define UGKS_BC_OUTFLOW 3  /* ghost cell: the interior state */
 
 /* ---- precision forms (ugks_options.precision) -------------------------- */
+/* most rows one ugks_mlp_forward_noalloc call takes (its static staging array) */
+#define UGKS_NOALLOC_MAX_ROWS 65536
+
 #define UGKS_FP64 64 /* h, b, their gradients and fluxes in FP64 */
 #define UGKS_FP32 32 /* h, b stored and fluxed in FP32; moments, the
                         macroscopic update and the interface equilibrium in FP64 */
@@ -380,6 +383,26 @@ int ugks_mlp_get_params(ugks_mlp* net, float* params);
 int ugks_mlp_set_box(ugks_mlp* net, const float* lo, const float* hi);
 /* y[rows*9] = network(x[rows*9]) in physical units (bf16 matrix-core inference) */
 int ugks_mlp_forward(ugks_mlp* net, const float* x, int64_t rows, float* y, int32_t on_device);
+/*
+ * ugks_mlp_forward_noalloc - the inference of ugks_mlp_forward for callers
+ * that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc).
+ *
+ * x: device pointer, rows x 9 floats (row-major features); y: device
+ * pointer, rows x 9 floats (outputs, physical units), written.  The caller
+ * owns both.  The call only enqueues work on the network's stream and
+ * returns: y is ready once that stream has reached this point.  It allocates
+ * nothing: its staging rows live in a static device array of
+ * UGKS_NOALLOC_MAX_ROWS rows (8 MiB per GPU, held until the process ends),
+ * looked up once per device.  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (other streams, other threads) race; calls
+ * ordered on one stream do not.  Nothing in the array has to start at zero.
+ * The network's device must be current.
+ * Errors: UGKS_EINVAL for rows < 0 or rows > UGKS_NOALLOC_MAX_ROWS, null
+ * pointers, or another current device (nothing is enqueued); UGKS_EHIP if a
+ * launch fails.
+ */
+int ugks_mlp_forward_noalloc(ugks_mlp* net, const float* x, int64_t rows, float* y);
 /* loss and its gradient (5385 floats, host) over all rows; the parameters are unchanged */
 int ugks_mlp_loss_grad(ugks_mlp* net, const float* x, const float* t, int64_t rows, float* grad,
                        double* loss, int32_t on_device);

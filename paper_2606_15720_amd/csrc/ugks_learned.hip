@@ -19,6 +19,14 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
+
+// Device memory of ugks_mlp_forward_noalloc: the padded input rows, then the
+// padded output rows, of at most UGKS_NOALLOC_MAX_ROWS rows (8 MiB).  Each
+// GPU holds its own copy until the process ends.  Host code never uses this
+// name as an address: it takes the device address that hipGetSymbolAddress
+// returns on each device.
+static __device__ __align__(256) float scratch[2 * UGKS_NOALLOC_MAX_ROWS * 16];
 
 namespace ugks {
 
@@ -198,6 +206,24 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpDev net, const float* __re
         if (u < NOUT) y[cell * FS + u] = z[r] * net.out_scale[u];
       }
   }
+}
+
+// Staging rows of the allocation-free inference: the caller's rows of 9
+// floats to padded rows of FS floats, and back.
+__global__ void k_rows_in(const float* __restrict__ x, int64_t rows, float* __restrict__ xs) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= rows * FS) return;
+  const int64_t r = t / FS;
+  const int j = (int)(t % FS);
+  xs[t] = j < NFEAT ? x[r * NFEAT + j] : 0.0f;
+}
+
+__global__ void k_rows_out(const float* __restrict__ ys, int64_t rows, float* __restrict__ y) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= rows * NOUT) return;
+  const int64_t r = t / NOUT;
+  const int j = (int)(t % NOUT);
+  y[t] = ys[r * FS + j];
 }
 
 // FP32 parameters -> the padded bf16 tiles of k_mlp_infer
@@ -425,6 +451,7 @@ using namespace ugks::host;
 struct ugks_mlp {
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = -1;  // the device the network's memory lives on
   std::vector<void*> allocations;
   float* p = nullptr;  // FP32 parameters
   float* m = nullptr;
@@ -496,6 +523,21 @@ void mlp_infer(const ugks_mlp* n, const float* x, int64_t rows, float* y, hipStr
   const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, 4096);
   hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(256), 0, s, mlp_dev(n), x, rows, y);
   HIP_TRY(hipGetLastError());
+}
+
+// Device address of the file-scope scratch array on the current device,
+// looked up once per device (every GPU holds its own copy of the array).
+std::mutex g_scratch_mu;
+float* g_scratch_dev[64] = {};
+
+float* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[device] = static_cast<float*>(ptr);
+  }
+  return g_scratch_dev[device];
 }
 
 // Inputs as device rows of 16 floats: copy (and pad) from the caller's rows of 9.
@@ -571,6 +613,7 @@ int ugks_mlp_create(const float* params, const float* in_scale, const float* out
       return mlp_err(nullptr, UGKS_EINVAL, "scales must be positive and finite");
   std::unique_ptr<ugks_mlp> n(new ugks_mlp());
   try {
+    HIP_TRY(hipGetDevice(&n->device));
     if (stream) {
       n->stream = (hipStream_t)stream;
     } else {
@@ -652,6 +695,33 @@ int ugks_mlp_forward(ugks_mlp* n, const float* x, int64_t rows, float* y, int32_
     HIP_TRY(hipStreamSynchronize(n->stream));
     (void)hipFree(yd);
     n->allocations.pop_back();
+  } catch (const HipFail& e) {
+    return mlp_err(n, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } UGKS_CATCH_REST(mlp_err, n)
+  return UGKS_OK;
+}
+
+int ugks_mlp_forward_noalloc(ugks_mlp* n, const float* x, int64_t rows, float* y) {
+  static_assert(FS == 16, "scratch rows are 16 floats");
+  if (!n) return mlp_err(n, UGKS_EINVAL, "null network");
+  if (rows < 0 || rows > UGKS_NOALLOC_MAX_ROWS)
+    return mlp_err(n, UGKS_EINVAL, "rows must be in [0, " + std::to_string(UGKS_NOALLOC_MAX_ROWS) +
+                                       "] for the allocation-free inference");
+  if (rows > 0 && (!x || !y)) return mlp_err(n, UGKS_EINVAL, "null input or output");
+  if (rows == 0) return UGKS_OK;
+  try {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != n->device || dev < 0 || dev >= 64)
+      return mlp_err(n, UGKS_EINVAL, "the network's device must be the current device");
+    float* xs = noalloc_scratch(dev);
+    float* ys = xs + (size_t)UGKS_NOALLOC_MAX_ROWS * FS;
+    const int64_t tin = rows * FS, tout = rows * NOUT;
+    hipLaunchKernelGGL(k_rows_in, dim3((unsigned)((tin + 255) / 256)), dim3(256), 0, n->stream, x, rows, xs);
+    HIP_TRY(hipGetLastError());
+    mlp_infer(n, xs, rows, ys, n->stream);
+    hipLaunchKernelGGL(k_rows_out, dim3((unsigned)((tout + 255) / 256)), dim3(256), 0, n->stream, ys, rows, y);
+    HIP_TRY(hipGetLastError());
   } catch (const HipFail& e) {
     return mlp_err(n, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
   } UGKS_CATCH_REST(mlp_err, n)

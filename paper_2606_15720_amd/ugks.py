@@ -28,10 +28,12 @@ EXPORTED = [
     "ugks_batch_last_error", "ugks_autotune_save", "ugks_autotune_load", "ugks_autotune_clear",
     "ugks_mlp_create", "ugks_mlp_get_params", "ugks_mlp_set_box", "ugks_mlp_forward",
     "ugks_mlp_loss_grad", "ugks_mlp_train", "ugks_mlp_destroy", "ugks_mlp_last_error",
+    "ugks_mlp_forward_noalloc",
     "ugks_snapshot", "ugks_warm_start",
 ]
 
 MLP_NPARAM = 5385
+NOALLOC_MAX_ROWS = 65536  # UGKS_NOALLOC_MAX_ROWS
 
 
 class ugks_mesh(C.Structure):
@@ -150,6 +152,8 @@ def load_library(path: str = LIB_PATH):
     lib.ugks_mlp_set_box.argtypes = [P, P, P]
     lib.ugks_mlp_forward.restype = C.c_int
     lib.ugks_mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32]
+    lib.ugks_mlp_forward_noalloc.restype = C.c_int
+    lib.ugks_mlp_forward_noalloc.argtypes = [P, P, C.c_int64, P]
     lib.ugks_mlp_loss_grad.restype = C.c_int
     lib.ugks_mlp_loss_grad.argtypes = [P, P, P, C.c_int64, P, P, C.c_int32]
     lib.ugks_mlp_train.restype = C.c_int
@@ -521,6 +525,16 @@ class MLP:
         y = np.zeros_like(x)
         _check_mlp(load_library().ugks_mlp_forward(self.h, _p(x), x.shape[0], _p(y), 0), self.h)
         return y
+
+    def forward_device(self, x_ptr: int, rows: int, y_ptr: int):
+        """ugks_mlp_forward with device rows (x, y: device pointers, rows x 9 floats)."""
+        _check_mlp(load_library().ugks_mlp_forward(self.h, C.c_void_p(x_ptr), int(rows),
+                                                   C.c_void_p(y_ptr), 1), self.h)
+
+    def forward_noalloc(self, x_ptr: int, rows: int, y_ptr: int):
+        """ugks_mlp_forward_noalloc: enqueued on the network's stream, allocates nothing."""
+        _check_mlp(load_library().ugks_mlp_forward_noalloc(self.h, C.c_void_p(x_ptr), int(rows),
+                                                           C.c_void_p(y_ptr)), self.h)
 
     def loss_grad(self, x, t):
         x, t = _f4(x), _f4(t)
