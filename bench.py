@@ -19,9 +19,13 @@ The printed JSON line also carries
     measured by rocprofv3 counters when the committed summary matches the
     current kernel source;
   * ``fp32``: the same step in the FP32 form;
-  * ``batched``: the batched form on 64 uneven 2-D cases;
+  * ``batched``: the batched form on 64 uneven 2-D cases, with the whole
+    step against HBM;
+  * ``sphere``: the Mach-5 sphere at the paper's size (101,376 tets x 28^3),
+    FP64 and FP32, with the sweep's roofline;
   * ``cpu_baseline``: the FP64 CPU oracle timed on one step of the same
-    workload.
+    workload on every host thread, and on a smaller sample on one thread,
+    with the CPU model.
 """
 
 from __future__ import annotations
@@ -40,6 +44,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (published; counts dual-issue/packed forms)
+# Unpacked FP32 vector rate, the one this library's kernels can reach (packed
+# FP32 is kept out of them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+FP32_VECTOR_TFLOPS = 78.6
 # Algorithmic FP64 flops of the sweep per cell-velocity update, 3-D tets,
 # N_r = 1 (an FMA counts 2): least-squares gradient 28, two face-velocity
 # fluxes (each face's flux serves its two cells) 2 x 69, moment sum 16,
@@ -127,12 +134,12 @@ def measure_copy_bandwidth(gib: float = 2.0, reps: int = 5) -> dict:
             "kernel": f"torch device-to-device copy of {gib:g} GiB, {reps} repetitions"}
 
 
-def run_gpu(case, precision: int, steps: int, warmup: int):
+def run_gpu(case, precision: int, steps: int, warmup: int, flags: int = 0):
     import torch
     from paper_2606_15720_amd.ugks import Solver, ugks_profile_enable, ugks_profile_read
 
     stream = torch.cuda.current_stream()
-    s = Solver(case, precision=precision, stream=stream.cuda_stream)
+    s = Solver(case, precision=precision, stream=stream.cuda_stream, flags=flags)
     info = s.info
     if warmup:
         s.step(warmup)
@@ -177,7 +184,16 @@ def run_batched(steps: int, warmup: int):
     wall = time.perf_counter() - t
     info = b.info
     b.close()
+    # whole step against HBM: f read and written by the sweep and again by
+    # stage 2, 4 N_r P = 64 bytes per update in 2-D FP64 (h and b)
+    alg_bytes = 64.0 * ups
+    gbs = alg_bytes / (wall / steps) / 1e9
     return {"value": ups * steps / wall, "unit": "cell-velocity updates/s",
+            "roofline": {"bound": "hbm", "scope": "whole step (the batch replays one graph per "
+                                                  "step; its kernels are not timed one by one)",
+                         "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_step": alg_bytes, "bytes_per_update": 64},
             "ms_per_step": wall / steps * 1e3, "cases": len(cases), "updates_per_step": ups,
             "create_and_tune_s": create_s, "lanes": info["threads"],
             "work_items": info["work_items"], "graph": bool(info["graph"]),
@@ -185,20 +201,80 @@ def run_batched(steps: int, warmup: int):
                         "velocities, Kn 1e-3..10), FP64"}
 
 
-def run_cpu_baseline(n: int):
-    """One oracle step of the same workload family on an n^3-hex mesh."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(n: int, n1: int):
+    """The FP64 oracle on the host cores: one step of the workload (n^3 hexes,
+    all threads), and one step of a smaller sample of the same family
+    (n1^3 hexes) on one thread."""
     import ugks_cases as uc
-    from oracle import Oracle, threads
+    from oracle import Oracle, set_threads, threads
 
     case = uc.sod3d_tets(n=n)
     o = Oracle(case)
     t0 = time.perf_counter()
     o.step(1)
     t = time.perf_counter() - t0
+    cores = threads()
+    del o
+    small = uc.sod3d_tets(n=n1)
+    set_threads(1)
+    try:
+        o1 = Oracle(small)
+        t0 = time.perf_counter()
+        o1.step(1)
+        t1 = time.perf_counter() - t0
+        del o1
+    finally:
+        set_threads(cores)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
     return dict(value=case.updates_per_step / t, unit="cell-velocity updates/s",
-                cores=threads(), kind="oracle",
+                cores=cores, kind="oracle", cpu_model=_cpu_model(), host_cpus=affinity,
                 sample=f"one FP64 oracle step of the 3-D Sod tet cube at {n}^3 hexes "
-                       f"({case.mesh.n_cells} tets) x 24^3 velocities, {t:.1f} s")
+                       f"({case.mesh.n_cells} tets) x 24^3 velocities on {cores} threads, {t:.1f} s",
+                one_core={"value": small.updates_per_step / t1, "unit": "cell-velocity updates/s",
+                          "cores": 1,
+                          "sample": f"one FP64 oracle step at {n1}^3 hexes ({small.mesh.n_cells} "
+                                    f"tets) x 24^3 velocities on 1 thread, {t1:.1f} s"})
+
+
+def run_sphere(steps: int, warmup: int):
+    """The Mach-5 sphere at the paper's size (101,376 tets x 28^3 velocities on
+    [-11, 11]^3, Kn 0.01, potential-flow start), FP64 and FP32, at the order
+    the time-to-residual runs use."""
+    import ugks_cases as uc
+
+    case = uc.sphere_mach5(n_ang=8, n_rad=22, nv=28, a=11.0, kn=0.01, first=0.05, start="potential")
+    first_order = 16  # ugks_options.flags bit: piecewise-constant reconstruction
+    out = {"workload": f"sphere_m5_kn0.01_{case.mesh.n_cells}x28^3", "n_cells": case.mesh.n_cells,
+           "n_faces": case.mesh.n_faces, "nv": case.vel.nv,
+           "reconstruction": "first order (unlimited second-order slopes fail at Mach 5)",
+           "steps": steps, "warmup": warmup}
+    for prec in (64, 32):
+        r = run_gpu(case, prec, steps, warmup, flags=first_order)
+        peak = FP64_PEAK_TFLOPS if prec == 64 else FP32_VECTOR_TFLOPS
+        out[f"fp{prec}"] = {
+            "value": r["value"], "unit": "cell-velocity updates/s", "ms_per_step": r["ms_per_step"],
+            "sweep_ms": r["sweep_ms"],
+            "roofline": {"bound": "alu", "kernel": "sweep", "achieved": r["tflops"], "peak": peak,
+                         "unit": "TFLOP/s", "frac": r["tflops"] / peak,
+                         "hbm": {"achieved": r["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": r["achieved"] / HBM_PEAK_GBS}}}
+        print(f"sphere fp{prec}: {r['ms_per_step']:.2f} ms/step, sweep {r['sweep_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
+    return out
 
 
 def run_warm_start(args):
@@ -313,6 +389,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=20,
                     help="hexes per edge of the oracle's sample (20 = the full workload)")
+    ap.add_argument("--cpu-sample-n1", type=int, default=10,
+                    help="hexes per edge of the oracle's one-thread sample")
+    ap.add_argument("--no-sphere", action="store_true",
+                    help="leave out the Mach-5 sphere record (101,376 tets x 28^3)")
+    ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--warm-start", action="store_true",
                     help="instead of the throughput line, the time to a 1e-6 density residual on "
                          "the reduced sphere: plain FP64 against predictor + learned warm start")
@@ -410,6 +491,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": r64["tflops"] / FP64_PEAK_TFLOPS,
             "traffic": _traffic(64),
+            "traffic_frac_of_copy": (None if _traffic(64) is None else
+                                     _traffic(64) / (r64["sweep_ms"] * 1e-3) / 1e9 / copy["GB_per_s"]),
             "avg_ms": r64["sweep_ms"],
             "algorithmic_flops_per_launch": r64["alg_flops"],
             "hbm": {"achieved": r64["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -425,16 +508,22 @@ def main():
         r32 = run_gpu(case, 32, args.steps, args.warmup)
         out["fp32"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
                        "sweep_ms": r32["sweep_ms"],
-                       "alu": {"achieved": r32["tflops"], "peak": FP32_PEAK_TFLOPS,
-                               "unit": "TFLOP/s", "frac": r32["tflops"] / FP32_PEAK_TFLOPS},
+                       "alu": {"achieved": r32["tflops"], "peak": FP32_VECTOR_TFLOPS,
+                               "unit": "TFLOP/s", "frac": r32["tflops"] / FP32_VECTOR_TFLOPS,
+                               "peak_note": "unpacked FP32 vector rate (packed FP32 is kept out "
+                                            "of the kernels); the published 157.3 TFLOP/s counts "
+                                            "packed forms",
+                               "frac_of_published": r32["tflops"] / FP32_PEAK_TFLOPS},
                        "hbm": {"achieved": r32["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": r32["achieved"] / HBM_PEAK_GBS},
                        "traffic": _traffic(32),
                        "step_hbm": _step_hbm(r32, 32, case.mesh.n_cells * case.vel.nv, copy)}
     if not args.no_batched:
         out["batched"] = run_batched(args.steps, args.warmup)
+    if not args.no_sphere:
+        out["sphere"] = run_sphere(args.sphere_steps, 2)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_n)
+        out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_n, args.cpu_sample_n1)
     print(json.dumps(out), flush=True)
 
 

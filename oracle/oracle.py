@@ -74,6 +74,8 @@ def _load():
     lib.oracle_grad_W.argtypes = [P, P]
     lib.oracle_threads.restype = i32
     lib.oracle_threads.argtypes = []
+    lib.oracle_set_threads.restype = None
+    lib.oracle_set_threads.argtypes = [i32]
     _lib = lib
     return lib
 
@@ -179,6 +181,11 @@ class Oracle:
 def threads() -> int:
     """OpenMP threads the oracle uses."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results do not depend on it)."""
+    _load().oracle_set_threads(int(n))
 
 
 def gamma(dt: float, tau: float) -> np.ndarray:

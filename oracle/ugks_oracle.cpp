@@ -1020,3 +1020,13 @@ extern "C" int oracle_threads() {
   return 1;
 #endif
 }
+
+// Set the threads of the following parallel loops (n >= 1); the results do
+// not depend on it (every reduction over velocities is sequential).
+extern "C" void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -67,3 +67,30 @@ def test_sphere_potential_start():
     np.testing.assert_allclose(f.W0[:, 1] / f.W0[:, 0], u_inf)
     with pytest.raises(ValueError):
         uc.sphere_mach5(n_ang=2, n_rad=6, nv=8, first=0.1, start="nope")
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_hex_box_is_a_closed_graded_mesh(periodic):
+    m = uc.hex_box(5, 4, 3, grading=0.4, seed=2, periodic_x=periodic)
+    m.validate()
+    assert m.n_cells == 60
+    assert m.cell_volume.sum() == pytest.approx(1.0, rel=1e-14)
+    assert m.cell_volume.max() / m.cell_volume.min() > 1.5  # uneven volumes
+    per_cell = np.bincount(m.face_cells[:, 0], minlength=60) + np.bincount(
+        m.face_cells[m.face_cells[:, 1] >= 0, 1], minlength=60)
+    assert np.all(per_cell == 6)
+    seam = np.abs(m.face_shift[:, 0]) > 0
+    assert seam.sum() == (12 if periodic else 0)
+
+
+def test_locally_refined_velocity_set():
+    v = uc.locally_refined_grid(8, 4.0, 3, (1.5, 0.0, 0.0), 0.7, levels=2)
+    # the cells still tile the box: the weights integrate 1 and u exactly
+    assert v.w.sum() == pytest.approx(8.0 ** 3, rel=1e-13)
+    np.testing.assert_allclose(v.w @ v.u, 0.0, atol=1e-11)
+    # uneven weights, no tensor product, and points inside the refined box
+    assert len(np.unique(v.w)) == 3
+    assert v.nv != round(v.nv ** (1 / 3)) ** 3
+    fine = v.w == v.w.min()
+    assert np.all(np.max(np.abs(v.u[fine] - [1.5, 0.0, 0.0]), axis=1) < 0.7 + 0.125)
+    assert len({tuple(p) for p in v.u}) == v.nv

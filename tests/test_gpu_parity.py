@@ -374,8 +374,9 @@ def test_gauss_hermite_velocity_set_fused_parity():
 
 @pytest.mark.parametrize("periodic", [False, True])
 def test_hexahedral_mesh_six_faces_per_cell_parity(periodic):
-    """Cells of six faces (graded hexahedra) run on the staged sweep."""
-    mesh = uc.hex_box(4, 3, 3, grading=0.4, seed=6)
+    """Cells of six faces (graded hexahedra) run on the staged sweep; walls
+    on every side, or a periodic seam in x."""
+    mesh = uc.hex_box(4, 3, 3, grading=0.4, seed=6, periodic_x=periodic)
     nb = 6
     vel = uc.midpoint_grid(6, 4.0, 3)
     gas = uc.Gas(mu_ref=uc.hard_sphere_mu_ref(0.05))

@@ -168,15 +168,17 @@ def quad_mesh(nx: int, ny: int | None = None, *, lx: float = 1.0, ly: float = 1.
 
 
 def hex_box(nx: int, ny: int | None = None, nz: int | None = None, *, grading: float = 0.0,
-            seed: int = 0, name: str = "") -> Mesh:
+            seed: int = 0, periodic_x: bool = False, name: str = "") -> Mesh:
     """Rectilinear hexahedral mesh of the unit cube, stored as a face list.
 
     Each axis is cut at nodes 0 < x_1 < ... < 1 whose spacings are
     (1 + grading * U(-1, 1)) times uniform, renormalised (numpy
     ``default_rng(seed)``), so cell volumes differ.  Every cell has six faces
     (rectangles).  Walls get boundary-table rows 0..5 for the sides x=0,
-    x=1, y=0, y=1, z=0, z=1, as in kuhn_tet_cube.  Cell (i, j, k) has index
-    i + nx (j + ny k).
+    x=1, y=0, y=1, z=0, z=1, as in kuhn_tet_cube; with ``periodic_x`` the
+    sides x=0 and x=1 are instead one periodic seam of interior faces
+    (L = last layer, R = first layer, shift (1, 0, 0)).  Cell (i, j, k) has
+    index i + nx (j + ny k).
     """
     ny = nx if ny is None else ny
     nz = nx if nz is None else nz
@@ -195,7 +197,7 @@ def hex_box(nx: int, ny: int | None = None, nz: int | None = None, *, grading: f
     hi = [ax[d][g.ravel()[order] + 1] for d, g in enumerate((I, J, K))]
     cen = np.stack([(lo[d] + hi[d]) / 2.0 for d in range(3)], axis=1)
     vol = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
-    fc, fa, fn, fx, fb, fi = [], [], [], [], [], []
+    fc, fa, fn, fx, fs, fb, fi = [], [], [], [], [], [], []
     for d in range(3):
         e1, e2 = [a for a in range(3) if a != d]
         for t in range(nn[d] + 1):
@@ -213,7 +215,15 @@ def hex_box(nx: int, ny: int | None = None, nz: int | None = None, *, grading: f
                     x[e2] = 0.5 * (ax[e2][b] + ax[e2][b + 1])
                     area = (ax[e1][a + 1] - ax[e1][a]) * (ax[e2][b + 1] - ax[e2][b])
                     n = np.zeros(3)
-                    if t == 0:
+                    shift = np.zeros(3)
+                    if periodic_x and d == 0 and t == 0:
+                        continue  # the seam is the face at x = 1
+                    if periodic_x and d == 0 and t == nn[d]:
+                        n[d] = 1.0
+                        shift[0] = 1.0
+                        ijk_r[0] = 0
+                        fc.append((cid(*ijk_l), cid(*ijk_r))); fb.append(BC_INTERIOR); fi.append(-1)
+                    elif t == 0:
                         n[d] = -1.0
                         fc.append((cid(*ijk_r), -1)); fb.append(BC_WALL); fi.append(2 * d)
                     elif t == nn[d]:
@@ -222,9 +232,9 @@ def hex_box(nx: int, ny: int | None = None, nz: int | None = None, *, grading: f
                     else:
                         n[d] = 1.0
                         fc.append((cid(*ijk_l), cid(*ijk_r))); fb.append(BC_INTERIOR); fi.append(-1)
-                    fa.append(area); fn.append(n); fx.append(x)
+                    fa.append(area); fn.append(n); fx.append(x); fs.append(shift)
     m = Mesh(3, vol, cen, np.array(fc), np.array(fa), np.array(fn), np.array(fx),
-             np.zeros((len(fa), 3)), np.array(fb), np.array(fi),
+             np.array(fs), np.array(fb), np.array(fi),
              name=name or f"hex{nx}x{ny}x{nz}_g{grading}_s{seed}")
     m = m.contiguous()
     m.validate()
