@@ -70,6 +70,12 @@ def _load():
     lib.oracle_steps_done.argtypes = [P]
     lib.oracle_set_order.restype = None
     lib.oracle_set_order.argtypes = [P, i32]
+    lib.oracle_set_limiter.restype = None
+    lib.oracle_set_limiter.argtypes = [P, i32, d]
+    lib.oracle_micro_grad.restype = None
+    lib.oracle_micro_grad.argtypes = [P, i64, P, P]
+    lib.oracle_macro_grad.restype = None
+    lib.oracle_macro_grad.argtypes = [P, P]
     lib.oracle_grad_W.restype = None
     lib.oracle_grad_W.argtypes = [P, P]
     lib.oracle_threads.restype = i32
@@ -91,7 +97,8 @@ def _f8(a):
 class Oracle:
     """One oracle context for a ``ugks_cases.Case``."""
 
-    def __init__(self, case, dt: float | None = None, order: int = 2):
+    def __init__(self, case, dt: float | None = None, order: int = 2, limiter: int = 0,
+                 limiter_k: float = 0.0):
         lib = _load()
         m = case.mesh.contiguous()
         v = case.vel
@@ -119,6 +126,8 @@ class Oracle:
         self.lib = lib
         if order == 1:
             lib.oracle_set_order(self.h_, 1)
+        if limiter:
+            lib.oracle_set_limiter(self.h_, int(limiter), float(limiter_k))
 
     def __del__(self):
         if getattr(self, "h_", None):
@@ -165,6 +174,20 @@ class Oracle:
         G = np.zeros(self.dim * m)
         self.lib.oracle_ls_coeffs(self.h_, i, _p(G))
         return G.reshape(self.dim, m)
+
+    def micro_grad(self, k: int):
+        """Gradients of h and b at velocity k as the next step reconstructs
+        them (order and limiter applied), [nc, D] each."""
+        gh = np.zeros((self.nc, self.dim))
+        gb = np.zeros((self.nc, self.dim))
+        self.lib.oracle_micro_grad(self.h_, int(k), _p(gh), _p(gb))
+        return gh, gb
+
+    def macro_grad(self):
+        """Gradients of W as the next step reconstructs them, [nc, D, D+2]."""
+        g = np.zeros((self.nc, self.dim, self.dim + 2))
+        self.lib.oracle_macro_grad(self.h_, _p(g))
+        return g
 
     def grad_W(self):
         """Least-squares gradients of W at the current state, [nc, D, D+2]."""

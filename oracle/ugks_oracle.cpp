@@ -40,6 +40,14 @@
 //   R16 far-field ghost = W_inf if U_inf.n < 0 else W_L; outflow ghost = W_L.
 //   R17 the Shakhov term of the stage-2 equilibrium uses q^n.
 //   R18 time coefficients by closed form for dt/tau >= 1/2, series below.
+//   R7 optional slope limiter: Venkatakrishnan's (1995) smooth limiter on the
+//      least-squares gradient of every cell field it is applied to, each
+//      conservative component of W and each (cell, velocity) of h and b:
+//      with v_max, v_min over the cell and its stencil values, at each face
+//      d- = g.(x_f - x_i), d+ = v_max - v_i (d- > 0) or v_min - v_i (d- < 0),
+//      psi = (d+^2 + eps^2 + 2 d- d+) / (d+^2 + 2 d-^2 + d- d+ + eps^2)
+//      (psi = 1 where d- = 0), phi = min(1, min_faces psi), g -> phi g,
+//      eps^2 = (K V_i^(1/D))^3.  Off by default.
 //
 // Layout (oracle's own choice): distributions are velocity-major,
 // h[k * n_cells + i], so one velocity is swept over all cells at a time, which
@@ -370,7 +378,8 @@ struct oracle_ctx {
   }
 
   // Gradient of a cell field given per-face neighbour values (step 4/5).
-  // nb[p] is the stencil value through face p of cell i.
+  // nb[p] is the stencil value through face p of cell i.  `exact` gives the
+  // plain least-squares gradient whatever the order and limiter.
   void ls_grad(int64_t i, double vi, const double* nb, double* g, bool exact = false) const {
     if (first_order && !exact) {  // piecewise-constant reconstruction
       for (int d = 0; d < D; ++d) g[d] = 0.0;
@@ -383,6 +392,40 @@ struct oracle_ctx {
       for (int p = 0; p < m; ++p) s += G[d * m + p] * (nb[p] - vi);
       g[d] = s;
     }
+    if (limiter == 1 && !exact) venkatakrishnan(i, vi, nb, g);
+  }
+
+  // Offset x_f - x_i of face f's centroid from cell i's (as seen from R
+  // across a periodic seam, the face centroid is shifted back).
+  void face_offset(int64_t i, int64_t f, double* dx) const {
+    const bool right = fbc[f] == BC_INTERIOR && fR[f] == i && fL[f] != i;
+    for (int d = 0; d < D; ++d)
+      dx[d] = fcen[f * D + d] - (right ? fshift[f * D + d] : 0.0) - cen[i * D + d];
+  }
+
+  // Reading R7: Venkatakrishnan's limiter scales the gradient g of a cell
+  // field with value vi and stencil values nb.
+  void venkatakrishnan(int64_t i, double vi, const double* nb, double* g) const {
+    const int m = (int)cfaces[i].size();
+    double vmax = vi, vmin = vi;
+    for (int p = 0; p < m; ++p) {
+      vmax = std::max(vmax, nb[p]);
+      vmin = std::min(vmin, nb[p]);
+    }
+    const double h = std::pow(vol[i], 1.0 / D);
+    const double eps2 = std::pow(limiter_k * h, 3);
+    double phi = 1.0;
+    for (int p = 0; p < m; ++p) {
+      double dx[3];
+      face_offset(i, cfaces[i][p], dx);
+      double dm = 0.0;
+      for (int d = 0; d < D; ++d) dm += g[d] * dx[d];
+      if (dm == 0.0) continue;
+      const double dp = dm > 0.0 ? vmax - vi : vmin - vi;
+      const double psi = (dp * dp + eps2 + 2.0 * dm * dp) / (dp * dp + 2.0 * dm * dm + dm * dp + eps2);
+      phi = std::min(phi, psi);
+    }
+    for (int d = 0; d < D; ++d) g[d] *= phi;
   }
 
   double compute_dt(double cfl) const {
@@ -425,6 +468,7 @@ struct oracle_ctx {
 
   int step_once();
   bool first_order = false;  // zero every least-squares gradient
+  double limiter_k = 0.0;    // Venkatakrishnan's K (reading R7)
   void macro_grad(const std::vector<double>& Wg, std::vector<double>& gW, bool exact = false) const;
 };
 
@@ -996,6 +1040,59 @@ int oracle_ctx::step_once() {
 
 // Reconstruction order: 1 = first order (all gradients zero), 2 = least squares.
 extern "C" void oracle_set_order(oracle_ctx* o, int order) { o->first_order = order == 1; }
+
+// Slope limiter (reading R7): kind 0 = none, 1 = Venkatakrishnan with constant K.
+extern "C" void oracle_set_limiter(oracle_ctx* o, int kind, double K) {
+  o->limiter = kind == 1 ? 1 : 0;
+  o->limiter_k = K;
+}
+
+// Gradients of h and b at velocity k of the current state, as the next step
+// reconstructs them (order and limiter applied), [nc*D] each.
+extern "C" void oracle_micro_grad(const oracle_ctx* o, int64_t k, double* gh, double* gb) {
+  const int D = o->D;
+  std::vector<double> Wg(o->nf * o->NW(), 0.0);
+  for (int64_t f = 0; f < o->nf; ++f)
+    if (o->fbc[f] == BC_FARFIELD || o->fbc[f] == BC_OUTFLOW)
+      o->ghost_W(f, &o->W[o->fL[f] * o->NW()], &Wg[f * o->NW()]);
+  for (int64_t i = 0; i < o->nc; ++i) {
+    const int m = (int)o->cfaces[i].size();
+    std::vector<double> nbh(m), nbb(m);
+    const double hi = o->h[k * o->nc + i], bi = o->nr == 2 ? o->b[k * o->nc + i] : 0.0;
+    for (int p = 0; p < m; ++p) {
+      const int64_t f = o->cfaces[i][p];
+      if (o->fbc[f] == BC_INTERIOR) {
+        const int64_t j = o->fL[f] == i ? o->fR[f] : o->fL[f];
+        nbh[p] = o->h[k * o->nc + j];
+        nbb[p] = o->nr == 2 ? o->b[k * o->nc + j] : 0.0;
+      } else if (o->fbc[f] == BC_WALL) {
+        nbh[p] = hi;
+        nbb[p] = bi;
+      } else {
+        const double* Wf = &Wg[f * o->NW()];
+        Prim g = o->prim(Wf);
+        nbh[p] = o->H_at(g.rho, g.U, g.lam, k);
+        nbb[p] = o->kxi / (2.0 * g.lam) * nbh[p];
+      }
+    }
+    o->ls_grad(i, hi, nbh.data(), &gh[i * D]);
+    if (o->nr == 2) o->ls_grad(i, bi, nbb.data(), &gb[i * D]);
+    else
+      for (int d = 0; d < D; ++d) gb[i * D + d] = 0.0;
+  }
+}
+
+// Gradients of W of the current state as the next step reconstructs them
+// (order and limiter applied), [nc*D*(D+2)].
+extern "C" void oracle_macro_grad(const oracle_ctx* o, double* gW) {
+  const int nw = o->NW();
+  std::vector<double> Wg(o->nf * nw, 0.0);
+  for (int64_t f = 0; f < o->nf; ++f)
+    if (o->fbc[f] == BC_FARFIELD || o->fbc[f] == BC_OUTFLOW) o->ghost_W(f, &o->W[o->fL[f] * nw], &Wg[f * nw]);
+  std::vector<double> g;
+  o->macro_grad(Wg, g, false);
+  std::copy(g.begin(), g.end(), gW);
+}
 
 // Least-squares gradients of the current state (steps 3-4 only; nothing
 // advances), whatever the reconstruction order.
