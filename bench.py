@@ -295,13 +295,17 @@ def run_warm_start(args):
     def log(*x):
         print(f"[{time.perf_counter() - t0:7.1f}s]", *x, flush=True)
 
+    second = args.ws_order == 2
     out = WS.time_to_residual(fine, coarse, target=args.ws_target, max_steps=args.ws_max_steps,
                               predictor_target=args.ws_predictor_target, log=log,
                               arms_run=tuple(args.ws_arms.split(",")),
                               ref_out=args.ws_save_ref or None, ref_in=args.ws_ref or None,
-                              deep_target=args.ws_deep or None, deep_max_steps=args.ws_max_steps)
+                              deep_target=args.ws_deep or None, deep_max_steps=args.ws_max_steps,
+                              flags=0 if second else 16, limiter=1 if second else 0,
+                              limiter_k=args.ws_limiter_k)
     out["metric"] = "time to 1e-6 density residual (s)"
-    out["reconstruction"] = "first order (no limiter: unlimited slopes fail at this Mach number)"
+    out["reconstruction"] = (f"second order with Venkatakrishnan's limiter, K = {args.ws_limiter_k}"
+                             if second else "first order")
     out["mach"] = args.ws_mach
     out["kn"] = args.ws_kn
     out["velocity_box"] = a
@@ -417,6 +421,10 @@ def main():
     ap.add_argument("--ws-deep", type=float, default=0.0,
                     help="also continue every arm to this residual and compare the fields "
                          "with the plain FP64 arm's there (0: off)")
+    ap.add_argument("--ws-order", type=int, default=1, choices=(1, 2),
+                    help="reconstruction order of every arm (2: with Venkatakrishnan's limiter)")
+    ap.add_argument("--ws-limiter-k", type=float, default=1.0,
+                    help="Venkatakrishnan's K at second order")
     ap.add_argument("--ws-start", default="freestream",
                     choices=("freestream", "rest", "potential", "sheltered"),
                     help="initial state of the sphere case")

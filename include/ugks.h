@@ -160,6 +160,17 @@ typedef struct {
  *   velocity space in device memory.
  *   stream     hipStream_t to enqueue on, or NULL for a library-owned stream.
  *              A caller stream is borrowed, never destroyed.
+ *   limiter    1 limits every least-squares gradient the step reconstructs
+ *              with (Sec. 2.1, Eq. initial_reconstruction; each conservative
+ *              component of W and each (cell, velocity) of h and b) by
+ *              Venkatakrishnan's smooth limiter (J. Comput. Phys. 118, 1995):
+ *              with v_max, v_min over the cell and its stencil values, at each
+ *              face d- = g.(x_f - x_i), d+ = v_max - v_i (d- > 0) or
+ *              v_min - v_i (d- < 0), psi = (d+^2 + eps^2 + 2 d- d+) /
+ *              (d+^2 + 2 d-^2 + d- d+ + eps^2), and g is scaled by
+ *              min(1, min_faces psi), on either sweep.  limiter_k sets eps
+ *              (0: strictly within the stencil bounds).  UGKS_EINVAL for another limiter or a negative or
+ *              non-finite K; the batched form refuses it (UGKS_EUNSUPPORTED).
  */
 typedef struct {
   int32_t precision;
@@ -167,6 +178,8 @@ typedef struct {
   int32_t flags;
   int32_t tile_cells;
   void* stream;
+  int32_t limiter;   /* 0: none; 1: Venkatakrishnan's limiter (see below) */
+  double limiter_k;  /* its constant K >= 0: eps^2 = (K V_i^(1/D))^3 */
 } ugks_options;
 
 /* Read-only facts about a context. */

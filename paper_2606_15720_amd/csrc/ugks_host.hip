@@ -88,6 +88,10 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   fail_if(Bv < 0 || Bv % WAVE != 0, "block_v must be 0 or a positive multiple of 64");
   const int tile = opt && opt->tile_cells ? opt->tile_cells : 0;
   fail_if(tile < 0, "tile_cells must be >= 0");
+  const int lim = opt ? opt->limiter : 0;
+  const double limk = opt ? opt->limiter_k : 0.0;
+  fail_if(lim != 0 && lim != 1, "limiter must be 0 (none) or 1 (Venkatakrishnan)");
+  fail_if(lim == 1 && !(limk >= 0.0 && std::isfinite(limk)), "limiter_k must be finite and >= 0");
   c->D = D;
   c->kxi = 3 - D;
   c->nr = D == 2 ? 2 : 1;
@@ -323,6 +327,12 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   m.fmir = upload(c, fmir);
   m.walls = upload(c, walls);
   m.nwall = (int64_t)walls.size();
+  m.limiter = lim;
+  if (lim) {
+    std::vector<double> veps2(nc);
+    for (int64_t i = 0; i < nc; ++i) veps2[i] = std::pow(limk * std::pow(vol[i], 1.0 / D), 3);
+    m.veps2 = upload(c, veps2);
+  }
   DevVel& v = c->vel;
   v.nv = nv;
   v.nvp = nvp;
@@ -456,6 +466,42 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     c->fmesh.crec_i = upload(c, ci);
     c->fmesh.crec_d = upload(c, cdr);
     if (prec == UGKS_FP32) c->fmesh.crec_d32 = upload(c, std::vector<float>(cdr.begin(), cdr.end()));
+    if (lim) {
+      // Limiter record (reading R7): what the sweep needs beyond the stencil
+      // to limit the cell's gradient and each neighbour's.
+      std::vector<double> lr(nc * CRL, 0.0);
+      auto eps2_of = [&](int64_t cell) { return std::pow(limk * std::pow(vol[cell], 1.0 / D), 3); };
+      auto wall_slot = [&](int64_t cell, int p) {
+        if (p >= nfc[cell]) return false;
+        return cnbr[cell * MAXF + p] < 0 && ghost_row[cface[cell * MAXF + p]] < 0;
+      };
+      for (int64_t i = 0; i < nc; ++i) {
+        double* Lr = &lr[i * CRL];
+        Lr[0] = eps2_of(i);
+        for (int p = 0; p < 4; ++p) Lr[1 + p] = wall_slot(i, p) ? 1.0 : 0.0;
+        for (int p = 0; p < 4 && p < nfc[i]; ++p) {
+          const int f = cface[i * MAXF + p];
+          const int j = cnbr[i * MAXF + p];
+          if (j < 0) continue;  // wall or ghost: the incoming side has no gradient
+          double* Fr = &Lr[CRL_F0 + CRL_FS * p];
+          Fr[0] = eps2_of(j);
+          // the neighbour's slots in record order: the shared face at slot 0
+          int order[4] = {0, 1, 2, 3};
+          for (int t = 0; t < nfc[j]; ++t)
+            if (cface[j * MAXF + t] == f) std::swap(order[0], order[t]);
+          for (int r = 0; r < 4; ++r) {
+            const int t = order[r];
+            Fr[1 + r] = wall_slot(j, t) ? 1.0 : 0.0;
+            if (t >= nfc[j]) continue;
+            const int fj = cface[j * MAXF + t];
+            const bool left = csign[j * MAXF + t] > 0.0;
+            for (int d = 0; d < 3; ++d) Fr[5 + 3 * r + d] = left ? fdxL[fj * 3 + d] : fdxR[fj * 3 + d];
+          }
+        }
+      }
+      c->fmesh.crec_l = upload(c, lr);
+      if (prec == UGKS_FP32) c->fmesh.crec_l32 = upload(c, std::vector<float>(lr.begin(), lr.end()));
+    }
     c->fmesh.nff = (int64_t)ffaces.size();
     c->fmesh.ffaces = upload(c, ffaces);
   }
@@ -635,10 +681,10 @@ void enqueue_step_fused(ugks_ctx* c) {
     // the FP32 sweep reads FP32 copies of this step's records and tables
     TIMED(KK_TABLES, launch_to_f32(B.frec, B.frec32, c->nf * FREC, B.cs, B.cs32, c->nc * CSREC,
                                    B.tabs, B.tabs32, (c->nf + c->nc) * (int64_t)D * c->fmesh.na, s));
-    TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, c->sched, c->fmesh.crec_d32, B.cs32,
+    TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, c->sched, c->fmesh.crec_d32, c->fmesh.crec_l32, B.cs32,
                                  B.frec32, B.tabs32, B.h, B.b, B.ht, B.bt, B.dW, B.flag, s));
   } else {
-    TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, c->sched, c->fmesh.crec_d, B.cs, B.frec,
+    TIMED(KK_SWEEP, launch_sweep(D, P, c->fmesh, v, g, c->sched, c->fmesh.crec_d, c->fmesh.crec_l, B.cs, B.frec,
                                  B.tabs, B.h, B.b, B.ht, B.bt, B.dW, B.flag, s));
   }
   // 8 conservative update; 10 new equilibrium (with q^n, reading R17)
@@ -994,6 +1040,9 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
   const int fixed_bv = opt ? opt->block_v : 0, fixed_tile = opt ? opt->tile_cells : 0;
   fail_if(fixed_bv < 0 || fixed_bv % WAVE != 0, "block_v must be 0 or a positive multiple of 64");
   fail_if(fixed_tile < 0, "tile_cells must be >= 0");
+  if (opt && opt->limiter)
+    throw std::pair<int, std::string>(UGKS_EUNSUPPORTED,
+                                      "the batched form runs the fused sweep, which has no limiter");
   // every case's arguments, and one dimension for all, before any device work
   for (int32_t i = 0; i < n; ++i) {
     const ugks_case& k = cases[i];

@@ -59,6 +59,8 @@ struct DevMesh {
   const double* fmir;       // [nf*3] mirror ghost offset from L: 2((x_f-x_L).n) n
   const int32_t* walls;     // [nwall] ids of the wall faces
   int64_t nwall;
+  int32_t limiter = 0;      // 1: Venkatakrishnan's limiter on every reconstruction gradient
+  const double* veps2 = nullptr;  // [nc] its eps^2 = (K V^(1/D))^3
 };
 
 // Static per-cell records of the fused sweep (built once at create).
@@ -75,6 +77,13 @@ struct DevMesh {
 //   member has no equilibrium term).
 constexpr int CRI = 48, CRI_F0 = 6, CRI_FS = 10;
 constexpr int CRD = 112, CRD_F0 = 12, CRD_FS = 24;
+// Limiter record of the fused path (CRL doubles per cell, only with the
+// limiter): [0] eps^2 of the cell, [1..4] 1 where own stencil slot s is a
+// wall (its row is the zero row; its value for the bounds is the cell's own),
+// then per face p at CRL_F0 + CRL_FS p: [0] eps^2 of the neighbour, [1..4]
+// the neighbour's wall slots, [5 + 3 r + d] the offset of the neighbour's
+// face in its stencil slot r from its centroid (slot order of the record).
+constexpr int CRL = 88, CRL_F0 = 8, CRL_FS = 20;
 // Per-cell, per-step record of the fused path (CSREC doubles per cell).
 constexpr int CSREC = 48, CS_CC = 0, CS_KAP = 1, CS_NORM = 2, CS_SH = 4, CS_SB = 24;
 
@@ -86,6 +95,8 @@ struct FusedMesh {
   const int32_t* crec_i;    // [nc*CRI]
   const double* crec_d;     // [nc*CRD]
   const float* crec_d32;    // [nc*CRD] FP32 copy (FP32 compute form), else null
+  const double* crec_l = nullptr;  // [nc*CRL] limiter record, null without the limiter
+  const float* crec_l32 = nullptr; // its FP32 copy (FP32 compute form)
   const int32_t* ffaces;    // [nff] far-field / outflow faces; face m owns ghost row nc+1+m
   int64_t nff;
 };
@@ -216,7 +227,8 @@ hipError_t launch_cell_prep(int D, int64_t nc, const GasP& g, const double* W, c
                             double* prim, double* cs, int32_t* flag, hipStream_t s);
 // crec_d, cs, frec, tabs: FP64 records, or their FP32 copies when prec is FP32
 hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, const GasP& g,
-                        const SweepSched& sc, const void* crec_d, const void* cs, const void* frec,
+                        const SweepSched& sc, const void* crec_d, const void* crec_l,
+                        const void* cs, const void* frec,
                         const void* tabs, const void* h, const void* b, void* ht, void* bt,
                         double* dWp, const int32_t* flag, hipStream_t s);
 hipError_t launch_to_f32(const double* a, float* fa, int64_t na, const double* b, float* fb,

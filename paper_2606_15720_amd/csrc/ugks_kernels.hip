@@ -54,6 +54,30 @@ __global__ __launch_bounds__(TPB) void k_heatflux(DevVel v, const T* __restrict_
   }
 }
 
+// Venkatakrishnan's limiter factor of one cell field (Sec. 2.1 reconstruction
+// with an optional limiter): vi is the cell's value, [vmin, vmax] the range
+// of the cell and its stencil values, g its least-squares gradient.  At each
+// face d- = g.(x_f - x_i) and d+ the room left toward the bound on its side;
+// psi = (d+^2 + eps^2 + 2 d- d+) / (d+^2 + 2 d-^2 + d- d+ + eps^2); the
+// factor is min(1, min_faces psi).
+template <int D>
+__device__ __forceinline__ double venkat_phi(const DevMesh& m, int64_t i, int nfc, double vi,
+                                             double vmin, double vmax, const double* g) {
+  const double eps2 = m.veps2[i];
+  double phi = 1.0;
+  for (int p = 0; p < nfc; ++p) {
+    const int f = m.cface[i * MAXF + p];
+    const double* dx = m.csign[i * MAXF + p] > 0.0 ? &m.fdxL[f * 3] : &m.fdxR[f * 3];
+    double dm = 0.0;
+    for (int d = 0; d < D; ++d) dm += g[d] * dx[d];
+    if (dm == 0.0) continue;
+    const double dp = dm > 0.0 ? vmax - vi : vmin - vi;
+    const double psi = (dp * dp + eps2 + 2.0 * dm * dp) / (dp * dp + 2.0 * dm * dm + dm * dp + eps2);
+    phi = fmin(phi, psi);
+  }
+  return phi;
+}
+
 // Macroscopic least-squares gradients of W (step 4).
 template <int D>
 __device__ __forceinline__ void gradW_at(int64_t i, const DevMesh& m, const DevBC* __restrict__ bcs,
@@ -62,9 +86,10 @@ __device__ __forceinline__ void gradW_at(int64_t i, const DevMesh& m, const DevB
   if (*flag) return;
   const int nfc = m.nfc[i];
   const double* Wi = &W[i * (D + 2)];
-  double acc[3][5];
+  double acc[3][5], vmin[5], vmax[5];
   for (int d = 0; d < 3; ++d)
     for (int v = 0; v < 5; ++v) acc[d][v] = 0.0;
+  for (int v = 0; v < D + 2; ++v) vmin[v] = vmax[v] = Wi[v];
   for (int p = 0; p < nfc; ++p) {
     const int f = m.cface[i * MAXF + p];
     const int j = m.cnbr[i * MAXF + p];
@@ -76,11 +101,21 @@ __device__ __forceinline__ void gradW_at(int64_t i, const DevMesh& m, const DevB
     } else {
       ghost_state<D>(m.fbc[f], bcs[m.fbcid[f]], &m.fnorm[f * 3], Wi, g.R, nb);
     }
+    for (int v = 0; v < D + 2; ++v) {
+      vmin[v] = fmin(vmin[v], nb[v]);
+      vmax[v] = fmax(vmax[v], nb[v]);
+    }
     for (int d = 0; d < D; ++d) {
       const double G = m.lsG[(i * 3 + d) * MAXF + p];
       for (int v = 0; v < D + 2; ++v) acc[d][v] += G * (nb[v] - Wi[v]);
     }
   }
+  if (m.limiter)
+    for (int v = 0; v < D + 2; ++v) {
+      double gv[3] = {acc[0][v], acc[1][v], acc[2][v]};
+      const double phi = venkat_phi<D>(m, i, nfc, Wi[v], vmin[v], vmax[v], gv);
+      for (int d = 0; d < D; ++d) acc[d][v] *= phi;
+    }
   for (int d = 0; d < 3; ++d)
     for (int v = 0; v < 5; ++v) gW[(i * 3 + d) * 5 + v] = (d < D && v < D + 2) ? acc[d][v] : 0.0;
 }
@@ -289,6 +324,7 @@ __global__ __launch_bounds__(TPB) void k_grad_micro(DevMesh m, DevVel v,
   const double hi = ld(h, i * nvp + k);
   const double bi = (D == 2) ? ld(b, i * nvp + k) : 0.0;
   double ah[3] = {0, 0, 0}, ab[3] = {0, 0, 0};
+  double hmin = hi, hmax = hi, bmin = bi, bmax = bi;
   const int nfc = m.nfc[i];
   for (int p = 0; p < nfc; ++p) {
     const int j = m.cnbr[i * MAXF + p];
@@ -312,10 +348,22 @@ __global__ __launch_bounds__(TPB) void k_grad_micro(DevMesh m, DevVel v,
         bn = (3 - D) / (2.0 * R[FR_GLAM]) * hn;
       }
     }
+    hmin = fmin(hmin, hn);
+    hmax = fmax(hmax, hn);
+    bmin = fmin(bmin, bn);
+    bmax = fmax(bmax, bn);
     for (int d = 0; d < D; ++d) {
       const double G = m.lsG[(i * 3 + d) * MAXF + p];
       ah[d] += G * (hn - hi);
       if (D == 2) ab[d] += G * (bn - bi);
+    }
+  }
+  if (m.limiter) {
+    const double ph = venkat_phi<D>(m, i, nfc, hi, hmin, hmax, ah);
+    const double pb = (D == 2) ? venkat_phi<D>(m, i, nfc, bi, bmin, bmax, ab) : 1.0;
+    for (int d = 0; d < D; ++d) {
+      ah[d] *= ph;
+      ab[d] *= pb;
     }
   }
   for (int d = 0; d < D; ++d) {

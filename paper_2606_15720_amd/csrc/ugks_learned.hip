@@ -802,6 +802,7 @@ int ugks_snapshot(ugks_ctx* c, float* feat, float* targ) {
     HIP_TRY(launch_prims(D, c->mesh, c->gas, B.W, B.prim, B.flag, 0, s));
     DevMesh mg = c->mesh;
     mg.lsG = c->lsG_exact;  // features use the true gradient at any reconstruction order
+    mg.limiter = 0;         // and unlimited
     HIP_TRY(launch_gradW(D, mg, c->bcs, c->gas, B.W, B.gW, B.flag, s));
     const unsigned g1 = (unsigned)((nc + 127) / 128);
     if (D == 2) hipLaunchKernelGGL(k_features<2>, dim3(g1), dim3(128), 0, s, nc, c->gas, B.W, B.gW, fd);
@@ -858,6 +859,7 @@ int ugks_warm_start(ugks_ctx* c, const ugks_mlp* net, const double* W, int64_t* 
     HIP_TRY(launch_prims(D, c->mesh, c->gas, B.W, B.prim, B.flag, 0, s));
     DevMesh mg = c->mesh;
     mg.lsG = c->lsG_exact;  // features use the true gradient at any reconstruction order
+    mg.limiter = 0;         // and unlimited
     HIP_TRY(launch_gradW(D, mg, c->bcs, c->gas, B.W, B.gW, B.flag, s));
     const unsigned g1 = (unsigned)((nc + 127) / 128);
     if (D == 2) hipLaunchKernelGGL(k_features<2>, dim3(g1), dim3(128), 0, s, nc, c->gas, B.W, B.gW, fd);

@@ -86,6 +86,32 @@ __device__ __forceinline__ void cubic_eo(PT P, const C* v, C v2, C& E, C& O) {
   }
 }
 
+// Venkatakrishnan's limiter factor (Sec. 2.1 reconstruction with the
+// optional limiter) of a gradient g of a field with cell value vi and stencil
+// range [vmin, vmax]: at each of four faces with offsets off[q * stride + d]
+// from the centroid, d- = g.off, d+ = vmax - vi (d- > 0) or vmin - vi,
+// psi = (d+^2 + eps^2 + 2 d- d+) / (d+^2 + 2 d-^2 + d- d+ + eps^2) (psi = 1
+// where d- = 0); returns min(1, min_faces psi).  The minimum is kept as a
+// fraction and divided once.
+template <int D, typename C, typename PT>
+__device__ __forceinline__ C venkat_phi(C vi, C vmin, C vmax, const C* g, PT off, int stride, C eps2) {
+  C Nm = C(1), Dm = C(1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    C dm = C(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) dm += g[d] * off[q * stride + d];
+    const C dp = dm > C(0) ? vmax - vi : vmin - vi;
+    C N = dp * dp + eps2 + C(2) * dm * dp;
+    C Dn = dp * dp + C(2) * dm * dm + dm * dp + eps2;
+    if (dm == C(0)) N = Dn = C(1);
+    const bool lt = N * Dm < Nm * Dn;
+    Nm = lt ? N : Nm;
+    Dm = lt ? Dn : Dm;
+  }
+  return Nm / Dm;
+}
+
 // Per-cell first-stage data of one step: dt/(2 tau), K_xi/(2 lambda) and the
 // Shakhov polynomials H+/H, B+/B of the cell's equilibrium (Eqs. H_plus, B_plus).
 template <int D>
@@ -183,10 +209,10 @@ struct SweepLds {
 // Every read-only array is its own __restrict__ argument so that the
 // compiler can prove no store of the sweep clobbers it and serve the
 // wave-uniform reads from the scalar cache.
-template <int D, typename T, typename C, bool SPLIT>
+template <int D, typename T, typename C, bool SPLIT, bool LIM = false>
 __device__ __forceinline__ void sweep_item(
     const FusedMesh& fm, int64_t nvp, const SweepSched& sc, const int32_t* __restrict__ crec_i,
-    const C* __restrict__ crec_d, const int32_t* __restrict__ vidx,
+    const C* __restrict__ crec_d, const C* __restrict__ crec_l, const int32_t* __restrict__ vidx,
     const double* __restrict__ w, const C* __restrict__ cs, const C* __restrict__ frec,
     const C* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
     T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dWp,
@@ -197,6 +223,7 @@ __device__ __forceinline__ void sweep_item(
   crec_t<C>* cd0 = (crec_t<C>*)(crec_d + ic * CRD);
   crec_t<C>* cc0 = (crec_t<C>*)(cs + ic * CSREC);
   crec_t<C>* frc = (crec_t<C>*)frec;
+  crec_t<C>* cl0 = LIM ? (crec_t<C>*)(crec_l + ic * CRL) : nullptr;
   const unsigned nthr = blockDim.x;  // lanes of the work-group, one mirror pair each
   const int na = fm.na;
   {
@@ -560,6 +587,29 @@ __device__ __forceinline__ void sweep_item(
             g1[d] += G * d1;
           }
         }
+        crec_t<C>* cl = LIM ? cl0 + z : nullptr;
+        if constexpr (LIM) {
+          // the cell's own gradients at u and -u, limited (a wall slot's
+          // zero row stands for the cell's own value in the bounds)
+          C lo0 = f0, hi0 = f0, lo1 = f1, hi1 = f1;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const C wm = cl[1 + s];
+            const C v0 = wm * f0 + os0[s], v1 = wm * f1 + os1[s];
+            lo0 = fmin(lo0, v0);
+            hi0 = fmax(hi0, v0);
+            lo1 = fmin(lo1, v1);
+            hi1 = fmax(hi1, v1);
+          }
+          const C e2 = cl[0];
+          const C p0 = venkat_phi<D>(f0, lo0, hi0, g0, cd + CRD_F0 + 4, CRD_FS, e2);
+          const C p1 = venkat_phi<D>(f1, lo1, hi1, g1, cd + CRD_F0 + 4, CRD_FS, e2);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            g0[d] *= p0;
+            g1[d] *= p1;
+          }
+        }
         C ug0 = C(0), ug1 = C(0);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -592,6 +642,21 @@ __device__ __forceinline__ void sweep_item(
             const C df = nhs[p][r] - fj;
 #pragma unroll
             for (int d = 0; d < D; ++d) gj[d] += fd[10 + d * 4 + r] * df;
+          }
+          if constexpr (LIM) {
+            // the neighbour's gradient at the incoming member, limited with
+            // its own stencil bounds and face offsets
+            crec_t<C>* Fr = cl + CRL_F0 + CRL_FS * p;
+            C lo = fj, hi = fj;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const C vr = Fr[1 + r] * fj + nhs[p][r];
+              lo = fmin(lo, vr);
+              hi = fmax(hi, vr);
+            }
+            const C pj = venkat_phi<D>(fj, lo, hi, gj, Fr + 5, 3, Fr[0]);
+#pragma unroll
+            for (int d = 0; d < D; ++d) gj[d] *= pj;
           }
           C ffj = fj, ugj = C(0);
 #pragma unroll
@@ -665,10 +730,10 @@ __device__ __forceinline__ void sweep_item(
 // FP32 copies of the records and tables; moment sums stay FP64).  The FP32
 // body fits in half the registers; its bound asks for the occupancy that
 // hides the gathers' latency (measured: 7 waves per SIMD, no spills).
-template <int D, typename T>
+template <int D, typename T, bool LIM>
 __global__ __launch_bounds__(SWT, (sizeof(T) == 4 ? 6 : 4)) void k_sweep(
     FusedMesh fm, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
-    const T* __restrict__ crec_d, const int32_t* __restrict__ vidx,
+    const T* __restrict__ crec_d, const T* __restrict__ crec_l, const int32_t* __restrict__ vidx,
     const double* __restrict__ w, const T* __restrict__ cs, const T* __restrict__ frec,
     const T* __restrict__ tabs, const T* __restrict__ h, const T* __restrict__ b,
     T* __restrict__ ht, T* __restrict__ bt, double* __restrict__ dWp,
@@ -686,8 +751,8 @@ __global__ __launch_bounds__(SWT, (sizeof(T) == 4 ? 6 : 4)) void k_sweep(
   const int64_t chunk = rem / sc.tile;
   const int64_t ic = tile * sc.tile + rem % sc.tile;
   if (ic >= fm.nc) return;
-  sweep_item<D, T, T, true>(fm, nvp, sc, crec_i, crec_d, vidx, w, cs, frec, tabs, h, b, ht, bt, dWp,
-                      flag, ic, chunk, L);
+  sweep_item<D, T, T, true, LIM>(fm, nvp, sc, crec_i, crec_d, crec_l, vidx, w, cs, frec, tabs, h, b,
+                                 ht, bt, dWp, flag, ic, chunk, L);
 }
 
 // The fused sweep over a batch of cases: a persistent grid walks a list of
@@ -735,7 +800,7 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 3)) void k_sweep_b(BatchDev bd) 
     double* dW = cases[c].B.dW;
     const int32_t* flag = cases[c].B.flag;
     __syncthreads();  // the previous item's readers of L are done
-    sweep_item<D, T, double, false>(fm, nvp, sc, fm.crec_i, fm.crec_d, fm.vidx, w, cs, frec, tabs, h, b, ht, bt,
+    sweep_item<D, T, double, false>(fm, nvp, sc, fm.crec_i, fm.crec_d, nullptr, fm.vidx, w, cs, frec, tabs, h, b, ht, bt,
                      dW, flag, ic, chunk, L);
   }
 }
@@ -896,7 +961,7 @@ struct WallLds {
 // cell (its gradient evaluated in place) against the re-emitted wall
 // Maxwellian, whose value at a tensor point is a product of three LDS
 // axis factors (no per-velocity exp).
-template <int D, typename T>
+template <int D, typename T, bool LIM = false>
 __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const DevVel& v,
                                             const FusedMesh& fm, const GasP& g,
                                             const T* __restrict__ h, double* __restrict__ frec,
@@ -991,6 +1056,20 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
 #pragma unroll
           for (int d = 0; d < D; ++d) gr[d] += cd[d * 4 + s] * dh;
         }
+        if constexpr (LIM) {
+          // the wall cell's gradient limited as the sweep limits it
+          crec_t<double>* cl = (crec_t<double>*)(fm.crec_l + L * CRL);
+          double lo = hl[u], hi = hl[u];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const double vs = cl[1 + s] * hl[u] + hs[u][s];
+            lo = fmin(lo, vs);
+            hi = fmax(hi, vs);
+          }
+          const double ph = venkat_phi<D>(hl[u], lo, hi, gr, cd + CRD_F0 + 4, CRD_FS, cl[0]);
+#pragma unroll
+          for (int d = 0; d < D; ++d) gr[d] *= ph;
+        }
         double hf = hl[u], ugh = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -1019,7 +1098,8 @@ __global__ __launch_bounds__(WALLT) void k_wall_rho_inline(DevMesh m, DevVel v, 
                                                          double* __restrict__ frec,
                                                          const int32_t* flag) {
   __shared__ WallLds S;
-  wall_rho_at<D, T>(blockIdx.x, m, v, fm, g, h, frec, flag, S);
+  if (fm.crec_l) wall_rho_at<D, T, true>(blockIdx.x, m, v, fm, g, h, frec, flag, S);
+  else wall_rho_at<D, T, false>(blockIdx.x, m, v, fm, g, h, frec, flag, S);
 }
 
 // Ghost rows of the far-field / outflow faces: the Maxwellian of the face's
@@ -1185,14 +1265,18 @@ hipError_t launch_cell_prep(int D, int64_t nc, const GasP& g, const double* W, c
 }
 
 hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, const GasP& g,
-                        const SweepSched& sc, const void* crec_d, const void* cs, const void* frec,
+                        const SweepSched& sc, const void* crec_d, const void* crec_l,
+                        const void* cs, const void* frec,
                         const void* tabs, const void* h, const void* b, void* ht, void* bt,
                         double* dWp, const int32_t* flag, hipStream_t s) {
   const int64_t ntile = (fm.nc + sc.tile - 1) / sc.tile;
   const unsigned grid = (unsigned)(((ntile + 7) / 8) * 8 * sc.nchunk * sc.tile);
-  UGKS_DISPATCH_DT(D, prec, k_sweep<DD, TT><<<grid, SWT, 0, s>>>(
-      fm, v.nvp, sc, fm.crec_i, (const TT*)crec_d, fm.vidx, v.w, (const TT*)cs, (const TT*)frec,
-      (const TT*)tabs, (const TT*)h, (const TT*)b, (TT*)ht, (TT*)bt, dWp, flag));
+#define UGKS_SWEEP_ARGS                                                                       \
+  fm, v.nvp, sc, fm.crec_i, (const TT*)crec_d, (const TT*)crec_l, fm.vidx, v.w, (const TT*)cs, \
+      (const TT*)frec, (const TT*)tabs, (const TT*)h, (const TT*)b, (TT*)ht, (TT*)bt, dWp, flag
+  if (crec_l) UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, true><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+  else UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, false><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+#undef UGKS_SWEEP_ARGS
   return hipGetLastError();
 }
 

@@ -60,7 +60,8 @@ class ugks_bc(C.Structure):
 
 class ugks_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("block_v", C.c_int32), ("flags", C.c_int32),
-                ("tile_cells", C.c_int32), ("stream", C.c_void_p)]
+                ("tile_cells", C.c_int32), ("stream", C.c_void_p), ("limiter", C.c_int32),
+                ("limiter_k", C.c_double)]
 
 
 class ugks_info_t(C.Structure):
@@ -192,7 +193,7 @@ def _check(rc, ctx=None):
 
 
 def ugks_create(mesh, vel, gas, bcs, W0, precision=UGKS_FP64, block_v=0, flags=0, stream=None,
-                tile_cells=0):
+                tile_cells=0, limiter=0, limiter_k=0.0):
     """Create a context from a ``ugks_cases`` mesh / velocity / gas / BC list.
 
     Returns ``(handle, keepalive)``; the arrays are copied by the library, so
@@ -200,7 +201,8 @@ def ugks_create(mesh, vel, gas, bcs, W0, precision=UGKS_FP64, block_v=0, flags=0
     """
     lib = load_library()
     keep = _marshal(mesh, vel, gas, bcs, W0)
-    opt = ugks_options(precision, block_v, flags, tile_cells, C.c_void_p(stream) if stream else None)
+    opt = ugks_options(precision, block_v, flags, tile_cells, C.c_void_p(stream) if stream else None,
+                       int(limiter), float(limiter_k))
     h = C.c_void_p()
     rc = lib.ugks_create(C.byref(keep["cm"]), C.byref(keep["cv"]), C.byref(keep["cg"]),
                          C.cast(keep["bcs"], C.c_void_p), keep["nb"], _p(keep["W0"]), C.byref(opt),
@@ -287,13 +289,14 @@ def ugks_last_error(h=None) -> str:
 class Solver:
     """Owning wrapper around one library context for a ``ugks_cases.Case``."""
 
-    def __init__(self, case, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0):
+    def __init__(self, case, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0,
+                 limiter=0, limiter_k=0.0):
         self.case = case
         self.dim = case.mesh.dim
         self.nc, self.nf, self.nv = case.mesh.n_cells, case.mesh.n_faces, case.vel.nv
         self.h, _ = ugks_create(case.mesh, case.vel, case.gas, case.bcs, case.W0,
                                 precision=precision, block_v=block_v, flags=flags, stream=stream,
-                                tile_cells=tile_cells)
+                                tile_cells=tile_cells, limiter=limiter, limiter_k=limiter_k)
 
     def close(self):
         if getattr(self, "h", None):
@@ -349,7 +352,8 @@ def _check_batch(rc, b=None):
         raise UGKSError(rc, msg.decode() if msg else "")
 
 
-def ugks_batch_create(cases, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0):
+def ugks_batch_create(cases, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0,
+                      limiter=0, limiter_k=0.0):
     """Create a batch from a list of ``ugks_cases.Case``; returns the handle."""
     lib = load_library()
     keeps = [_marshal(c.mesh, c.vel, c.gas, c.bcs, c.W0) for c in cases]
@@ -358,7 +362,8 @@ def ugks_batch_create(cases, precision=UGKS_FP64, block_v=0, flags=0, stream=Non
         arr[i] = ugks_case(C.cast(C.pointer(k["cm"]), C.c_void_p), C.cast(C.pointer(k["cv"]), C.c_void_p),
                            C.cast(C.pointer(k["cg"]), C.c_void_p), C.cast(k["bcs"], C.c_void_p),
                            k["nb"], _p(k["W0"]))
-    opt = ugks_options(precision, block_v, flags, tile_cells, C.c_void_p(stream) if stream else None)
+    opt = ugks_options(precision, block_v, flags, tile_cells, C.c_void_p(stream) if stream else None,
+                       int(limiter), float(limiter_k))
     h = C.c_void_p()
     rc = lib.ugks_batch_create(C.cast(arr, C.c_void_p), len(cases), C.byref(opt), C.byref(h))
     _check_batch(rc, None)
@@ -420,10 +425,12 @@ def ugks_autotune_clear():
 class Batch:
     """Owning wrapper around one batch of ``ugks_cases.Case`` objects."""
 
-    def __init__(self, cases, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0):
+    def __init__(self, cases, precision=UGKS_FP64, block_v=0, flags=0, stream=None, tile_cells=0,
+                 limiter=0, limiter_k=0.0):
         self.cases = list(cases)
         self.h = ugks_batch_create(self.cases, precision=precision, block_v=block_v, flags=flags,
-                                   stream=stream, tile_cells=tile_cells)
+                                   stream=stream, tile_cells=tile_cells, limiter=limiter,
+                                   limiter_k=limiter_k)
 
     def close(self):
         if getattr(self, "h", None):

@@ -145,19 +145,26 @@ def train(F, T, *, seed=0, steps=2000, batch=512, lr=3e-3, lr_final=3e-4, box_ma
 # ---------------------------------------------------------------------------
 # time to a steady residual: plain start against predictor + learned start
 
-def run_to_residual(solver, target, max_steps, chunk=500, log=None, label=""):
+def run_to_residual(solver, target, max_steps, chunk=500, log=None, label="", r20=None):
     """Step until the density residual (RMS dRho / RMS rho per step) <= target.
 
     Returns (steps, final residual, reached).  Steps are taken in chunks; the
     check uses the last step of each chunk, so `steps` is rounded up to the
-    chunk.  `log(label, steps, residual)` is called after every chunk.
+    chunk.  `log(label, steps, residual)` is called after every chunk.  If
+    `r20` is a dict, r20["steps"] receives the first chunk end at which the
+    residual normalised by the run's first density change (reading R20,
+    resid[0]) is <= target, and r20["last"] its last value.
     """
     done = 0
     r = float("inf")
     while done < max_steps:
         n = min(chunk, max_steps - done)
-        r = solver.step(n)[1]
+        r0, r = solver.step(n)
         done += n
+        if r20 is not None:
+            r20["last"] = r0
+            if r0 <= target and r20.get("steps") is None:
+                r20["steps"] = done
         if log:
             log(label, done, r)
         if r <= target:
@@ -225,7 +232,8 @@ def build_training_set(seed: int = 4, copies: int = 3, log=None):
 def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e-4,
                      max_steps=60000, chunk=1000, flags=16, train_seed=4, log=None,
                      arms_run=("plain64", "maxwell32", "learned32", "learned64"),
-                     ref_out=None, ref_in=None, deep_target=None, deep_max_steps=200000):
+                     ref_out=None, ref_in=None, deep_target=None, deep_max_steps=200000,
+                     limiter=0, limiter_k=0.0):
     """Plain FP64 from the initial state against predictor + learned warm start.
 
     Arms (all to a density residual <= target, wall time from creation):
@@ -246,7 +254,9 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
     """
     import time
     out = {"case": case_fine.name, "n_cells": case_fine.mesh.n_cells, "nv": case_fine.vel.nv,
-           "nv_predictor": case_coarse.vel.nv, "target": target, "flags": flags}
+           "nv_predictor": case_coarse.vel.nv, "target": target, "flags": flags,
+           "limiter": limiter, "limiter_k": limiter_k}
+    lim = dict(limiter=limiter, limiter_k=limiter_k)
     t0 = time.perf_counter()
     F, T = build_training_set(train_seed, log=log)
     t1 = time.perf_counter()
@@ -262,16 +272,19 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
         if W0 is not None:
             case = type(case_fine)(case_fine.name, case_fine.mesh, case_fine.vel, case_fine.gas,
                                    case_fine.bcs, W0, case_fine.steps, case_fine.meta)
-        s = U.Solver(case, precision=precision, flags=flags)
+        s = U.Solver(case, precision=precision, flags=flags, **lim)
         nfall = None
         if warm:
             nfall = U.ugks_warm_start(s.h, net)
-        steps, r, ok = run_to_residual(s, target, max_steps, chunk, log, name)
+        r20 = {}
+        steps, r, ok = run_to_residual(s, target, max_steps, chunk, log, name, r20=r20)
         W = s.W()
         dt = time.perf_counter() - t
         arms[name] = {"precision": precision, "steps": steps, "residual": r, "reached": ok,
                       "seconds": dt + extra_s, "seconds_without_predictor": dt,
-                      "fallback_cells": nfall}
+                      "fallback_cells": nfall,
+                      "r20": {"steps_to_target": r20.get("steps"), "last": r20.get("last"),
+                              "note": "residual normalised by this run's own first density change"}}
         if deep_target:
             ds, dr, dok = run_to_residual(s, deep_target, deep_max_steps, chunk, log, name + "-deep")
             deep[name] = s.W()
@@ -301,7 +314,7 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
         net.close()
         return out
     t = time.perf_counter()
-    p = U.Solver(case_coarse, precision=U.UGKS_FP32, flags=flags)
+    p = U.Solver(case_coarse, precision=U.UGKS_FP32, flags=flags, **lim)
     psteps, pr, pok = run_to_residual(p, predictor_target, max_steps, chunk, log, "predictor")
     Wp = p.W()
     p.close()

@@ -142,6 +142,9 @@ def test_fixed_schedule_and_mixed_dimension_rejected():
     assert b.info["tuned"] == 0
     assert b.case_info(0)["tile_cells"] == min(16, cases[0].mesh.n_cells)
     b.close()
+    with pytest.raises(U.UGKSError) as e:
+        U.Batch(cases, limiter=1, limiter_k=1.0)
+    assert e.value.code == U.UGKS_EUNSUPPORTED and "limiter" in str(e.value)
     mixed = [cases[0], uc.sod3d_tets(n=2, nv=8)]
     with pytest.raises(U.UGKSError) as e:
         U.Batch(mixed)

@@ -90,9 +90,9 @@ STAGED = 2  # ugks_options.flags bit: force the staged (unfused) sweep
 FIRST_ORDER = 16  # ugks_options.flags bit: first-order reconstruction
 
 
-def _compare_step(case, steps, flags=0, tol=TOL):
-    o = Oracle(case, order=1 if flags & FIRST_ORDER else 2)
-    s = Solver(case, flags=flags)
+def _compare_step(case, steps, flags=0, tol=TOL, limiter=0, limiter_k=0.0):
+    o = Oracle(case, order=1 if flags & FIRST_ORDER else 2, limiter=limiter, limiter_k=limiter_k)
+    s = Solver(case, flags=flags, limiter=limiter, limiter_k=limiter_k)
     assert s.dt == pytest.approx(o.dt, rel=1e-14)
     done = 0
     r1_first = 0.0
@@ -390,3 +390,47 @@ def test_hexahedral_mesh_six_faces_per_cell_parity(periodic):
     assert s.info["fused"] == 0
     s.close()
     _compare_step(case, 5)
+
+
+@pytest.mark.parametrize("flags", PATHS)
+@pytest.mark.parametrize("which,k", [("cavity2d", 0.0), ("cavity2d", 1.0), ("sod3d", 1.0),
+                                     ("sod3d", 0.0), ("sphere3d", 1.0), ("channel2d", 0.3)])
+def test_venkatakrishnan_limiter_parity(which, k, flags):
+    """Second order with Venkatakrishnan's limiter (reading R7) on W and on
+    every (cell, velocity) of h and b, against the oracle with the same
+    limiter, on both sweeps (the fused one limits each neighbour's gradient
+    at the incoming member from its record, and the wall pre-pass the wall
+    cell's)."""
+    if which == "cavity2d":
+        case, steps = uc.cavity2d(n=10, nv=12, kn=0.05, lid=0.4), 15
+    elif which == "sod3d":
+        case, steps = uc.sod3d_tets(n=3, nv=8, jitter=0.15, seed=3), 6
+    elif which == "channel2d":
+        case, steps = uc.channel2d(n=10, nv=12, kn=0.05, u_in=1.2), 12
+    else:
+        case, steps = uc.sphere_mach5(n_ang=2, n_rad=4, nv=10, first=0.3), 6
+    s = Solver(case, limiter=1, limiter_k=k, flags=flags)
+    assert s.info["fused"] == (0 if flags & STAGED else 1)
+    s.close()
+    _compare_step(case, steps, flags=flags, limiter=1, limiter_k=k)
+
+
+def test_limiter_arguments_are_checked():
+    case = uc.cavity2d(n=3, nv=6)
+    for lim, k in ((2, 0.0), (1, -1.0), (1, float("nan"))):
+        with pytest.raises(UGKSError) as e:
+            Solver(case, limiter=lim, limiter_k=k)
+        assert e.value.code == -1 and "limiter" in str(e.value)
+
+
+def test_limited_fp32_form_against_fp64_oracle():
+    """The FP32 form with the limiter (FP32 copy of the limiter record)."""
+    case = uc.cavity2d(n=12, nv=16, kn=0.05, lid=0.4)
+    o = Oracle(case, limiter=1, limiter_k=0.0)
+    s = Solver(case, precision=UGKS_FP32, limiter=1, limiter_k=0.0)
+    o.step(30)
+    s.step(30)
+    err = _normwise(s.W(), o.state(with_h=False)[0])
+    print("limited FP32 form normwise error after 30 steps:", err, flush=True)
+    assert np.all(err < 1e-5)
+    s.close()
