@@ -302,7 +302,7 @@ def run_warm_start(args):
                               ref_out=args.ws_save_ref or None, ref_in=args.ws_ref or None,
                               deep_target=args.ws_deep or None, deep_max_steps=args.ws_max_steps,
                               flags=0 if second else 16, limiter=1 if second else 0,
-                              limiter_k=args.ws_limiter_k)
+                              limiter_k=args.ws_limiter_k, blunt=not args.ws_no_blunt)
     out["metric"] = "time to 1e-6 density residual (s)"
     out["reconstruction"] = (f"second order with Venkatakrishnan's limiter, K = {args.ws_limiter_k}"
                              if second else "first order")
@@ -423,8 +423,10 @@ def main():
                          "with the plain FP64 arm's there (0: off)")
     ap.add_argument("--ws-order", type=int, default=1, choices=(1, 2),
                     help="reconstruction order of every arm (2: with Venkatakrishnan's limiter)")
-    ap.add_argument("--ws-limiter-k", type=float, default=1.0,
+    ap.add_argument("--ws-limiter-k", type=float, default=0.0,
                     help="Venkatakrishnan's K at second order")
+    ap.add_argument("--ws-no-blunt", action="store_true",
+                    help="train without the supersonic cylinder flows")
     ap.add_argument("--ws-start", default="freestream",
                     choices=("freestream", "rest", "potential", "sheltered"),
                     help="initial state of the sphere case")

@@ -192,29 +192,40 @@ def field_errors(W, Wref, dim):
     return out
 
 
-def training_cases(seed: int = 4):
+FIRST_ORDER = dict(flags=16)
+LIMITED = dict(limiter=1, limiter_k=0.0)
+
+
+def training_cases(seed: int = 4, blunt: bool = True):
     """2-D runs in the spirit of the batched workload (cavities and Couette
     flows over a range of Kn) plus channels with far-field inflow at
     sub- to supersonic speeds, so the training set also holds shocks and
-    expansions.  Returns (case, first_order, snapshot steps) triples."""
+    expansions, and (blunt=True) supersonic flows past a circular cylinder
+    at Mach 3 and 5, second order with the limiter, whose bow shocks, shock
+    layers and near wakes are the 2-D counterparts of the sphere's.
+    Returns (case, solver options, snapshot steps) triples."""
     import ugks_cases as uc
     rng = np.random.default_rng(seed)
     out = []
     for kn in (0.01, 0.05, 0.2, 1.0):
-        out.append((uc.cavity2d(n=24, nv=20, kn=kn, lid=float(rng.uniform(0.15, 0.6))), False))
+        out.append((uc.cavity2d(n=24, nv=20, kn=kn, lid=float(rng.uniform(0.15, 0.6))), {}))
     for kn, top in ((0.01, 0.15), (0.1, 0.5), (0.5, 1.0)):
-        out.append((uc.couette2d(n=24, nv=20, kn=kn, top=top), False))
+        out.append((uc.couette2d(n=24, nv=20, kn=kn, top=top), {}))
     for kn, u in ((0.01, 0.3), (0.05, 1.2), (0.01, 2.4), (0.1, 2.4)):
         a = 4.0 + 1.5 * u
-        out.append((uc.channel2d(n=24, nv=20, a=a, kn=kn, u_in=u), True))
-    return [(c, fo, (200, 600, 1500, 3000)) for c, fo in out]
+        out.append((uc.channel2d(n=24, nv=20, a=a, kn=kn, u_in=u), FIRST_ORDER))
+    if blunt:
+        for mach, kn in ((3.0, 0.01), (3.0, 0.05), (5.0, 0.01), (5.0, 0.05)):
+            out.append((uc.cylinder2d(48, 20, nv=24, a=3.0 * mach, kn=kn, mach=mach,
+                                      start="sheltered"), LIMITED))
+    return [(c, o, (200, 600, 1500, 3000)) for c, o in out]
 
 
-def build_training_set(seed: int = 4, copies: int = 3, log=None):
+def build_training_set(seed: int = 4, copies: int = 3, log=None, blunt: bool = True):
     """Snapshots of the training runs (library kernels), rotated copies added."""
     Fs, Ts = [], []
-    for case, first_order, stops in training_cases(seed):
-        s = U.Solver(case, flags=16 if first_order else 0)
+    for case, opts, stops in training_cases(seed, blunt):
+        s = U.Solver(case, **opts)
         done = 0
         for k in stops:
             s.step(k - done)
@@ -233,7 +244,7 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
                      max_steps=60000, chunk=1000, flags=16, train_seed=4, log=None,
                      arms_run=("plain64", "maxwell32", "learned32", "learned64"),
                      ref_out=None, ref_in=None, deep_target=None, deep_max_steps=200000,
-                     limiter=0, limiter_k=0.0):
+                     limiter=0, limiter_k=0.0, blunt=True):
     """Plain FP64 from the initial state against predictor + learned warm start.
 
     Arms (all to a density residual <= target, wall time from creation):
@@ -258,11 +269,12 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
            "limiter": limiter, "limiter_k": limiter_k}
     lim = dict(limiter=limiter, limiter_k=limiter_k)
     t0 = time.perf_counter()
-    F, T = build_training_set(train_seed, log=log)
+    F, T = build_training_set(train_seed, log=log, blunt=blunt)
     t1 = time.perf_counter()
     net, losses = train(F, T, seed=train_seed, steps=4000, batch=1024)
     t2 = time.perf_counter()
-    out["training"] = {"samples": int(len(F)), "snapshot_s": t1 - t0, "train_s": t2 - t1,
+    out["training"] = {"samples": int(len(F)), "blunt_body_flows": bool(blunt),
+                       "snapshot_s": t1 - t0, "train_s": t2 - t1,
                        "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
     arms = {}
 

@@ -94,3 +94,28 @@ def test_locally_refined_velocity_set():
     fine = v.w == v.w.min()
     assert np.all(np.max(np.abs(v.u[fine] - [1.5, 0.0, 0.0]), axis=1) < 0.7 + 0.125)
     assert len({tuple(p) for p in v.u}) == v.nv
+
+
+def test_cylinder_ogrid_and_its_starts():
+    m = uc.cylinder_ogrid(32, 10, first=0.05)
+    m.validate()
+    assert m.n_cells == 320
+    # straight-edged quads: the area is the polygonal annulus, a little under the circles'
+    n = 32
+    poly = lambda r: 0.5 * n * r * r * math.sin(2 * math.pi / n)  # noqa: E731
+    assert m.cell_volume.sum() == pytest.approx(poly(6.0) - poly(1.0), rel=1e-12)
+    assert (m.face_bc == uc.BC_WALL).sum() == 32 and (m.face_bc == uc.BC_FARFIELD).sum() == 32
+    r = np.linalg.norm(m.cell_centroid, axis=1)
+    assert 1.0 < r.min() < 1.05 and r.max() < 6.0
+    c = uc.cylinder2d(32, 10, nv=8, start="potential")
+    U = c.W0[:, 1:3] / c.W0[:, :1]
+    x, y = m.cell_centroid[:, 0], m.cell_centroid[:, 1]
+    # potential flow: no flux through circles about the origin far from... the radial
+    # velocity U cos(t)(1 - 1/r^2) and the speed never above 2 U
+    ur = (U[:, 0] * x + U[:, 1] * y) / r
+    np.testing.assert_allclose(ur, c.meta["u_inf"] * (x / r) * (1 - r ** -2), atol=1e-12)
+    assert np.sqrt((U * U).sum(1)).max() <= 2 * c.meta["u_inf"]
+    s = uc.cylinder2d(32, 10, nv=8, start="sheltered")
+    Us = s.W0[:, 1:3] / s.W0[:, :1]
+    np.testing.assert_allclose(Us[:, 1], 0.0)
+    np.testing.assert_allclose(Us[:, 0], s.meta["u_inf"] * (1 - np.exp(-(r - 1) ** 2)), rtol=1e-12)

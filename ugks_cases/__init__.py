@@ -14,11 +14,11 @@ lambda0 = 1/(2 R T0) = 1.  Hard-sphere viscosity mu = mu_ref (T/T0)^0.5 with
 mu_ref = (5 sqrt(pi) / 16) Kn.
 """
 
-from .meshes import Mesh, quad_mesh, kuhn_tet_cube, cubed_sphere_shell, hex_box  # noqa: F401
+from .meshes import Mesh, quad_mesh, kuhn_tet_cube, cubed_sphere_shell, hex_box, cylinder_ogrid  # noqa: F401
 from .velocity import (Velocity, midpoint_grid, gauss_hermite_grid, stretched_grid,  # noqa: F401
                        locally_refined_grid)
 from .configs import (  # noqa: F401
     Gas, BC, Case, BC_INTERIOR, BC_WALL, BC_FARFIELD, BC_OUTFLOW,
     hard_sphere_mu_ref, cavity2d, couette2d, sod3d_tets, batch_cases,
-    sphere_mach5, channel2d, make_case, uniform_W, maxwellian_box_case,
+    sphere_mach5, channel2d, make_case, uniform_W, maxwellian_box_case, cylinder2d,
 )

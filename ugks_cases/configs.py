@@ -14,7 +14,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .meshes import (BC_FARFIELD, BC_INTERIOR, BC_OUTFLOW, BC_WALL, Mesh,  # noqa: F401
-                     cubed_sphere_shell, kuhn_tet_cube, quad_mesh)
+                     cubed_sphere_shell, cylinder_ogrid, kuhn_tet_cube, quad_mesh)
 from .velocity import Velocity, midpoint_grid
 
 R_GAS = 0.5      # speed unit sqrt(2 R T0) with T0 = 1
@@ -199,6 +199,41 @@ def sphere_mach5(n_ang: int = 8, n_rad: int = 22, nv: int = 28, a: float = 11.0,
     else:
         raise ValueError(f"unknown start {start!r}")
     return Case(f"sphere_m{mach}_kn{kn}", mesh, vel, gas, bcs, W0, 0,
+                {"kn": kn, "u_inf": u_inf})
+
+
+def cylinder2d(n_theta: int = 64, n_r: int = 24, nv: int = 28, a: float = 11.0,
+               kn: float = 0.01, mach: float = 5.0, first: float = 0.05,
+               start: str = "potential") -> Case:
+    """Supersonic flow along +x past a circular cylinder of radius 1 (2-D),
+    far field at r = 6, isothermal wall at T_w = 1; the 2-D counterpart of the
+    sphere case.  Free stream rho = 1, T = 1, U = mach sqrt(5/6) (the
+    monatomic speed of sound, as for the sphere).  start="potential" begins
+    from incompressible potential flow past the cylinder (U (1 - (x^2 - y^2)/r^4),
+    -2 U x y / r^4) at the free-stream rho and T; "freestream" from the free
+    stream everywhere; "sheltered" from the free stream brought smoothly to
+    rest toward the cylinder, U (1 - exp(-(r - 1)^2)) along x."""
+    mesh = cylinder_ogrid(n_theta, n_r, first=first)
+    vel = midpoint_grid(nv, a, 2)
+    u_inf = mach * math.sqrt(5.0 / 3.0 * R_GAS * 1.0)
+    bcs = [BC(BC_WALL, 1.0, (0.0, 0.0, 0.0), 1.0), BC(BC_FARFIELD, 1.0, (u_inf, 0.0, 0.0), 1.0)]
+    gas = Gas(mu_ref=hard_sphere_mu_ref(kn), cfl=0.8)
+    if start == "freestream":
+        W0 = uniform_W(mesh.n_cells, 2, 1.0, (u_inf, 0.0), 1.0)
+    elif start == "potential":
+        x, y = mesh.cell_centroid[:, 0], mesh.cell_centroid[:, 1]
+        r2 = np.maximum(x * x + y * y, 1.0)
+        U = np.stack([u_inf * (1.0 - (x * x - y * y) / r2 ** 2), -u_inf * 2.0 * x * y / r2 ** 2], axis=1)
+        W0 = uniform_W(mesh.n_cells, 2, 1.0, U, 1.0)
+    elif start == "sheltered":
+        # the free stream, brought smoothly to rest toward the cylinder
+        r = np.linalg.norm(mesh.cell_centroid, axis=1)
+        U = np.zeros((mesh.n_cells, 2))
+        U[:, 0] = u_inf * (1.0 - np.exp(-(np.maximum(r, 1.0) - 1.0) ** 2))
+        W0 = uniform_W(mesh.n_cells, 2, 1.0, U, 1.0)
+    else:
+        raise ValueError(f"unknown start {start!r}")
+    return Case(f"cylinder_m{mach}_kn{kn}", mesh, vel, gas, bcs, W0, 0,
                 {"kn": kn, "u_inf": u_inf})
 
 

@@ -241,6 +241,80 @@ def hex_box(nx: int, ny: int | None = None, nz: int | None = None, *, grading: f
     return m
 
 
+def cylinder_ogrid(n_theta: int = 64, n_r: int = 24, *, r0: float = 1.0, r1: float = 6.0,
+                   first: float = 0.05, name: str = "") -> Mesh:
+    """2-D O-grid of quadrilaterals around a circular cylinder of radius r0.
+
+    Nodes sit at (r_j cos t_i, r_j sin t_i) with n_theta equal angles and
+    n_r radial layers whose thickness grows geometrically from ``first`` so
+    the layers end at r1; cells are the straight-edged quads between them.
+    The ring closes on itself (cells of angle n_theta-1 and 0 share an
+    ordinary interior face).  Boundary tags: row 0 for the wall at r0, row 1
+    for the far field at r1.  Cell (i, j) has index i + n_theta j.
+    """
+    # growth ratio q with first * (q^n - 1)/(q - 1) = r1 - r0
+    lo, hi = 1.0 + 1e-12, 2.0
+    for _ in range(200):
+        q = 0.5 * (lo + hi)
+        tot = first * (q ** n_r - 1.0) / (q - 1.0)
+        lo, hi = (q, hi) if tot < r1 - r0 else (lo, q)
+    q = 0.5 * (lo + hi)
+    rad = np.concatenate([[r0], r0 + first * (q ** np.arange(1, n_r + 1) - 1.0) / (q - 1.0)])
+    rad[-1] = r1
+    th = 2.0 * np.pi * np.arange(n_theta) / n_theta
+    P = np.stack([np.outer(rad, np.cos(th)), np.outer(rad, np.sin(th))], axis=-1)  # [j, i, 2]
+    cid = lambda i, j: (i % n_theta) + n_theta * j  # noqa: E731
+    nc = n_theta * n_r
+    vol = np.zeros(nc)
+    cen = np.zeros((nc, 2))
+    for j in range(n_r):
+        for i in range(n_theta):
+            poly = [P[j, i], P[j + 1, i], P[j + 1, (i + 1) % n_theta], P[j, (i + 1) % n_theta]]
+            a = 0.0
+            cx = cy = 0.0
+            for k in range(4):
+                x0, y0 = poly[k]
+                x1, y1 = poly[(k + 1) % 4]
+                cr = x0 * y1 - x1 * y0
+                a += cr
+                cx += (x0 + x1) * cr
+                cy += (y0 + y1) * cr
+            a *= 0.5
+            vol[cid(i, j)] = a
+            cen[cid(i, j)] = (cx / (6.0 * a), cy / (6.0 * a))
+    fc, fa, fn, fx, fb, fi = [], [], [], [], [], []
+
+    def add(L, R, p, q_, bc, bid):
+        e = q_ - p
+        length = float(np.hypot(e[0], e[1]))
+        n = np.array([e[1], -e[0]]) / length  # right-hand normal of p -> q
+        x = 0.5 * (p + q_)
+        ref = cen[R] if R >= 0 else x
+        if np.dot(ref - cen[L], n) < 0:
+            n = -n
+        fc.append((L, R)); fa.append(length); fn.append(n); fx.append(x); fb.append(bc); fi.append(bid)
+
+    for j in range(n_r):          # radial edges between angular neighbours
+        for i in range(n_theta):
+            add(cid(i, j), cid(i + 1, j), P[j, (i + 1) % n_theta], P[j + 1, (i + 1) % n_theta],
+                BC_INTERIOR, -1)
+    for j in range(n_r + 1):      # rings
+        for i in range(n_theta):
+            p, q_ = P[j, i], P[j, (i + 1) % n_theta]
+            if j == 0:
+                add(cid(i, 0), -1, p, q_, BC_WALL, 0)
+            elif j == n_r:
+                add(cid(i, n_r - 1), -1, p, q_, BC_FARFIELD, 1)
+            else:
+                add(cid(i, j - 1), cid(i, j), p, q_, BC_INTERIOR, -1)
+    m = Mesh(2, vol, cen, np.array(fc), np.array(fa), np.array(fn), np.array(fx),
+             np.zeros((len(fa), 2)), np.array(fb), np.array(fi),
+             name=name or f"cyl{n_theta}x{n_r}_f{first}")
+    m = m.contiguous()
+    m.validate()
+    return m
+
+
 def _tri_geometry(a, b, c):
     cr = np.cross(b - a, c - a)
     area2 = np.linalg.norm(cr, axis=1)
