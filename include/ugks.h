@@ -147,6 +147,7 @@ typedef struct {
  *                     (Sec. 2.2 steps 4 and 5) is zero, so each face sees the
  *                     piecewise-constant states of its two cells; robust where
  *                     unlimited second-order slopes overshoot (strong shocks).
+ *              bit 6: track the boundary flux (ugks_boundary_flux).
  *              bit 5: replay each step from a HIP graph of its kernels
  *                     (captured at the first step that can use it; not on the
  *                     null stream, nor while profiling).  Same results as
@@ -236,6 +237,22 @@ int ugks_step(ugks_ctx* ctx, int32_t n_steps, double* residual_out);
  *   out_on_device 0: host pointer; 1: device pointer
  */
 int ugks_moments(ugks_ctx* ctx, int32_t which, double* out, int32_t out_on_device);
+
+/*
+ * ugks_boundary_flux - the boundary flux accumulated over the steps since
+ * create (or the last ugks_set_state), for balance checks (Eq. macro_update
+ * summed over the cells: sum_i V_i W_i^n - sum_i V_i W_i^0 + A = 0 up to
+ * rounding, A = sum over steps and boundary faces of S_f F_f, F_f the face's
+ * time-integrated flux of mass, momentum and energy, Eq. macro_flux).
+ * Needs options.flags bit 6 (boundary-flux tracking) at create: the wall
+ * pass then also keeps each wall face's flux (fused sweep) or the staged
+ * sweep's face fluxes are summed, one small reduction per step.
+ * out: host, dim+2 doubles, written.  complete: optional host int32, set to
+ * 1 if A covers every boundary face, 0 on the fused sweep with far-field or
+ * outflow faces (there only the wall faces are summed).
+ * Errors: UGKS_EINVAL (null context or out, tracking off), UGKS_EHIP.
+ */
+int ugks_boundary_flux(ugks_ctx* ctx, double* out, int32_t* complete);
 
 /*
  * ugks_get_state / ugks_set_state - checkpoint, restart and warm start.

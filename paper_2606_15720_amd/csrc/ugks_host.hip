@@ -15,6 +15,7 @@
 #include <exception>
 #include <fstream>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <sstream>
@@ -104,6 +105,19 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   // rows are padded to whole waves; the velocity block of the sweep is a
   // scheduling unit and needs no padding
   c->nvp = (nv + WAVE - 1) / WAVE * WAVE;
+  {
+    // a point whose mirror -u_k is not in the set is paired with a pad slot
+    // on the fused sweep: keep at least one
+    std::set<std::vector<double>> pts;
+    for (int64_t k = 0; k < nv; ++k) pts.insert(std::vector<double>(vel->u + k * D, vel->u + (k + 1) * D));
+    bool all_mirrored = true;
+    for (int64_t k = 0; k < nv && all_mirrored; ++k) {
+      std::vector<double> m(D);
+      for (int d = 0; d < D; ++d) m[d] = -vel->u[k * D + d];
+      all_mirrored = pts.count(m) > 0;
+    }
+    if (!all_mirrored && c->nvp == nv) c->nvp += WAVE;
+  }
 
   // ---- mesh validation and cell -> face tables --------------------------
   for (int64_t i = 0; i < nc; ++i)
@@ -279,14 +293,33 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
         r /= na;
       }
     }
-    for (int64_t f = 0; ok && f < nf; ++f)
-      ok = mesh->face_bc[f] >= UGKS_BC_INTERIOR && mesh->face_bc[f] <= UGKS_BC_OUTFLOW;
-    for (int64_t i = 0; ok && i < nc; ++i) ok = nfc[i] <= 4;
-    c->fused = ok;
+    bool mesh_ok = !(c->flags & 2);
+    for (int64_t f = 0; mesh_ok && f < nf; ++f)
+      mesh_ok = mesh->face_bc[f] >= UGKS_BC_INTERIOR && mesh->face_bc[f] <= UGKS_BC_OUTFLOW;
+    for (int64_t i = 0; mesh_ok && i < nc; ++i) mesh_ok = nfc[i] <= 4;
+    ok = ok && mesh_ok;
     if (ok) {
       ax = a0;
       c->fmesh.na = (int)na;
+    } else if (mesh_ok) {
+      // Sparse tensor set: every coordinate of every point is a node of one
+      // 1-D set A = -A of at most 64 nodes (a locally refined set whose levels
+      // are lattices is one), so the Maxwellians still factor over the axes.
+      std::vector<double> aa;
+      for (int64_t k = 0; k < nv * D; ++k) {
+        aa.push_back(vel->u[k]);
+        aa.push_back(-vel->u[k]);
+      }
+      std::sort(aa.begin(), aa.end());
+      aa.erase(std::unique(aa.begin(), aa.end()), aa.end());
+      if ((int64_t)aa.size() <= 64) {
+        ax = aa;
+        c->fmesh.na = (int)aa.size();
+        c->fmesh.sparse = true;
+        ok = true;
+      }
     }
+    c->fused = ok;
   }
   // ---- initial state check ---------------------------------------------
   for (int64_t i = 0; i < nc; ++i) {
@@ -450,14 +483,52 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     }
     std::vector<int32_t> vidx(nv);
     const int64_t na = c->fmesh.na;
-    for (int64_t k = 0; k < nv; ++k) {
-      int64_t r = k;
-      int32_t packed = 0;
-      for (int d = D - 1; d >= 0; --d) {
-        packed |= (int32_t)(r % na) << (8 * d);
-        r /= na;
+    if (!c->fmesh.sparse) {
+      for (int64_t k = 0; k < nv; ++k) {
+        int64_t r = k;
+        int32_t packed = 0;
+        for (int d = D - 1; d >= 0; --d) {
+          packed |= (int32_t)(r % na) << (8 * d);
+          r /= na;
+        }
+        vidx[k] = packed;
       }
-      vidx[k] = packed;
+      c->fmesh.npairs = (nv + 1) / 2;
+    } else {
+      // node indices of every coordinate, then mirror pairs: point k with the
+      // point at the mirrored indices, itself (u = 0), or a pad slot whose
+      // weight is 0 and which is never stored (a "phantom" partner)
+      std::map<std::vector<int32_t>, int64_t> at;
+      std::vector<std::vector<int32_t>> ids(nv, std::vector<int32_t>(D));
+      for (int64_t k = 0; k < nv; ++k) {
+        int32_t packed = 0;
+        for (int d = 0; d < D; ++d) {
+          const double x = vel->u[k * D + d];
+          const int32_t n = (int32_t)(std::lower_bound(ax.begin(), ax.end(), x) - ax.begin());
+          ids[k][d] = n;
+          packed |= n << (8 * d);
+        }
+        vidx[k] = packed;
+        at[ids[k]] = k;
+      }
+      std::vector<int32_t> pairs, pvidx;
+      std::vector<char> done(nv, 0);
+      for (int64_t k = 0; k < nv; ++k) {
+        if (done[k]) continue;
+        std::vector<int32_t> m(D);
+        for (int d = 0; d < D; ++d) m[d] = (int32_t)na - 1 - ids[k][d];
+        auto it = at.find(m);
+        int64_t k1 = (int64_t)nv;  // pad slot
+        if (it != at.end() && !done[it->second]) k1 = it->second;
+        done[k] = 1;
+        if (k1 < nv) done[k1] = 1;
+        pairs.push_back((int32_t)k);
+        pairs.push_back((int32_t)k1);
+        pvidx.push_back(vidx[k]);
+      }
+      c->fmesh.npairs = (int64_t)pvidx.size();
+      c->fmesh.pairs = upload(c, pairs);
+      c->fmesh.pvidx = upload(c, pvidx);
     }
     c->fmesh.nc = nc;
     c->fmesh.nv = nv;
@@ -523,7 +594,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   B.F = dalloc<double>(c, nf * 5);
   if (c->fused) {
     // velocity block: B_v velocities = B_v/2 mirror pairs per work item
-    const int64_t npairs = (nv + 1) / 2;
+    const int64_t npairs = c->fmesh.npairs;
     int64_t cp = Bv ? Bv / 2 : 2048;
     cp = std::max<int64_t>(64, std::min<int64_t>(cp, npairs));
     c->sched.nf = nf;
@@ -562,8 +633,10 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   B.resid = dalloc<double>(c, 8);
   B.cellred = dalloc<double>(c, nc * 3);
   B.flag = dalloc<int32_t>(c, 4);
+  B.bflux = dalloc<double>(c, 5);
   HIP_TRY(hipMemsetAsync(B.frec, 0, nf * FREC * sizeof(double), c->stream));
   HIP_TRY(hipMemsetAsync(B.resid, 0, 8 * sizeof(double), c->stream));
+  HIP_TRY(hipMemsetAsync(B.bflux, 0, 5 * sizeof(double), c->stream));
   HIP_TRY(hipMemsetAsync(B.flag, 0, 4 * sizeof(int32_t), c->stream));
   HIP_TRY(hipMemsetAsync(B.q, 0, nc * 3 * sizeof(double), c->stream));
   std::vector<double> W0p(nc * NW);
@@ -673,7 +746,11 @@ void enqueue_step_fused(ugks_ctx* c) {
   // the wall densities
   if (c->fmesh.nff)
     TIMED(KK_WALL, launch_ghost_rows(D, P, c->fmesh, v, B.frec, B.h, B.b, B.flag, s));
-  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, c->fmesh, g, B.h, B.frec, B.flag, s));
+  // (with boundary-flux tracking the wall pass also keeps each wall face's flux)
+  const bool track = (c->flags & 64) != 0;
+  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, c->fmesh, g, B.h, B.frec, B.flag, s,
+                                        track ? (D == 2 ? B.b : B.h) : nullptr));
+  if (track) TIMED(KK_RESID, launch_bflux(D, m, B.frec, B.F, 0, B.bflux, B.flag, s));
   // Maxwellian axis tables of every face and cell of this step
   TIMED(KK_TABLES, launch_tables(D, m, c->fmesh, g, B.frec, B.prim, B.cs, B.tabs, B.flag, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep
@@ -724,6 +801,7 @@ void enqueue_step(ugks_ctx* c) {
   // 6.7-6.8 microscopic fluxes and their moments
   TIMED(KK_FLUX, launch_flux(D, P, m, v, g, B.frec, B.h, B.b, B.gradh, B.gradb, B.fluxh, B.fluxb,
                               B.F, B.flag, s));
+  if (c->flags & 64) TIMED(KK_RESID, launch_bflux(D, m, B.frec, B.F, 1, B.bflux, B.flag, s));
   // 9 first stage
   TIMED(KK_STAGE1, launch_stage1(D, P, m, v, g, B.prim, B.q, B.h, B.b, B.fluxh, B.fluxb, B.ht,
                                 B.bt, B.flag, s));
@@ -950,7 +1028,7 @@ double time_sweep(ugks_batch* b, const std::vector<int32_t>& items, int32_t** bu
 }
 
 void apply_sched(ugks_ctx* c, int64_t chunk_pairs, int64_t tile) {
-  const int64_t npairs = (c->nv + 1) / 2;
+  const int64_t npairs = c->fmesh.npairs;
   // at least 64 pairs (or all): the per-block moment buffer was sized for that
   chunk_pairs = std::max(std::min<int64_t>(64, npairs), std::min(chunk_pairs, npairs));
   c->sched.chunk_pairs = chunk_pairs;
@@ -993,7 +1071,7 @@ void autotune(ugks_batch* b) {
         }
       }
       if (!hit) {
-        const int64_t npairs = (c->nv + 1) / 2;
+        const int64_t npairs = c->fmesh.npairs;
         tc.us = INFINITY;
         int64_t last_cp = -1;
         for (int mult : {1, 2, 4, 8, 1 << 20}) {
@@ -1097,11 +1175,11 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
       b->nr = cc->nr;
     }
     fail_if(cc->D != b->D, "case " + std::to_string(i) + ": every case needs the same dimension");
-    if (!cc->fused)
+    if (!cc->fused || cc->fmesh.sparse)
       throw std::pair<int, std::string>(
           UGKS_EUNSUPPORTED, "case " + std::to_string(i) +
-                                 ": the batched form needs the fused sweep (symmetric tensor "
-                                 "velocity set, at most 4 faces per cell)");
+                                 ": the batched form needs the fused sweep over a full tensor "
+                                 "product velocity set (symmetric nodes, at most 4 faces per cell)");
     // flags and residuals of all cases side by side: one copy reads them all
     cc->buf.flag = b->flags_dev + 4 * i;
     cc->buf.resid = b->resid_dev + 8 * i;
@@ -1323,6 +1401,23 @@ int ugks_moments(ugks_ctx* c, int32_t which, double* out, int32_t on_device) {
   return UGKS_OK;
 }
 
+
+int ugks_boundary_flux(ugks_ctx* c, double* out, int32_t* complete) {
+  if (!c || !out) return set_err(c, UGKS_EINVAL, "null argument");
+  if (!(c->flags & 64))
+    return set_err(c, UGKS_EINVAL, "boundary-flux tracking is off (options.flags bit 6)");
+  try {
+    double acc[5];
+    HIP_TRY(hipMemcpyAsync(acc, c->buf.bflux, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int x = 0; x < c->D + 2; ++x) out[x] = acc[x];
+    if (complete) *complete = (!c->fused || c->fmesh.nff == 0) ? 1 : 0;
+  } catch (const HipFail& e) {
+    return set_err(c, UGKS_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } UGKS_CATCH_REST(set_err, c)
+  return UGKS_OK;
+}
+
 int ugks_get_state(ugks_ctx* c, double* W, double* h, double* b) {
   if (!c) return set_err(nullptr, UGKS_EINVAL, "ctx is NULL");
   try {
@@ -1385,7 +1480,9 @@ int ugks_set_state(ugks_ctx* c, const double* W, const double* h, const double* 
         HIP_TRY(hipMemcpy(dst[r], tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
       }
     }
-    // a new state restarts the residual normalisation and clears a failure
+    // a new state restarts the residual normalisation and the boundary-flux
+    // sum, and clears a failure
+    HIP_TRY(hipMemset(c->buf.bflux, 0, 5 * sizeof(double)));
     c->q_valid = false;
     HIP_TRY(hipMemset(c->buf.resid, 0, 8 * sizeof(double)));
     HIP_TRY(hipMemset(c->buf.flag, 0, 4 * sizeof(int32_t)));

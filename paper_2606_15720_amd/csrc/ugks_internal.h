@@ -35,6 +35,7 @@ enum FaceRec : int {
   FR_GC = 40,    // ghost: rho_g (lambda_g/pi)^(D/2)
   FR_PH = 48,    // cubic polynomial PH(u) of the h-equation equilibrium terms (20)
   FR_PB = 68,    // cubic polynomial PB(u) of the b-equation equilibrium terms (20, 2-D)
+  FR_BF = 88,    // wall: the step's flux of mass, momentum, energy (boundary-flux tracking)
 };
 
 struct DevMesh {
@@ -95,6 +96,10 @@ struct FusedMesh {
   const int32_t* crec_i;    // [nc*CRI]
   const double* crec_d;     // [nc*CRD]
   const float* crec_d32;    // [nc*CRD] FP32 copy (FP32 compute form), else null
+  bool sparse = false;      // points on the tensor product of `axis`, not all of it
+  int64_t npairs = 0;       // mirror pairs of the sweep
+  const int32_t* pairs = nullptr;  // sparse: [2*npairs] (k, mirror of k, or the pad slot nv)
+  const int32_t* pvidx = nullptr;  // sparse: [npairs] packed axis indices of each pair's first point
   const double* crec_l = nullptr;  // [nc*CRL] limiter record, null without the limiter
   const float* crec_l32 = nullptr; // its FP32 copy (FP32 compute form)
   const int32_t* ffaces;    // [nff] far-field / outflow faces; face m owns ghost row nc+1+m
@@ -153,6 +158,7 @@ struct StepBuffers {
   double* fluxh;   // [nf*nvp] time-integrated microscopic fluxes (staged sweep)
   double* fluxb;
   double* resid;   // [8] residual accumulators and state
+  double* bflux;   // [5] running boundary flux (with boundary-flux tracking)
   double* cellred; // [nc*3] per-cell residual contributions
   int32_t* flag;   // numeric error flag
 };
@@ -244,7 +250,9 @@ hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v
                            void* h, void* b, double* qn, const int32_t* flag, hipStream_t s);
 hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
                                   const FusedMesh& fm, const GasP& g, const void* h, double* frec,
-                                  const int32_t* flag, hipStream_t s);
+                                  const int32_t* flag, hipStream_t s, const void* b_bf = nullptr);
+hipError_t launch_bflux(int D, const DevMesh& m, const double* frec, const double* F, int staged,
+                        double* acc, const int32_t* flag, hipStream_t s);
 hipError_t launch_ghost_rows(int D, int prec, const FusedMesh& fm, const DevVel& v,
                              const double* frec, void* h, void* b, const int32_t* flag,
                              hipStream_t s);

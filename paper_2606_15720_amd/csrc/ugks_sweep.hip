@@ -209,7 +209,7 @@ struct SweepLds {
 // Every read-only array is its own __restrict__ argument so that the
 // compiler can prove no store of the sweep clobbers it and serve the
 // wave-uniform reads from the scalar cache.
-template <int D, typename T, typename C, bool SPLIT, bool LIM = false>
+template <int D, typename T, typename C, bool SPLIT, bool LIM = false, bool SPARSE = false>
 __device__ __forceinline__ void sweep_item(
     const FusedMesh& fm, int64_t nvp, const SweepSched& sc, const int32_t* __restrict__ crec_i,
     const C* __restrict__ crec_d, const C* __restrict__ crec_l, const int32_t* __restrict__ vidx,
@@ -255,7 +255,7 @@ __device__ __forceinline__ void sweep_item(
   }
   constexpr int NM = D + 2;
   const unsigned nv = (unsigned)fm.nv;
-  const unsigned npairs = (nv + 1) / 2;
+  const unsigned npairs = (unsigned)fm.npairs;
   const unsigned kbeg = (unsigned)(chunk * sc.chunk_pairs);
   const unsigned kend = (unsigned)min((int64_t)npairs, (chunk + 1) * sc.chunk_pairs);
   // Row r of h (or b) starts r * rowb bytes in.  Row indices are 32-bit and
@@ -528,7 +528,15 @@ __device__ __forceinline__ void sweep_item(
         crec_i_t* ci = ci0 + z;
         crec_t<C>* cd = cd0 + z;
         crec_t<C>* cc = cc0 + z;
-        const unsigned k0 = kp, k1 = nv - 1 - kp;
+        // a pair's two points: k and its mirror; a sparse set lists them
+        // (a point without a mirror in the set has the pad slot nv as a
+        // partner: weight 0, never stored)
+        unsigned k0 = kp, k1 = nv - 1 - kp;
+        if constexpr (SPARSE) {
+          k0 = (unsigned)fm.pairs[2 * kp];
+          k1 = (unsigned)fm.pairs[2 * kp + 1];
+        }
+        const bool has1 = k1 != k0 && (!SPARSE || k1 < nv);
         const int pk = pk_next;
         pk_next = vidx[min(kp + nthr, kend - 1)];
         int id[3], im[3];
@@ -688,7 +696,7 @@ __device__ __forceinline__ void sweep_item(
         }
         // moments of the net outflow (the zero velocity of an odd grid once)
         {
-          const double a0 = w[k0] * (double)acc0, a1 = (k1 != k0) ? w[k1] * (double)acc1 : 0.0;
+          const double a0 = w[k0] * (double)acc0, a1 = has1 ? w[k1] * (double)acc1 : 0.0;
           if constexpr (X == 0) {
             mw[0] += a0 + a1;
 #pragma unroll
@@ -714,7 +722,7 @@ __device__ __forceinline__ void sweep_item(
         cubic_eo<D>(cc + (X ? CS_SB : CS_SH), vv, v2, E, O);
         const C ccoll = cc[CS_CC];
         st(fto, k0, f0 - acc0 + ccoll * (c0 * (C(1) + E + O) - f0));
-        if (k1 != k0) st(fto, k1, f1 - acc1 + ccoll * (c1 * (C(1) + E - O) - f1));
+        if (has1) st(fto, k1, f1 - acc1 + ccoll * (c1 * (C(1) + E - O) - f1));
       }
     };
     pass(std::integral_constant<int, 0>{});
@@ -730,7 +738,7 @@ __device__ __forceinline__ void sweep_item(
 // FP32 copies of the records and tables; moment sums stay FP64).  The FP32
 // body fits in half the registers; its bound asks for the occupancy that
 // hides the gathers' latency (measured: 7 waves per SIMD, no spills).
-template <int D, typename T, bool LIM>
+template <int D, typename T, bool LIM, bool SPARSE>
 __global__ __launch_bounds__(SWT, (sizeof(T) == 4 ? 6 : 4)) void k_sweep(
     FusedMesh fm, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
     const T* __restrict__ crec_d, const T* __restrict__ crec_l, const int32_t* __restrict__ vidx,
@@ -751,8 +759,8 @@ __global__ __launch_bounds__(SWT, (sizeof(T) == 4 ? 6 : 4)) void k_sweep(
   const int64_t chunk = rem / sc.tile;
   const int64_t ic = tile * sc.tile + rem % sc.tile;
   if (ic >= fm.nc) return;
-  sweep_item<D, T, T, true, LIM>(fm, nvp, sc, crec_i, crec_d, crec_l, vidx, w, cs, frec, tabs, h, b,
-                                 ht, bt, dWp, flag, ic, chunk, L);
+  sweep_item<D, T, T, true, LIM, SPARSE>(fm, nvp, sc, crec_i, crec_d, crec_l, vidx, w, cs, frec, tabs,
+                                         h, b, ht, bt, dWp, flag, ic, chunk, L);
 }
 
 // The fused sweep over a batch of cases: a persistent grid walks a list of
@@ -781,6 +789,7 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 3)) void k_sweep_b(BatchDev bd) 
     fm.na = cases[c].fm.na;
     fm.axis = cases[c].fm.axis;
     fm.vidx = cases[c].fm.vidx;
+    fm.npairs = cases[c].fm.npairs;
     fm.crec_i = cases[c].fm.crec_i;
     fm.crec_d = cases[c].fm.crec_d;
     SweepSched sc;
@@ -955,17 +964,19 @@ struct WallLds {
   double ax[NAX];
   double wx[3][NAX];  // axis factors of the wall Maxwellian, C_w folded into the first
   double red[2 * 16];
+  double red2[5 * 16];
 };
 
 // Wall density of one wall face: the incident free transport of the wall
 // cell (its gradient evaluated in place) against the re-emitted wall
 // Maxwellian, whose value at a tensor point is a product of three LDS
 // axis factors (no per-velocity exp).
-template <int D, typename T, bool LIM = false>
+template <int D, typename T, bool LIM = false, bool BF = false>
 __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const DevVel& v,
                                             const FusedMesh& fm, const GasP& g,
                                             const T* __restrict__ h, double* __restrict__ frec,
-                                            const int32_t* flag, WallLds& S) {
+                                            const int32_t* flag, WallLds& S,
+                                            const T* __restrict__ b = nullptr) {
   if (*flag) return;
   const int f = m.walls[wi];
   const int64_t L = m.fL[f];
@@ -996,6 +1007,11 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
 #pragma unroll
   for (int s = 0; s < 4; ++s) hs_row[s] = h + (int64_t)ci[2 + s] * nvp;
   double acc[2] = {0.0, 0.0};
+  // with BF: the wall flux's moments, incident (time-integrated free transport
+  // of the wall cell's h, and b in 2-D) and reflected (per unit rho_w dt)
+  double bfi[D + 2], bfr[D + 2];
+#pragma unroll
+  for (int x = 0; x < D + 2; ++x) bfi[x] = bfr[x] = 0.0;
   // Four velocities per lane per pass: their axis indices are loaded one
   // pass ahead, and the rows of the incident ones (u.n > 0, the only ones
   // that read f) are loaded together before any arithmetic.
@@ -1077,16 +1093,85 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
           ugh += uu[u][d] * gr[d];
         }
         acc[0] += wk[u] * un[u] * (dt * hf - 0.5 * dt * dt * ugh);
+        if constexpr (BF) {
+          const double fh = wk[u] * un[u] * (dt * hf - 0.5 * dt * dt * ugh);
+          double u2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            bfi[1 + d] += uu[u][d] * fh;
+            u2 += uu[u][d] * uu[u][d];
+          }
+          bfi[0] += fh;
+          bfi[D + 1] += 0.5 * u2 * fh;
+          if constexpr (D == 2) {
+            // the b part of the energy: the same free transport of the wall cell's b
+            const unsigned kk = k0 + u * nb;
+            const T* __restrict__ bl_row = b + L * nvp;
+            const double bl = ld(bl_row, kk);
+            double gb[3] = {0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const double db = ld(b + (int64_t)ci[2 + s] * nvp, kk) - bl;
+#pragma unroll
+              for (int d = 0; d < D; ++d) gb[d] += cd[d * 4 + s] * db;
+            }
+            if constexpr (LIM) {
+              crec_t<double>* cl = (crec_t<double>*)(fm.crec_l + L * CRL);
+              double lo = bl, hi = bl;
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                const double vs = cl[1 + s] * bl + ld(b + (int64_t)ci[2 + s] * nvp, kk);
+                lo = fmin(lo, vs);
+                hi = fmax(hi, vs);
+              }
+              const double pb = venkat_phi<D>(bl, lo, hi, gb, cd + CRD_F0 + 4, CRD_FS, cl[0]);
+#pragma unroll
+              for (int d = 0; d < D; ++d) gb[d] *= pb;
+            }
+            double bf = bl, ugb = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              bf += dxl[d] * gb[d];
+              ugb += uu[u][d] * gb[d];
+            }
+            bfi[D + 1] += 0.5 * wk[u] * un[u] * (dt * bf - 0.5 * dt * dt * ugb);
+          }
+        }
       } else if (out[u]) {
         double M = S.wx[0][id[u][0]];
 #pragma unroll
         for (int d = 1; d < D; ++d) M *= S.wx[d][id[u][d]];
         acc[1] += wk[u] * un[u] * M;
+        if constexpr (BF) {
+          const double fm_ = wk[u] * un[u] * M;
+          double u2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            bfr[1 + d] += uu[u][d] * fm_;
+            u2 += uu[u][d] * uu[u][d];
+          }
+          bfr[0] += fm_;
+          // 2-D: the re-emitted b = K_xi/(2 lambda_w) H_w adds to the energy
+          bfr[D + 1] += 0.5 * (u2 + (D == 2 ? 1.0 / (2.0 * lamw) : 0.0)) * fm_;
+        }
       }
     }
   }
   block_sum<2>(acc, S.red);
-  if (threadIdx.x == 0) R[FR_RHOW] = -acc[0] / (dt * acc[1]);
+  if constexpr (BF) {
+    __syncthreads();
+    block_sum<D + 2>(bfi, S.red2);
+    __syncthreads();
+    block_sum<D + 2>(bfr, S.red2);
+  }
+  if (threadIdx.x == 0) {
+    const double rhow = -acc[0] / (dt * acc[1]);
+    R[FR_RHOW] = rhow;
+    // the wall face's time-integrated flux of mass, momentum and energy
+    // (Eq. macro_flux): incident part plus rho_w dt times the re-emitted part
+    if constexpr (BF)
+      for (int x = 0; x < D + 2; ++x) R[FR_BF + x] = bfi[x] + rhow * dt * bfr[x];
+  }
 }
 
 // One work-group per wall face (256 lanes measured faster than 1024).
@@ -1096,10 +1181,15 @@ template <int D, typename T>
 __global__ __launch_bounds__(WALLT) void k_wall_rho_inline(DevMesh m, DevVel v, FusedMesh fm, GasP g,
                                                          const T* __restrict__ h,
                                                          double* __restrict__ frec,
-                                                         const int32_t* flag) {
+                                                         const int32_t* flag, const T* b_bf) {
   __shared__ WallLds S;
-  if (fm.crec_l) wall_rho_at<D, T, true>(blockIdx.x, m, v, fm, g, h, frec, flag, S);
-  else wall_rho_at<D, T, false>(blockIdx.x, m, v, fm, g, h, frec, flag, S);
+  if (b_bf) {
+    if (fm.crec_l) wall_rho_at<D, T, true, true>(blockIdx.x, m, v, fm, g, h, frec, flag, S, b_bf);
+    else wall_rho_at<D, T, false, true>(blockIdx.x, m, v, fm, g, h, frec, flag, S, b_bf);
+  } else {
+    if (fm.crec_l) wall_rho_at<D, T, true>(blockIdx.x, m, v, fm, g, h, frec, flag, S);
+    else wall_rho_at<D, T, false>(blockIdx.x, m, v, fm, g, h, frec, flag, S);
+  }
 }
 
 // Ghost rows of the far-field / outflow faces: the Maxwellian of the face's
@@ -1271,11 +1361,18 @@ hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, c
                         double* dWp, const int32_t* flag, hipStream_t s) {
   const int64_t ntile = (fm.nc + sc.tile - 1) / sc.tile;
   const unsigned grid = (unsigned)(((ntile + 7) / 8) * 8 * sc.nchunk * sc.tile);
+  // a sparse set's pairs carry their own packed axis indices
+  const int32_t* pv = fm.sparse ? fm.pvidx : fm.vidx;
 #define UGKS_SWEEP_ARGS                                                                       \
-  fm, v.nvp, sc, fm.crec_i, (const TT*)crec_d, (const TT*)crec_l, fm.vidx, v.w, (const TT*)cs, \
+  fm, v.nvp, sc, fm.crec_i, (const TT*)crec_d, (const TT*)crec_l, pv, v.w, (const TT*)cs,      \
       (const TT*)frec, (const TT*)tabs, (const TT*)h, (const TT*)b, (TT*)ht, (TT*)bt, dWp, flag
-  if (crec_l) UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, true><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
-  else UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, false><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+  if (fm.sparse) {
+    if (crec_l) UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, true, true><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+    else UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, false, true><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+  } else {
+    if (crec_l) UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, true, false><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+    else UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, false, false><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+  }
 #undef UGKS_SWEEP_ARGS
   return hipGetLastError();
 }
@@ -1309,10 +1406,43 @@ hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v
 
 hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
                                   const FusedMesh& fm, const GasP& g, const void* h, double* frec,
-                                  const int32_t* flag, hipStream_t s) {
+                                  const int32_t* flag, hipStream_t s, const void* b_bf) {
   if (m.nwall == 0) return hipSuccess;
   UGKS_DISPATCH_DT(D, prec, k_wall_rho_inline<DD, TT><<<(unsigned)m.nwall, WALLT, 0, s>>>(
-      m, v, fm, g, (const TT*)h, frec, flag));
+      m, v, fm, g, (const TT*)h, frec, flag, (const TT*)b_bf));
+  return hipGetLastError();
+}
+
+// The step's boundary flux, added to the running sum acc[0..D+1]: the sum
+// over boundary faces of S_f F_f, from the wall records' fluxes (fused path,
+// FR_BF) or from the face fluxes (staged path, every boundary face).  One
+// work-group; each lane adds its faces in order, then a fixed reduction.
+template <int D>
+__global__ __launch_bounds__(256) void k_bflux(DevMesh m, const double* __restrict__ frec,
+                                               const double* __restrict__ F, int staged,
+                                               double* __restrict__ acc, const int32_t* flag) {
+  __shared__ double red[5 * 16];
+  if (*flag) return;
+  double s[D + 2];
+  for (int x = 0; x < D + 2; ++x) s[x] = 0.0;
+  if (staged) {
+    for (int64_t f = threadIdx.x; f < m.nf; f += 256)
+      if (m.fR[f] < 0)
+        for (int x = 0; x < D + 2; ++x) s[x] += m.farea[f] * F[f * 5 + x];
+  } else {
+    for (int64_t wi = threadIdx.x; wi < m.nwall; wi += 256) {
+      const int64_t f = m.walls[wi];
+      for (int x = 0; x < D + 2; ++x) s[x] += m.farea[f] * frec[f * FREC + FR_BF + x];
+    }
+  }
+  block_sum<D + 2>(s, red);
+  if (threadIdx.x == 0)
+    for (int x = 0; x < D + 2; ++x) acc[x] += s[x];
+}
+
+hipError_t launch_bflux(int D, const DevMesh& m, const double* frec, const double* F, int staged,
+                        double* acc, const int32_t* flag, hipStream_t s) {
+  UGKS_DISPATCH_D(D, k_bflux<DD><<<1, 256, 0, s>>>(m, frec, F, staged, acc, flag));
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ EXPORTED = [
     "ugks_batch_last_error", "ugks_autotune_save", "ugks_autotune_load", "ugks_autotune_clear",
     "ugks_mlp_create", "ugks_mlp_get_params", "ugks_mlp_set_box", "ugks_mlp_forward",
     "ugks_mlp_loss_grad", "ugks_mlp_train", "ugks_mlp_destroy", "ugks_mlp_last_error",
-    "ugks_mlp_forward_noalloc",
+    "ugks_mlp_forward_noalloc", "ugks_boundary_flux",
     "ugks_snapshot", "ugks_warm_start",
 ]
 
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.ugks_step.argtypes = [P, C.c_int32, P]
     lib.ugks_moments.restype = C.c_int
     lib.ugks_moments.argtypes = [P, C.c_int32, P, C.c_int32]
+    lib.ugks_boundary_flux.restype = C.c_int
+    lib.ugks_boundary_flux.argtypes = [P, P, P]
     lib.ugks_get_state.restype = C.c_int
     lib.ugks_get_state.argtypes = [P, P, P, P]
     lib.ugks_set_state.restype = C.c_int
@@ -326,6 +328,13 @@ class Solver:
         ncol = self.dim if which == 2 else self.dim + 2
         out = np.zeros((self.nc, ncol))
         return ugks_moments(self.h, which, out)
+
+    def boundary_flux(self):
+        """(A, complete): the boundary flux summed over the steps (needs flags bit 6)."""
+        out = np.zeros(self.dim + 2)
+        comp = C.c_int32(0)
+        _check(load_library().ugks_boundary_flux(self.h, _p(out), C.byref(comp)), self.h)
+        return out, bool(comp.value)
 
     def state(self, with_h: bool = True):
         W = np.zeros((self.nc, self.dim + 2))

@@ -145,6 +145,10 @@ def test_fixed_schedule_and_mixed_dimension_rejected():
     with pytest.raises(U.UGKSError) as e:
         U.Batch(cases, limiter=1, limiter_k=1.0)
     assert e.value.code == U.UGKS_EUNSUPPORTED and "limiter" in str(e.value)
+    refined = uc.cavity2d(n=4, velocity=uc.locally_refined_grid(8, 4.0, 2, (0.5, 0.0), 1.0))
+    with pytest.raises(U.UGKSError) as e:
+        U.Batch([cases[0], refined])
+    assert e.value.code == U.UGKS_EUNSUPPORTED and "case 1" in str(e.value)
     mixed = [cases[0], uc.sod3d_tets(n=2, nv=8)]
     with pytest.raises(U.UGKSError) as e:
         U.Batch(mixed)

@@ -342,24 +342,47 @@ def test_device_memory_accounting(which, prec, flags):
     assert 0 <= extra <= 8192 * (nc + nf) + 256 * nvp + (4 << 20)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_nontensor_locally_refined_velocity_set_parity(dim):
+@pytest.mark.parametrize("flags", PATHS)
+@pytest.mark.parametrize("dim,center", [(2, (0.6, 0.2)), (3, (0.9, 0.0, -0.3)), (2, (0.0, 0.0)),
+                                        (3, (0.0, 0.0, 0.0))])
+def test_nontensor_locally_refined_velocity_set_parity(dim, center, flags):
     """A velocity set refined around one velocity (the paper's locally refined
-    sets, Sec. 3.3) is no tensor product: the library runs it on the staged
-    sweep, whatever velocity set it is given."""
+    sets, Sec. 3.3) is no tensor product.  Its points lie on the tensor
+    product of one small node set, so the fused sweep runs it from a table of
+    mirror pairs (refined off centre, points without a mirror get a pad
+    partner); the staged sweep runs any set."""
     if dim == 2:
-        vel = uc.locally_refined_grid(10, 4.0, 2, (0.6, 0.2), 1.3)
+        vel = uc.locally_refined_grid(10, 4.0, 2, center, 1.3)
         case = uc.cavity2d(n=6, kn=0.1, velocity=vel)
         steps = 10
     else:
         case = uc.sod3d_tets(n=2, nv=6, jitter=0.15, seed=4)
-        case.vel = uc.locally_refined_grid(6, 4.0, 3, (0.9, 0.0, -0.3), 1.2)
+        case.vel = uc.locally_refined_grid(6, 4.0, 3, center, 1.2)
         steps = 4
     assert case.vel.nv not in [n ** dim for n in range(2, 80)]
-    s = Solver(case)
-    assert s.info["fused"] == 0
+    s = Solver(case, flags=flags)
+    assert s.info["fused"] == (0 if flags & STAGED else 1)
     s.close()
-    _compare_step(case, steps)
+    _compare_step(case, steps, flags=flags)
+
+
+@pytest.mark.parametrize("flags", PATHS)
+def test_nontensor_refined_set_with_the_limiter_parity(flags):
+    case = uc.sod3d_tets(n=3, nv=6, jitter=0.15, seed=6)
+    case.vel = uc.locally_refined_grid(8, 4.0, 3, (1.0, 0.5, 0.0), 1.5, levels=2)
+    _compare_step(case, 4, flags=flags, limiter=1, limiter_k=0.0)
+
+
+def test_nontensor_refined_set_fp32_form():
+    case = uc.cavity2d(n=10, kn=0.1, velocity=uc.locally_refined_grid(12, 4.0, 2, (0.8, 0.0), 1.6))
+    o = Oracle(case)
+    s = Solver(case, precision=UGKS_FP32)
+    assert s.info["fused"] == 1
+    o.step(30)
+    s.step(30)
+    err = _normwise(s.W(), o.state(with_h=False)[0])
+    assert np.all(err < 1e-5), err
+    s.close()
 
 
 def test_gauss_hermite_velocity_set_fused_parity():
@@ -433,4 +456,60 @@ def test_limited_fp32_form_against_fp64_oracle():
     err = _normwise(s.W(), o.state(with_h=False)[0])
     print("limited FP32 form normwise error after 30 steps:", err, flush=True)
     assert np.all(err < 1e-5)
+    s.close()
+
+
+TRACK = 64  # ugks_options.flags bit: track the boundary flux
+
+
+@pytest.mark.parametrize("which,flags", [("cavity2d", 0), ("cavity2d", STAGED), ("sod3d", 0),
+                                         ("sod3d", STAGED), ("channel2d", STAGED),
+                                         ("sod3d_limited", 0)])
+def test_boundary_flux_balances_the_totals(which, flags):
+    """Eq. macro_update summed over the cells: the change of the totals
+    sum_i V_i W_i equals minus the accumulated boundary flux, and that flux
+    equals the oracle's face fluxes summed over boundary faces and steps."""
+    lim = {}
+    if which == "cavity2d":
+        case, steps = uc.cavity2d(n=10, nv=12, kn=0.05, lid=0.4), 12
+    elif which == "channel2d":
+        case, steps = uc.channel2d(n=8, nv=12, kn=0.05, u_in=0.8), 10
+    else:
+        case, steps = uc.sod3d_tets(n=3, nv=8, jitter=0.15, seed=3), 6
+        if which == "sod3d_limited":
+            lim = dict(limiter=1, limiter_k=0.0)
+    s = Solver(case, flags=flags | TRACK, **lim)
+    o = Oracle(case, **lim)
+    m = case.mesh
+    V = m.cell_volume
+    bnd = m.face_bc != uc.BC_INTERIOR
+    tot0 = V @ s.W()
+    Ao = np.zeros(m.dim + 2)
+    for _ in range(steps):
+        o.step(1)
+        F = o.faces()[0]
+        Ao += (m.face_area[bnd, None] * F[bnd]).sum(axis=0)
+    s.step(steps)
+    A, complete = s.boundary_flux()
+    assert complete
+    W = s.W()
+    scale = (V[:, None] * np.abs(W)).sum(axis=0).max()
+    bal = V @ W - tot0 + A
+    print(which, flags, "balance", bal, "A", A, "oracle A", Ao, flush=True)
+    assert np.all(np.abs(bal) <= 1e-13 * scale), bal
+    assert np.all(np.abs(A - Ao) <= 1e-12 * scale), (A, Ao)
+    assert np.abs(A[-1]) > 1e-6 * scale  # heat crosses the walls: the check is not vacuous
+    s.close()
+
+
+def test_boundary_flux_needs_tracking_and_is_partial_with_far_field_on_the_fused_sweep():
+    s = Solver(uc.cavity2d(n=3, nv=6))
+    with pytest.raises(UGKSError) as e:
+        s.boundary_flux()
+    assert e.value.code == -1 and "tracking" in str(e.value)
+    s.close()
+    s = Solver(uc.channel2d(n=6, nv=10), flags=TRACK)
+    s.step(2)
+    _, complete = s.boundary_flux()
+    assert not complete
     s.close()
