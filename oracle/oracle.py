@@ -78,6 +78,10 @@ def _load():
     lib.oracle_macro_grad.argtypes = [P, P]
     lib.oracle_grad_W.restype = None
     lib.oracle_grad_W.argtypes = [P, P]
+    lib.oracle_set_local_dt.restype = None
+    lib.oracle_set_local_dt.argtypes = [P, i32]
+    lib.oracle_local_dt.restype = None
+    lib.oracle_local_dt.argtypes = [P, P, P]
     lib.oracle_threads.restype = i32
     lib.oracle_threads.argtypes = []
     lib.oracle_set_threads.restype = None
@@ -98,7 +102,7 @@ class Oracle:
     """One oracle context for a ``ugks_cases.Case``."""
 
     def __init__(self, case, dt: float | None = None, order: int = 2, limiter: int = 0,
-                 limiter_k: float = 0.0):
+                 limiter_k: float = 0.0, local_dt: bool = False):
         lib = _load()
         m = case.mesh.contiguous()
         v = case.vel
@@ -128,6 +132,8 @@ class Oracle:
             lib.oracle_set_order(self.h_, 1)
         if limiter:
             lib.oracle_set_limiter(self.h_, int(limiter), float(limiter_k))
+        if local_dt:
+            lib.oracle_set_local_dt(self.h_, 1)
 
     def __del__(self):
         if getattr(self, "h_", None):
@@ -137,6 +143,14 @@ class Oracle:
     @property
     def dt(self) -> float:
         return self.lib.oracle_dt(self.h_)
+
+    def local_dt(self):
+        """Per-cell and per-face steps [nc], [nf] (local time steps, reading
+        R26; the global dt everywhere when they are off)."""
+        dtc = np.zeros(self.nc)
+        dtf = np.zeros(self.nf)
+        self.lib.oracle_local_dt(self.h_, _p(dtc), _p(dtf))
+        return dtc, dtf
 
     def step(self, n: int = 1):
         out = np.zeros(2)

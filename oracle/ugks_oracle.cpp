@@ -48,6 +48,12 @@
 //      psi = (d+^2 + eps^2 + 2 d- d+) / (d+^2 + 2 d-^2 + d- d+ + eps^2)
 //      (psi = 1 where d- = 0), phi = min(1, min_faces psi), g -> phi g,
 //      eps^2 = (K V_i^(1/D))^3.  Off by default.
+//   R26 optional local time steps for steady problems (the paper has none;
+//      its conclusion names steady-state acceleration as future work): cell
+//      i steps by dt_i = dt b_i / min_j b_j with b_i the cell's R5 bound,
+//      face f integrates over dt_f = min(dt_L, dt_R), and cell i applies the
+//      face's time-integrated fluxes scaled by dt_i / dt_f (the flux as a
+//      rate over dt_f, for dt_i).  Off by default.
 //
 // Layout (oracle's own choice): distributions are velocity-major,
 // h[k * n_cells + i], so one velocity is swept over all cells at a time, which
@@ -428,23 +434,55 @@ struct oracle_ctx {
     for (int d = 0; d < D; ++d) g[d] *= phi;
   }
 
+  // The step bound of cell i (R5 without the CFL number):
+  // 2 V_i / max_k sum_{j in faces(i)} S_j |u_k . n_j|.
+  double cell_bound(int64_t i) const {
+    double mx = 0.0;
+    for (int64_t k = 0; k < nv; ++k) {
+      double s = 0.0;
+      for (int64_t f : cfaces[i]) {
+        double un = 0.0;
+        for (int d = 0; d < D; ++d) un += u[k * D + d] * fnorm[f * D + d];
+        s += farea[f] * std::fabs(un);
+      }
+      mx = std::max(mx, s);
+    }
+    return 2.0 * vol[i] / mx;
+  }
+
   double compute_dt(double cfl) const {
     double best = INFINITY;
-    for (int64_t i = 0; i < nc; ++i) {
-      double mx = 0.0;
-      for (int64_t k = 0; k < nv; ++k) {
-        double s = 0.0;
-        for (int64_t f : cfaces[i]) {
-          double un = 0.0;
-          for (int d = 0; d < D; ++d) un += u[k * D + d] * fnorm[f * D + d];
-          s += farea[f] * std::fabs(un);
-        }
-        mx = std::max(mx, s);
-      }
-      best = std::min(best, 2.0 * vol[i] / mx);
-    }
+    for (int64_t i = 0; i < nc; ++i) best = std::min(best, cell_bound(i));
     return cfl * best;
   }
+
+  // Local time steps for steady problems (reading R26): cell i steps by
+  // dt_i = dt * b_i / min_j b_j, b_i its R5 bound, so the most restrictive
+  // cell keeps the global dt; face f integrates its flux over
+  // dt_f = min(dt_L, dt_R) (dt_L on a boundary face), and each cell takes the
+  // face's flux as a rate over dt_f for its own dt_i.
+  bool lts = false;
+  std::vector<double> dtc, dtf;
+  void set_local_dt(bool on) {
+    lts = on;
+    dtc.clear();
+    dtf.clear();
+    if (!on) return;
+    std::vector<double> bnd(nc);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < nc; ++i) bnd[i] = cell_bound(i);
+    double mn = INFINITY;
+    for (int64_t i = 0; i < nc; ++i) mn = std::min(mn, bnd[i]);
+    dtc.resize(nc);
+    for (int64_t i = 0; i < nc; ++i) dtc[i] = dt * (bnd[i] / mn);
+    dtf.resize(nf);
+    for (int64_t f = 0; f < nf; ++f)
+      dtf[f] = fbc[f] == BC_INTERIOR ? std::min(dtc[fL[f]], dtc[fR[f]]) : dtc[fL[f]];
+  }
+  double dt_face(int64_t f) const { return lts ? dtf[f] : dt; }
+  double dt_cell(int64_t i) const { return lts ? dtc[i] : dt; }
+  // S_f as cell i applies it: times dt_i / dt_f under local steps
+  double area_for(int64_t i, int64_t f) const { return lts ? farea[f] * (dtc[i] / dtf[f]) : farea[f]; }
 
   // Heat flux of every cell (step 2, Eq. reduced_heat_flux).
   void heat_flux(const std::vector<Prim>& P) {
@@ -791,7 +829,7 @@ int oracle_ctx::step_once() {
     if (!p0.ok) { bad = true; continue; }
     e.rho0 = p0.rho; e.lam0 = p0.lam; e.tau0 = p0.tau;
     for (int d = 0; d < 3; ++d) e.U0[d] = p0.U[d];
-    gamma_coeffs(dt, p0.tau, e.G);
+    gamma_coeffs(dt_face(f), p0.tau, e.G);
     double dW[3 * 5];
     for (int d = 0; d < D; ++d)
       for (int v = 0; v < nw; ++v)
@@ -845,6 +883,7 @@ int oracle_ctx::step_once() {
     double lamw = 1.0 / (2.0 * Rg * Tw);
     double Uw[3] = {bcU[id * 3], bcU[id * 3 + 1], bcU[id * 3 + 2]};
     double incident = 0.0, reflected = 0.0;
+    const double dt = dt_face(f);
     for (int64_t k = 0; k < nv; ++k) {
       double un = 0.0;
       for (int d = 0; d < D; ++d) un += u[k * D + d] * fnorm[f * D + d];
@@ -892,6 +931,7 @@ int oracle_ctx::step_once() {
       for (int d = 0; d < D; ++d) un += uk[d] * fnorm[f * D + d];
       int64_t L = fL[f];
       double ih = 0.0, ib = 0.0;
+      const double dt = dt_face(f);
       if (fbc[f] == BC_WALL) {
         int id = fbcid[f];
         double lamw = 1.0 / (2.0 * Rg * bcT[id]);
@@ -971,15 +1011,15 @@ int oracle_ctx::step_once() {
       double sh = 0.0, sb = 0.0;
       for (int64_t f : cfaces[i]) {
         double sg = fL[f] == i ? 1.0 : -1.0;
-        sh += sg * farea[f] * Hf[f];
-        sb += sg * farea[f] * Bf[f];
+        sh += sg * area_for(i, f) * Hf[f];
+        sb += sg * area_for(i, f) * Bf[f];
       }
       const Prim& p = P[i];
       double H = H_at(p.rho, p.U, p.lam, k);
       double Hp, Bp;
       shakhov(p.rho, p.U, p.lam, &q[i * D], k, H, Hp, Bp);
       double B = kxi / (2.0 * p.lam) * H;
-      double c = dt / (2.0 * p.tau);
+      double c = dt_cell(i) / (2.0 * p.tau);
       double hv = h[k * nc + i];
       ht[k * nc + i] = hv - sh / vol[i] + c * (H + Hp - hv);
       if (nr == 2) {
@@ -994,7 +1034,7 @@ int oracle_ctx::step_once() {
     double acc[5] = {0, 0, 0, 0, 0};
     for (int64_t f : cfaces[i]) {
       double sg = fL[f] == i ? 1.0 : -1.0;
-      for (int v = 0; v < nw; ++v) acc[v] += sg * farea[f] * F[f * nw + v];
+      for (int v = 0; v < nw; ++v) acc[v] += sg * area_for(i, f) * F[f * nw + v];
     }
     for (int v = 0; v < nw; ++v) Wn[i * nw + v] = W[i * nw + v] - acc[v] / vol[i];
   }
@@ -1007,7 +1047,7 @@ int oracle_ctx::step_once() {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nc; ++i) {
     const Prim& p = Pn[i];
-    double a = dt / (2.0 * p.tau);
+    double a = dt_cell(i) / (2.0 * p.tau);
     for (int64_t k = 0; k < nv; ++k) {
       double H = H_at(p.rho, p.U, p.lam, k);
       double Hp, Bp;
@@ -1036,6 +1076,15 @@ int oracle_ctx::step_once() {
   W.swap(Wn);
   ++steps_done;
   return 0;
+}
+
+// Local time steps (reading R26): on = 1 gives every cell its own step.
+extern "C" void oracle_set_local_dt(oracle_ctx* o, int on) { o->set_local_dt(on != 0); }
+
+// The cells' and faces' steps, [nc] and [nf] (the global dt everywhere when off).
+extern "C" void oracle_local_dt(const oracle_ctx* o, double* dtc, double* dtf) {
+  for (int64_t i = 0; i < o->nc; ++i) dtc[i] = o->dt_cell(i);
+  for (int64_t f = 0; f < o->nf; ++f) dtf[f] = o->dt_face(f);
 }
 
 // Reconstruction order: 1 = first order (all gradients zero), 2 = least squares.

@@ -49,8 +49,12 @@ def _maxwellian(u, rho, U, lam, D):
     return rho * (lam / math.pi) ** (D / 2.0) * np.exp(-lam * d2)
 
 
-def _first_order_step(case, W, h, b, dt, collisionless=False):
-    """One first-order step (Pr = 1) written from Sec. 2.1; see the header."""
+def _first_order_step(case, W, h, b, dt, collisionless=False, dtc=None, dtf=None):
+    """One first-order step (Pr = 1) written from Sec. 2.1; see the header.
+
+    With per-cell and per-face steps dtc, dtf (local time steps, reading R26)
+    face f integrates over dtf[f], cell i relaxes over dtc[i] and applies each
+    face's integral scaled by dtc[i] / dtf[f]."""
     m, v, gas = case.mesh, case.vel, case.gas
     assert gas.Pr == 1.0
     D = m.dim
@@ -69,18 +73,21 @@ def _first_order_step(case, W, h, b, dt, collisionless=False):
         S = m.face_area[f]
         un = u @ n
         bc = m.face_bc[f]
+        dt_f = dt if dtf is None else dtf[f]
+        rL = 1.0 if dtc is None else dtc[L] / dt_f
+        rR = 1.0 if dtc is None or bc != uc.BC_INTERIOR else dtc[R] / dt_f
         if bc == uc.BC_WALL:
             t = case.bcs[m.face_bc_id[f]]
             lamw = 1.0 / (2.0 * gas.R * t.T)
             Hw = _maxwellian(u, 1.0, np.asarray(t.U, float), lamw, D)
             out = un > 0.0
             back = un < 0.0
-            ih = np.where(out, dt * h[L], 0.0)
-            ib = np.where(out, dt * b[L], 0.0)
+            ih = np.where(out, dt_f * h[L], 0.0)
+            ib = np.where(out, dt_f * b[L], 0.0)
             # zero mass flux through the wall fixes rho_w (Eq. wall_density_condition)
-            rhow = -np.sum((w * un * ih)[out]) / (dt * np.sum((w * un * Hw)[back]))
-            ih = np.where(back, dt * rhow * Hw, ih)
-            ib = np.where(back, dt * rhow * kxi / (2.0 * lamw) * Hw, ib)
+            rhow = -np.sum((w * un * ih)[out]) / (dt_f * np.sum((w * un * Hw)[back]))
+            ih = np.where(back, dt_f * rhow * Hw, ih)
+            ib = np.where(back, dt_f * rhow * kxi / (2.0 * lamw) * Hw, ib)
         else:
             if bc == uc.BC_INTERIOR:
                 Wr, hr, br = W[R], h[R], b[R]
@@ -96,11 +103,11 @@ def _first_order_step(case, W, h, b, dt, collisionless=False):
             hup = np.where(un > 0.0, h[L], hr)
             bup = np.where(un > 0.0, b[L], br)
             if collisionless:
-                ih, ib = dt * hup, dt * bup
+                ih, ib = dt_f * hup, dt_f * bup
             else:
                 W0 = interface_state(W[L], Wr, n)
                 r0, U0, l0, t0 = _prim(W0, D, gas)
-                G = gamma(dt, t0)
+                G = gamma(dt_f, t0)
                 H0 = _maxwellian(u, r0, U0, l0, D)
                 ih = G[0] * hup + G[2] * H0
                 ib = G[0] * bup + G[2] * kxi / (2.0 * l0) * H0
@@ -109,20 +116,20 @@ def _first_order_step(case, W, h, b, dt, collisionless=False):
         F[0] = np.sum(w * Hk)
         F[1:1 + D] = (w * Hk) @ u
         F[D + 1] = 0.5 * np.sum(w * (u2 * Hk + Bk))
-        net_h[L] += S * Hk
-        net_b[L] += S * Bk
-        dW[L] += S * F
+        net_h[L] += rL * S * Hk
+        net_b[L] += rL * S * Bk
+        dW[L] += rL * S * F
         if bc == uc.BC_INTERIOR:
-            net_h[R] -= S * Hk
-            net_b[R] -= S * Bk
-            dW[R] -= S * F
+            net_h[R] -= rR * S * Hk
+            net_b[R] -= rR * S * Bk
+            dW[R] -= rR * S * F
     V = m.cell_volume
     ht = np.empty_like(h)
     bt = np.empty_like(b)
     for i in range(nc):
         rho, U, lam, tau = P[i]
         H = _maxwellian(u, rho, U, lam, D)
-        a = 0.0 if collisionless else dt / (2.0 * tau)
+        a = 0.0 if collisionless else (dt if dtc is None else dtc[i]) / (2.0 * tau)
         ht[i] = h[i] - net_h[i] / V[i] + a * (H - h[i])                       # Eq. f_tilde
         bt[i] = b[i] - net_b[i] / V[i] + a * (kxi / (2.0 * lam) * H - b[i])
     Wn = W - dW / V[:, None]                                                   # Eq. macro_update
@@ -131,7 +138,7 @@ def _first_order_step(case, W, h, b, dt, collisionless=False):
     for i in range(nc):
         rho, U, lam, tau = _prim(Wn[i], D, gas)
         H = _maxwellian(u, rho, U, lam, D)
-        a = 0.0 if collisionless else dt / (2.0 * tau)
+        a = 0.0 if collisionless else (dt if dtc is None else dtc[i]) / (2.0 * tau)
         hn[i] = (ht[i] + a * H) / (1.0 + a)                                    # Eq. f_final
         bn[i] = (bt[i] + a * kxi / (2.0 * lam) * H) / (1.0 + a)
     return Wn, hn, bn
