@@ -322,7 +322,8 @@ def run_warm_start(args):
                               arms_run=tuple(args.ws_arms.split(",")),
                               ref_out=args.ws_save_ref or None, ref_in=args.ws_ref or None,
                               deep_target=args.ws_deep or None, deep_max_steps=args.ws_max_steps,
-                              flags=0 if second else 16, limiter=1 if second else 0,
+                              flags=(0 if second else 16) | (128 if args.ws_local_dt else 0),
+                              limiter=1 if second else 0,
                               limiter_k=args.ws_limiter_k, blunt=not args.ws_no_blunt)
     out["metric"] = "time to 1e-6 density residual (s)"
     out["reconstruction"] = (f"second order with Venkatakrishnan's limiter, K = {args.ws_limiter_k}"
@@ -331,6 +332,15 @@ def run_warm_start(args):
     out["kn"] = args.ws_kn
     out["velocity_box"] = a
     out["start"] = args.ws_start
+    out["local_time_steps"] = bool(args.ws_local_dt)
+    if args.ws_compare and args.ws_save_ref and args.ws_deep:
+        # another run's final W (for example the global step's at the target)
+        # against this run's plain FP64 arm continued to the deep residual
+        import numpy as np
+        Wd = np.load(args.ws_save_ref.replace(".npy", "") + "_deep.npy")
+        Wc = np.load(args.ws_compare)
+        out["compare"] = {"state": os.path.basename(args.ws_compare),
+                          "field_error_vs_plain64_deep": WS.field_errors(Wc, Wd, fine.mesh.dim)}
     print(json.dumps(out), flush=True)
 
 
@@ -462,6 +472,10 @@ def main():
                     help="Venkatakrishnan's K at second order")
     ap.add_argument("--ws-no-blunt", action="store_true",
                     help="train without the supersonic cylinder flows")
+    ap.add_argument("--ws-local-dt", action="store_true",
+                    help="every arm with local time steps (each cell its own step)")
+    ap.add_argument("--ws-compare", default="",
+                    help="a W (.npy) to compare with the plain arm's deep state")
     ap.add_argument("--ws-start", default="freestream",
                     choices=("freestream", "rest", "potential", "sheltered"),
                     help="initial state of the sphere case")

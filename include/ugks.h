@@ -148,15 +148,31 @@ typedef struct {
  *                     piecewise-constant states of its two cells; robust where
  *                     unlimited second-order slopes overshoot (strong shocks).
  *              bit 6: track the boundary flux (ugks_boundary_flux).
+ *              bit 7: local time steps for steady problems (steady-state
+ *                     acceleration, which the paper's conclusion names as
+ *                     future work; this library's reading): cell i advances
+ *                     by dt_i = dt b_i / min_j b_j, b_i = 2 V_i / max_k sum_j
+ *                     S_j |u_k . n_j| its own bound (the most restrictive cell
+ *                     keeps dt).  Every face still integrates its fluxes
+ *                     (Eqs. micro_flux, macro_flux) over the global dt; cell i
+ *                     applies them scaled by dt_i / dt and relaxes (Eqs.
+ *                     f_tilde, f_final) over dt_i.  Not time-accurate, but a
+ *                     steady state of the global step is one of this step
+ *                     and vice versa.  Excludes bit 6 (UGKS_EINVAL); the
+ *                     batched form refuses it (UGKS_EUNSUPPORTED).  ugks_info's
+ *                     dt stays the global dt.
  *              bit 5: replay each step from a HIP graph of its kernels
  *                     (captured at the first step that can use it; not on the
  *                     null stream, nor while profiling).  Same results as
  *                     kernel-by-kernel launches.
  *   The fused sweep (one pass for reconstruction, interface flux, moment
- *   sums and the first stage) applies when the velocity set is a tensor
- *   product of one 1-D node set symmetric about zero, listed with the first
- *   axis slowest, and every cell has at most 4 faces (far-field and outflow
- *   faces read per-step ghost rows holding the ghost Maxwellian).  Otherwise
+ *   sums and the first stage) applies when every velocity point lies on the
+ *   tensor product of one 1-D node set symmetric about zero of at most 64
+ *   nodes (the full product listed with the first axis slowest, or any
+ *   subset of it, such as a locally refined set whose levels are lattices;
+ *   a point whose mirror is absent is paired with a weight-0 pad slot), and
+ *   every cell has at most 4 faces (far-field and outflow faces read
+ *   per-step ghost rows holding the ghost Maxwellian).  Otherwise
  *   the staged sweep keeps the microscopic gradients and fluxes of the whole
  *   velocity space in device memory.
  *   stream     hipStream_t to enqueue on, or NULL for a library-owned stream.

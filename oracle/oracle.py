@@ -81,7 +81,7 @@ def _load():
     lib.oracle_set_local_dt.restype = None
     lib.oracle_set_local_dt.argtypes = [P, i32]
     lib.oracle_local_dt.restype = None
-    lib.oracle_local_dt.argtypes = [P, P, P]
+    lib.oracle_local_dt.argtypes = [P, P]
     lib.oracle_threads.restype = i32
     lib.oracle_threads.argtypes = []
     lib.oracle_set_threads.restype = None
@@ -145,12 +145,11 @@ class Oracle:
         return self.lib.oracle_dt(self.h_)
 
     def local_dt(self):
-        """Per-cell and per-face steps [nc], [nf] (local time steps, reading
-        R26; the global dt everywhere when they are off)."""
+        """Per-cell steps [nc] (local time steps, reading R26; the global dt
+        everywhere when they are off)."""
         dtc = np.zeros(self.nc)
-        dtf = np.zeros(self.nf)
-        self.lib.oracle_local_dt(self.h_, _p(dtc), _p(dtf))
-        return dtc, dtf
+        self.lib.oracle_local_dt(self.h_, _p(dtc))
+        return dtc
 
     def step(self, n: int = 1):
         out = np.zeros(2)

@@ -50,10 +50,10 @@
 //      eps^2 = (K V_i^(1/D))^3.  Off by default.
 //   R26 optional local time steps for steady problems (the paper has none;
 //      its conclusion names steady-state acceleration as future work): cell
-//      i steps by dt_i = dt b_i / min_j b_j with b_i the cell's R5 bound,
-//      face f integrates over dt_f = min(dt_L, dt_R), and cell i applies the
-//      face's time-integrated fluxes scaled by dt_i / dt_f (the flux as a
-//      rate over dt_f, for dt_i).  Off by default.
+//      i advances by dt_i = dt b_i / min_j b_j, b_i the cell's R5 bound;
+//      every face still integrates over the global dt, and cell i applies
+//      the face integrals scaled by dt_i / dt and relaxes over dt_i.  A fixed
+//      point of the global step is a fixed point of this one.  Off by default.
 //
 // Layout (oracle's own choice): distributions are velocity-major,
 // h[k * n_cells + i], so one velocity is swept over all cells at a time, which
@@ -456,17 +456,15 @@ struct oracle_ctx {
     return cfl * best;
   }
 
-  // Local time steps for steady problems (reading R26): cell i steps by
+  // Local time steps for steady problems (reading R26): cell i advances by
   // dt_i = dt * b_i / min_j b_j, b_i its R5 bound, so the most restrictive
-  // cell keeps the global dt; face f integrates its flux over
-  // dt_f = min(dt_L, dt_R) (dt_L on a boundary face), and each cell takes the
-  // face's flux as a rate over dt_f for its own dt_i.
+  // cell keeps the global dt.  Faces integrate over the global dt; cell i
+  // applies their integrals as rates over dt, for its own dt_i.
   bool lts = false;
-  std::vector<double> dtc, dtf;
+  std::vector<double> dtc;
   void set_local_dt(bool on) {
     lts = on;
     dtc.clear();
-    dtf.clear();
     if (!on) return;
     std::vector<double> bnd(nc);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -475,14 +473,10 @@ struct oracle_ctx {
     for (int64_t i = 0; i < nc; ++i) mn = std::min(mn, bnd[i]);
     dtc.resize(nc);
     for (int64_t i = 0; i < nc; ++i) dtc[i] = dt * (bnd[i] / mn);
-    dtf.resize(nf);
-    for (int64_t f = 0; f < nf; ++f)
-      dtf[f] = fbc[f] == BC_INTERIOR ? std::min(dtc[fL[f]], dtc[fR[f]]) : dtc[fL[f]];
   }
-  double dt_face(int64_t f) const { return lts ? dtf[f] : dt; }
   double dt_cell(int64_t i) const { return lts ? dtc[i] : dt; }
-  // S_f as cell i applies it: times dt_i / dt_f under local steps
-  double area_for(int64_t i, int64_t f) const { return lts ? farea[f] * (dtc[i] / dtf[f]) : farea[f]; }
+  // S_f as cell i applies it: times dt_i / dt under local steps
+  double area_for(int64_t i, int64_t f) const { return lts ? farea[f] * (dtc[i] / dt) : farea[f]; }
 
   // Heat flux of every cell (step 2, Eq. reduced_heat_flux).
   void heat_flux(const std::vector<Prim>& P) {
@@ -829,7 +823,7 @@ int oracle_ctx::step_once() {
     if (!p0.ok) { bad = true; continue; }
     e.rho0 = p0.rho; e.lam0 = p0.lam; e.tau0 = p0.tau;
     for (int d = 0; d < 3; ++d) e.U0[d] = p0.U[d];
-    gamma_coeffs(dt_face(f), p0.tau, e.G);
+    gamma_coeffs(dt, p0.tau, e.G);
     double dW[3 * 5];
     for (int d = 0; d < D; ++d)
       for (int v = 0; v < nw; ++v)
@@ -883,7 +877,6 @@ int oracle_ctx::step_once() {
     double lamw = 1.0 / (2.0 * Rg * Tw);
     double Uw[3] = {bcU[id * 3], bcU[id * 3 + 1], bcU[id * 3 + 2]};
     double incident = 0.0, reflected = 0.0;
-    const double dt = dt_face(f);
     for (int64_t k = 0; k < nv; ++k) {
       double un = 0.0;
       for (int d = 0; d < D; ++d) un += u[k * D + d] * fnorm[f * D + d];
@@ -931,7 +924,6 @@ int oracle_ctx::step_once() {
       for (int d = 0; d < D; ++d) un += uk[d] * fnorm[f * D + d];
       int64_t L = fL[f];
       double ih = 0.0, ib = 0.0;
-      const double dt = dt_face(f);
       if (fbc[f] == BC_WALL) {
         int id = fbcid[f];
         double lamw = 1.0 / (2.0 * Rg * bcT[id]);
@@ -1081,10 +1073,9 @@ int oracle_ctx::step_once() {
 // Local time steps (reading R26): on = 1 gives every cell its own step.
 extern "C" void oracle_set_local_dt(oracle_ctx* o, int on) { o->set_local_dt(on != 0); }
 
-// The cells' and faces' steps, [nc] and [nf] (the global dt everywhere when off).
-extern "C" void oracle_local_dt(const oracle_ctx* o, double* dtc, double* dtf) {
+// The cells' steps, [nc] (the global dt everywhere when off).
+extern "C" void oracle_local_dt(const oracle_ctx* o, double* dtc) {
   for (int64_t i = 0; i < o->nc; ++i) dtc[i] = o->dt_cell(i);
-  for (int64_t f = 0; f < o->nf; ++f) dtf[f] = o->dt_face(f);
 }
 
 // Reconstruction order: 1 = first order (all gradients zero), 2 = least squares.

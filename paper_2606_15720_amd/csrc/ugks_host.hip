@@ -381,6 +381,38 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     fail_if(bcs[i].kind != UGKS_BC_OUTFLOW && !(bcs[i].T > 0.0), "boundary temperature must be positive");
   }
   c->bcs = upload(c, hb);
+  // ---- time step (R5), and the local steps of reading R26 -------------------
+  c->gas.Pr = gas->Pr;
+  c->gas.R = gas->R;
+  c->gas.Tref = gas->T_ref;
+  c->gas.muref = gas->mu_ref;
+  c->gas.omega = gas->omega;
+  const bool lts = (c->flags & 128) != 0;
+  fail_if(lts && (c->flags & 64),
+          "local time steps (flags bit 7) and boundary-flux tracking (bit 6) exclude each other");
+  std::vector<double> dtc;
+  {
+    fail_if(!(gas->dt > 0.0) && !(gas->cfl > 0.0), "cfl must be positive when dt = 0");
+    // each cell's bound 2 V_i / max_k sum_j S_j |u_k . n_j|
+    std::vector<double> bound;
+    double mn = INFINITY;
+    if (!(gas->dt > 0.0) || lts) {
+      double* cellv = dalloc<double>(c, nc);
+      HIP_TRY(launch_dt_cells(D, m, v, cellv, c->stream));
+      bound.resize(nc);
+      HIP_TRY(hipMemcpyAsync(bound.data(), cellv, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      for (double x : bound) mn = std::min(mn, x);
+      fail_if(!(mn > 0.0) || !std::isfinite(mn), "could not derive a time step");
+    }
+    c->gas.dt = gas->dt > 0.0 ? gas->dt : gas->cfl * mn;
+    if (lts) {
+      // cell i advances by dt b_i / min b (the most restrictive cell keeps dt)
+      dtc.resize(nc);
+      for (int64_t i = 0; i < nc; ++i) dtc[i] = c->gas.dt * (bound[i] / mn);
+      c->gas.dtc = upload(c, dtc);
+    }
+  }
   if (c->fused) {
     // Static records of the fused sweep: the cell's faces, its least-squares
     // stencil and, per face, the neighbour's stencil, all wave-uniform.
@@ -477,6 +509,8 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
           fd[7 + d] = j >= 0 ? (sg > 0.0 ? fdxR[f * 3 + d] : fdxL[f * 3 + d]) : 0.0;
         }
         fd[3] = p < nfc[i] ? farea[f] / vol[i] : 0.0;
+        // local steps: the face's integral over dt, applied for dt_i
+        if (lts && p < nfc[i]) fd[3] *= dtc[i] / c->gas.dt;
         // equilibrium term of the outgoing member: none at a wall
         fd[22] = (j >= 0 || gr >= 0) ? 1.0 : 0.0;
       }
@@ -644,26 +678,6 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
     for (int x = 0; x < NW; ++x) W0p[i * NW + x] = W0[perm[i] * NW + x];
   HIP_TRY(hipMemcpy(B.W, W0p.data(), nc * NW * sizeof(double), hipMemcpyHostToDevice));
 
-  // ---- time step ----------------------------------------------------------
-  c->gas.Pr = gas->Pr;
-  c->gas.R = gas->R;
-  c->gas.Tref = gas->T_ref;
-  c->gas.muref = gas->mu_ref;
-  c->gas.omega = gas->omega;
-  if (gas->dt > 0.0) {
-    c->gas.dt = gas->dt;
-  } else {
-    fail_if(!(gas->cfl > 0.0), "cfl must be positive when dt = 0");
-    double* cellv = dalloc<double>(c, nc);
-    HIP_TRY(launch_dt_cells(D, m, v, cellv, c->stream));
-    std::vector<double> hc(nc);
-    HIP_TRY(hipMemcpyAsync(hc.data(), cellv, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    double mn = INFINITY;
-    for (double x : hc) mn = std::min(mn, x);
-    fail_if(!(mn > 0.0) || !std::isfinite(mn), "could not derive a time step");
-    c->gas.dt = gas->cfl * mn;
-  }
   // ---- initial distributions: the reduced Maxwellian of W0 ---------------
   HIP_TRY(launch_prims(D, m, c->gas, B.W, B.prim, B.flag, 0, c->stream));
   HIP_TRY(launch_init_maxwellian(D, prec, m, v, B.prim, B.h, B.b, c->stream));
@@ -806,7 +820,7 @@ void enqueue_step(ugks_ctx* c) {
   TIMED(KK_STAGE1, launch_stage1(D, P, m, v, g, B.prim, B.q, B.h, B.b, B.fluxh, B.fluxb, B.ht,
                                 B.bt, B.flag, s));
   // 8 conservative update, 10 new equilibrium
-  TIMED(KK_MACRO, launch_macro_update(D, m, B.W, B.F, B.Wn, B.cellred, B.flag, s));
+  TIMED(KK_MACRO, launch_macro_update(D, m, g, B.W, B.F, B.Wn, B.cellred, B.flag, s));
   TIMED(KK_PRIMS, launch_prims(D, m, g, B.Wn, B.primn, B.flag, 1, s));
   // 11 second stage
   TIMED(KK_STAGE2, launch_stage2(D, P, m, v, g, B.primn, B.q, B.ht, B.bt, B.h, B.b, B.flag, s));
@@ -1118,9 +1132,12 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
   const int fixed_bv = opt ? opt->block_v : 0, fixed_tile = opt ? opt->tile_cells : 0;
   fail_if(fixed_bv < 0 || fixed_bv % WAVE != 0, "block_v must be 0 or a positive multiple of 64");
   fail_if(fixed_tile < 0, "tile_cells must be >= 0");
+  if (opt && (opt->flags & 128))
+    throw std::pair<int, std::string>(UGKS_EUNSUPPORTED,
+                                      "the batched form runs one global step (no local time steps)");
   if (opt && opt->limiter)
     throw std::pair<int, std::string>(UGKS_EUNSUPPORTED,
-                                      "the batched form runs the fused sweep, which has no limiter");
+                                      "the batched sweep has no limiter");
   // every case's arguments, and one dimension for all, before any device work
   for (int32_t i = 0; i < n; ++i) {
     const ugks_case& k = cases[i];

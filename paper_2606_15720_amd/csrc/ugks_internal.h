@@ -129,7 +129,17 @@ struct DevBC {
 
 struct GasP {
   double Pr, R, Tref, muref, omega, dt;
+  // local time steps (flags bit 7): per-cell steps dt_i [nc], or null for
+  // the global dt everywhere.  Faces always integrate over the global dt.
+  const double* dtc = nullptr;
 };
+
+// The step cell i advances by.
+__host__ __device__ inline double dt_cell(const GasP& g, int64_t i) { return g.dtc ? g.dtc[i] : g.dt; }
+// S_f as cell i applies it: times dt_i / dt under local steps
+__host__ __device__ inline double area_for(const GasP& g, int64_t i, double S) {
+  return g.dtc ? S * (g.dtc[i] / g.dt) : S;
+}
 
 // Kernel launchers (ugks_kernels.hip).  Each returns hipGetLastError().
 struct StepBuffers {
@@ -213,7 +223,7 @@ hipError_t launch_stage1(int D, int prec, const DevMesh& m, const DevVel& v, con
                          const double* prim, const double* q, const void* h, const void* b,
                          const double* fh, const double* fb, void* ht, void* bt,
                          const int32_t* flag, hipStream_t s);
-hipError_t launch_macro_update(int D, const DevMesh& m, const double* W, const double* F,
+hipError_t launch_macro_update(int D, const DevMesh& m, const GasP& g, const double* W, const double* F,
                                double* Wn, double* cellred, const int32_t* flag, hipStream_t s);
 hipError_t launch_stage2(int D, int prec, const DevMesh& m, const DevVel& v, const GasP& g,
                          const double* primn, const double* q, const void* ht, const void* bt,

@@ -590,7 +590,7 @@ __global__ __launch_bounds__(TPB) void k_stage1(DevMesh m, DevVel v, GasP g,
   const int nfc = m.nfc[i];
   for (int p = 0; p < nfc; ++p) {
     const int64_t f = m.cface[i * MAXF + p];
-    const double s = m.csign[i * MAXF + p] * m.farea[f];
+    const double s = m.csign[i * MAXF + p] * area_for(g, i, m.farea[f]);
     sh += s * fh[f * nvp + k];
     if (D == 2) sb += s * fb[f * nvp + k];
   }
@@ -599,7 +599,7 @@ __global__ __launch_bounds__(TPB) void k_stage1(DevMesh m, DevVel v, GasP g,
   for (int d = 0; d < D; ++d) uk[d] = v.u[d * nvp + k];
   double Hs, Bs;
   cell_equilibrium<D>(P, &q[i * 3], g.Pr, uk, Hs, Bs);
-  const double c = g.dt / (2.0 * P[5]);
+  const double c = dt_cell(g, i) / (2.0 * P[5]);
   const double iv = 1.0 / m.vol[i];
   const double hv = ld(h, i * nvp + k);
   st(ht, i * nvp + k, hv - sh * iv + c * (Hs - hv));
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(TPB) void k_stage1(DevMesh m, DevVel v, GasP g,
 
 // Conservative update (Eq. macro_update) and per-cell residual parts.
 template <int D>
-__global__ void k_macro_update(DevMesh m, const double* __restrict__ W, const double* __restrict__ F,
+__global__ void k_macro_update(DevMesh m, GasP g, const double* __restrict__ W, const double* __restrict__ F,
                                double* __restrict__ Wn, double* __restrict__ cellred,
                                const int32_t* flag) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -620,7 +620,7 @@ __global__ void k_macro_update(DevMesh m, const double* __restrict__ W, const do
   const int nfc = m.nfc[i];
   for (int p = 0; p < nfc; ++p) {
     const int64_t f = m.cface[i * MAXF + p];
-    const double s = m.csign[i * MAXF + p] * m.farea[f];
+    const double s = m.csign[i * MAXF + p] * area_for(g, i, m.farea[f]);
     for (int x = 0; x < D + 2; ++x) acc[x] += s * F[f * 5 + x];
   }
   const double V = m.vol[i];
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(TPB) void k_stage2(DevVel v, GasP g, const double* 
   for (int d = 0; d < D; ++d) uk[d] = v.u[d * nvp + k];
   double Hs, Bs;
   cell_equilibrium<D>(P, &q[i * 3], g.Pr, uk, Hs, Bs);
-  const double a = g.dt / (2.0 * P[5]);
+  const double a = dt_cell(g, i) / (2.0 * P[5]);
   const double inv = 1.0 / (1.0 + a);
   st(h, i * nvp + k, (ld(ht, i * nvp + k) + a * Hs) * inv);
   if (D == 2) st(b, i * nvp + k, (ld(bt, i * nvp + k) + a * Bs) * inv);
@@ -872,9 +872,9 @@ hipError_t launch_stage1(int D, int prec, const DevMesh& m, const DevVel& v, con
   return hipGetLastError();
 }
 
-hipError_t launch_macro_update(int D, const DevMesh& m, const double* W, const double* F,
+hipError_t launch_macro_update(int D, const DevMesh& m, const GasP& g, const double* W, const double* F,
                                double* Wn, double* cellred, const int32_t* flag, hipStream_t s) {
-  UGKS_DISPATCH_D(D, k_macro_update<DD><<<blocks_for(m.nc, 256), 256, 0, s>>>(m, W, F, Wn, cellred, flag));
+  UGKS_DISPATCH_D(D, k_macro_update<DD><<<blocks_for(m.nc, 256), 256, 0, s>>>(m, g, W, F, Wn, cellred, flag));
   return hipGetLastError();
 }
 

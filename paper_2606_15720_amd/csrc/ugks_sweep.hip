@@ -135,7 +135,7 @@ __device__ __forceinline__ void cell_prep_at(int64_t i, const GasP& g, const dou
   Cb::add_shakhov(SH, sh, U, qc, lam, 2.0 + D);
   Cb::add_shakhov(SB, sh, U, qc, lam, (double)D);
   double* C = &cs[i * CSREC];
-  C[CS_CC] = g.dt / (2.0 * P[5]);
+  C[CS_CC] = dt_cell(g, i) / (2.0 * P[5]);
   C[CS_KAP] = (3 - D) / (2.0 * lam);
   C[CS_NORM] = rho * maxw_norm<D>(lam);
   for (int x = 0; x < 20; ++x) {

@@ -268,14 +268,16 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
            "nv_predictor": case_coarse.vel.nv, "target": target, "flags": flags,
            "limiter": limiter, "limiter_k": limiter_k}
     lim = dict(limiter=limiter, limiter_k=limiter_k)
-    t0 = time.perf_counter()
-    F, T = build_training_set(train_seed, log=log, blunt=blunt)
-    t1 = time.perf_counter()
-    net, losses = train(F, T, seed=train_seed, steps=4000, batch=1024)
-    t2 = time.perf_counter()
-    out["training"] = {"samples": int(len(F)), "blunt_body_flows": bool(blunt),
-                       "snapshot_s": t1 - t0, "train_s": t2 - t1,
-                       "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+    net = None
+    if any(a.startswith("learned") for a in arms_run):
+        t0 = time.perf_counter()
+        F, T = build_training_set(train_seed, log=log, blunt=blunt)
+        t1 = time.perf_counter()
+        net, losses = train(F, T, seed=train_seed, steps=4000, batch=1024)
+        t2 = time.perf_counter()
+        out["training"] = {"samples": int(len(F)), "blunt_body_flows": bool(blunt),
+                           "snapshot_s": t1 - t0, "train_s": t2 - t1,
+                           "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
     arms = {}
 
     def arm(name, precision, W0=None, warm=False, extra_s=0.0):
@@ -323,7 +325,8 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
         arms["plain64"]["field_error_vs_plain64_deep"] = field_errors(Wref, Wdeep, D)
     if not any(a in arms_run for a in ("maxwell32", "learned32", "learned64")):
         out["arms"] = arms
-        net.close()
+        if net is not None:
+            net.close()
         return out
     t = time.perf_counter()
     p = U.Solver(case_coarse, precision=U.UGKS_FP32, flags=flags, **lim)
@@ -344,5 +347,6 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
             if name in deep:
                 arms[name]["deep"]["field_error_vs_plain64_deep"] = field_errors(deep[name], Wdeep, D)
     out["arms"] = arms
-    net.close()
+    if net is not None:
+        net.close()
     return out

@@ -90,8 +90,12 @@ STAGED = 2  # ugks_options.flags bit: force the staged (unfused) sweep
 FIRST_ORDER = 16  # ugks_options.flags bit: first-order reconstruction
 
 
+LOCAL_DT = 128  # ugks_options.flags bit: local time steps (reading R26)
+
+
 def _compare_step(case, steps, flags=0, tol=TOL, limiter=0, limiter_k=0.0):
-    o = Oracle(case, order=1 if flags & FIRST_ORDER else 2, limiter=limiter, limiter_k=limiter_k)
+    o = Oracle(case, order=1 if flags & FIRST_ORDER else 2, limiter=limiter, limiter_k=limiter_k,
+               local_dt=bool(flags & LOCAL_DT))
     s = Solver(case, flags=flags, limiter=limiter, limiter_k=limiter_k)
     assert s.dt == pytest.approx(o.dt, rel=1e-14)
     done = 0
@@ -513,3 +517,57 @@ def test_boundary_flux_needs_tracking_and_is_partial_with_far_field_on_the_fused
     _, complete = s.boundary_flux()
     assert not complete
     s.close()
+
+
+def _local_dt_case(which):
+    if which == "cylinder":
+        # 2-D O-grid graded toward a diffuse wall, Mach 2, far field
+        return uc.cylinder2d(n_theta=16, n_r=8, nv=12, a=8.0, kn=0.05, mach=2.0, first=0.05,
+                             start="freestream"), 8, {}
+    if which == "sphere":
+        # 3-D cubed-sphere shell at Mach 5: second order needs the limiter
+        return uc.sphere_mach5(n_ang=2, n_rad=4, nv=10, first=0.3), 6, dict(limiter=1, limiter_k=0.0)
+    if which == "tets":
+        return uc.sod3d_tets(n=3, nv=8, jitter=0.3, seed=4), 6, {}
+    # six-faced cells (staged sweep only), graded spacing, isothermal walls
+    case = uc.Case("hexes", uc.hex_box(4, 3, 3, grading=0.6, seed=5), uc.midpoint_grid(8, 4.0, 3),
+                   uc.Gas(mu_ref=uc.hard_sphere_mu_ref(0.05)),
+                   [uc.BC(uc.BC_WALL, 1.0, (0.0, 0.0, 0.0), 1.0 + 0.1 * s) for s in range(6)], None, 0)
+    case.W0 = uc.uniform_W(case.mesh.n_cells, 3, 1.0, (0.1, 0.0, 0.0), 1.0)
+    case.W0[:, 0] *= 1.0 + 0.2 * np.random.default_rng(3).uniform(-1, 1, case.mesh.n_cells)
+    return case, 6, {}
+
+
+@pytest.mark.parametrize("which,flags", [("cylinder", 0), ("cylinder", STAGED), ("sphere", 0),
+                                         ("sphere", STAGED), ("tets", 0), ("tets", STAGED),
+                                         ("hexes", STAGED)])
+def test_local_time_steps_follow_the_oracle(which, flags):
+    """Local time steps (reading R26) on graded meshes: every face's flux over
+    the global dt, every cell's update and relaxation for its own dt_i, on both
+    sweeps (cells with six faces run the staged one only)."""
+    case, steps, lim = _local_dt_case(which)
+    o = Oracle(case, local_dt=True)
+    dtc = o.local_dt()
+    print(which, "local steps from", dtc.min(), "to", dtc.max(), flush=True)
+    assert dtc.max() > 1.3 * dtc.min()
+    del o
+    _compare_step(case, steps, flags=flags | LOCAL_DT, **lim)
+
+
+def test_local_time_steps_fp32_form_against_fp64_oracle():
+    case, _, _ = _local_dt_case("cylinder")
+    o = Oracle(case, local_dt=True)
+    s = Solver(case, precision=UGKS_FP32, flags=LOCAL_DT)
+    o.step(20)
+    s.step(20)
+    err = _normwise(s.W(), o.state(with_h=False)[0])
+    print("FP32 form with local steps, normwise error after 20 steps:", err, flush=True)
+    assert np.all(err < 1e-5)
+    s.close()
+
+
+def test_local_time_steps_refuse_boundary_flux_tracking():
+    case = uc.cavity2d(n=4, nv=6)
+    with pytest.raises(UGKSError) as e:
+        Solver(case, flags=LOCAL_DT | TRACK)
+    assert e.value.code == -1 and "local time steps" in str(e.value)

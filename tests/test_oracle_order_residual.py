@@ -49,12 +49,12 @@ def _maxwellian(u, rho, U, lam, D):
     return rho * (lam / math.pi) ** (D / 2.0) * np.exp(-lam * d2)
 
 
-def _first_order_step(case, W, h, b, dt, collisionless=False, dtc=None, dtf=None):
+def _first_order_step(case, W, h, b, dt, collisionless=False, dtc=None):
     """One first-order step (Pr = 1) written from Sec. 2.1; see the header.
 
-    With per-cell and per-face steps dtc, dtf (local time steps, reading R26)
-    face f integrates over dtf[f], cell i relaxes over dtc[i] and applies each
-    face's integral scaled by dtc[i] / dtf[f]."""
+    With per-cell steps dtc (local time steps, reading R26) every face still
+    integrates over dt, and cell i applies each face's integral scaled by
+    dtc[i] / dt and relaxes over dtc[i]."""
     m, v, gas = case.mesh, case.vel, case.gas
     assert gas.Pr == 1.0
     D = m.dim
@@ -73,9 +73,9 @@ def _first_order_step(case, W, h, b, dt, collisionless=False, dtc=None, dtf=None
         S = m.face_area[f]
         un = u @ n
         bc = m.face_bc[f]
-        dt_f = dt if dtf is None else dtf[f]
-        rL = 1.0 if dtc is None else dtc[L] / dt_f
-        rR = 1.0 if dtc is None or bc != uc.BC_INTERIOR else dtc[R] / dt_f
+        dt_f = dt
+        rL = 1.0 if dtc is None else dtc[L] / dt
+        rR = 1.0 if dtc is None or bc != uc.BC_INTERIOR else dtc[R] / dt
         if bc == uc.BC_WALL:
             t = case.bcs[m.face_bc_id[f]]
             lamw = 1.0 / (2.0 * gas.R * t.T)
