@@ -323,7 +323,7 @@ def run_warm_start(args):
                               ref_out=args.ws_save_ref or None, ref_in=args.ws_ref or None,
                               deep_target=args.ws_deep or None, deep_max_steps=args.ws_max_steps,
                               flags=(0 if second else 16) | (128 if args.ws_local_dt else 0),
-                              limiter=1 if second else 0,
+                              limiter=1 if second else 0, chunk=args.ws_chunk,
                               limiter_k=args.ws_limiter_k, blunt=not args.ws_no_blunt)
     out["metric"] = "time to 1e-6 density residual (s)"
     out["reconstruction"] = (f"second order with Venkatakrishnan's limiter, K = {args.ws_limiter_k}"
@@ -472,6 +472,8 @@ def main():
                     help="Venkatakrishnan's K at second order")
     ap.add_argument("--ws-no-blunt", action="store_true",
                     help="train without the supersonic cylinder flows")
+    ap.add_argument("--ws-chunk", type=int, default=1000,
+                    help="steps between residual checks (step counts are rounded up to it)")
     ap.add_argument("--ws-local-dt", action="store_true",
                     help="every arm with local time steps (each cell its own step)")
     ap.add_argument("--ws-compare", default="",
