@@ -56,12 +56,12 @@ def _load():
     lib.oracle_get_faces.argtypes = [P, P, P, P, P]
     lib.oracle_gamma.argtypes = [d, d, P]
     lib.oracle_half_moments.argtypes = [d, d, i32, i32, P]
-    lib.oracle_interface_state.restype = i32
-    lib.oracle_interface_state.argtypes = [i32, P, P, P, P]
-    lib.oracle_slopes.restype = i32
-    lib.oracle_slopes.argtypes = [i32, d, P, d, P, P, P]
-    lib.oracle_gram.argtypes = [i32, P, d, P]
-    lib.oracle_gram_u.argtypes = [i32, P, d, P]
+    lib.oracle_interface_state_k.restype = i32
+    lib.oracle_interface_state_k.argtypes = [i32, i32, P, P, P, P]
+    lib.oracle_slopes_k.restype = i32
+    lib.oracle_slopes_k.argtypes = [i32, i32, d, P, d, P, P, P]
+    lib.oracle_gram_k.argtypes = [i32, i32, P, d, P]
+    lib.oracle_gram_u_k.argtypes = [i32, i32, P, d, P]
     lib.oracle_ls_coeffs.restype = i32
     lib.oracle_ls_coeffs.argtypes = [P, i64, P]
     lib.oracle_last_error.restype = C.c_char_p
@@ -236,37 +236,37 @@ def half_moments(Un: float, lam: float, sign: int, nm: int = 3) -> np.ndarray:
     return out
 
 
-def interface_state(Wl, Wr, n) -> np.ndarray:
+def interface_state(Wl, Wr, n, K: int = 0) -> np.ndarray:
     Wl, Wr, n = _f8(Wl), _f8(Wr), _f8(n)
     D = n.shape[0]
     out = np.zeros(D + 2)
-    _load().oracle_interface_state(D, _p(Wl), _p(Wr), _p(n), _p(out))
+    _load().oracle_interface_state_k(D, int(K), _p(Wl), _p(Wr), _p(n), _p(out))
     return out
 
 
-def slopes(rho: float, U, lam: float, dW):
+def slopes(rho: float, U, lam: float, dW, K: int = 0):
     U = _f8(U)
     dW = _f8(dW)
     D = U.shape[0]
     a = np.zeros((D, D + 2))
     A = np.zeros(D + 2)
-    rc = _load().oracle_slopes(D, rho, _p(U), lam, _p(dW), _p(a), _p(A))
+    rc = _load().oracle_slopes_k(D, int(K), rho, _p(U), lam, _p(dW), _p(a), _p(A))
     if rc:
         raise RuntimeError("slope solve failed")
     return a, A
 
 
-def gram(U, lam: float) -> np.ndarray:
+def gram(U, lam: float, K: int = 0) -> np.ndarray:
     U = _f8(U)
     D = U.shape[0]
     M = np.zeros((D + 2, D + 2))
-    _load().oracle_gram(D, _p(U), lam, _p(M))
+    _load().oracle_gram_k(D, int(K), _p(U), lam, _p(M))
     return M
 
 
-def gram_u(U, lam: float) -> np.ndarray:
+def gram_u(U, lam: float, K: int = 0) -> np.ndarray:
     U = _f8(U)
     D = U.shape[0]
     M = np.zeros((D, D + 2, D + 2))
-    _load().oracle_gram_u(D, _p(U), lam, _p(M))
+    _load().oracle_gram_u_k(D, int(K), _p(U), lam, _p(M))
     return M

@@ -7,9 +7,9 @@
 //
 // What it computes (paper Sec. 2.1 and the one-step algorithm of Sec. 2.2):
 //   * BGK-Shakhov model with reduced distributions h = int f dxi and
-//     b = int xi^2 f dxi (Eqs. reduced_hb, reduced_bgk), monatomic gas K = 0,
-//     K_xi = 3 - D (Eq. Kxi_def).  In 3-D K_xi = 0, so b = B = B+ = 0 and b is
-//     not stored.
+//     b = int xi^2 f dxi (Eqs. reduced_hb, reduced_bgk), K >= 0 internal
+//     degrees of freedom, K_xi = K + 3 - D (Eq. Kxi_def).  For a monatomic
+//     gas in 3-D K_xi = 0, so b = B = B+ = 0 and b is not stored.
 //   * Reduced Maxwellian H, B (Eqs. H_def, B_def) and Shakhov corrections
 //     H+, B+ (Eqs. H_plus, B_plus).
 //   * Finite-volume update with time-integrated interface fluxes
@@ -24,6 +24,12 @@
 //   * Two-stage trapezoidal collision update (Eqs. f_tilde, f_final).
 //
 // Readings of points the paper leaves open (the same ones the library uses):
+//   R1 K > 0: the Shakhov correction g A c.q (2 lambda (c^2 + xi^2) - alpha)
+//      of Eq. shakhov_fp takes alpha = K + 5 (zero momentum) and
+//      A = 4 (1 - Pr) lambda^2 / ((K + 5) rho) (heat flux (1 - Pr) q), so
+//      H+ = A c.q (2 lambda c^2 - D - 2) H and
+//      B+ = A c.q (K_xi / 2 lambda)(2 lambda c^2 - D) H; for K = 0 these are
+//      Eqs. H_plus, B_plus.  lambda = (K + 3) rho / (4 (rho E - rho U^2 / 2)).
 //   R2 units rho0 = T0 = 1, speed unit sqrt(2RT0), R = 1/2.
 //   R3 hard-sphere viscosity mu = mu_ref (T/T_ref)^omega, tau = mu / p.
 //   R5 dt = CFL * min_i 2 V_i / max_k sum_{j in faces(i)} S_j |u_k . n_j|.
@@ -235,7 +241,7 @@ struct Prim {
 
 // ---------------------------------------------------------------------------
 struct oracle_ctx {
-  int D, kxi, nr, nbc, limiter;
+  int D, K, kxi, nr, nbc, limiter;
   int64_t nc, nf, nv;
   double Pr, Rg, Tref, muref, omega, dt;
   std::vector<double> vol, cen, farea, fnorm, fcen, fshift;
@@ -275,7 +281,7 @@ struct oracle_ctx {
       u2 += p.U[d] * p.U[d];
     }
     double eint = Wc[D + 1] - 0.5 * p.rho * u2;  // = 3 rho / (4 lambda)
-    p.lam = 3.0 * p.rho / (4.0 * eint);
+    p.lam = (K + 3.0) * p.rho / (4.0 * eint);
     p.ok = (p.rho > 0.0) && (eint > 0.0) && std::isfinite(p.lam);
     double pres = p.rho / (2.0 * p.lam);
     double T = 1.0 / (2.0 * Rg * p.lam);
@@ -302,7 +308,7 @@ struct oracle_ctx {
       cq += c * qv[d];
       c2 += c * c;
     }
-    double pre = 4.0 * (1.0 - Pr) * lam * lam / (5.0 * rho) * cq;
+    double pre = 4.0 * (1.0 - Pr) * lam * lam / ((K + 5.0) * rho) * cq;
     Hp = pre * (2.0 * lam * c2 - 2.0 - D) * H;
     Bp = pre * (2.0 * lam * c2 - D) * kxi / (2.0 * lam) * H;
   }
@@ -513,10 +519,11 @@ oracle_ctx* oracle_create(int D, int64_t nc, int64_t nf, const double* vol, cons
                           int K, double Pr, double Rg, double Tref, double muref, double omega,
                           double cfl, double dt, int nbc, const int32_t* bckind, const double* bcrho,
                           const double* bcU, const double* bcT, const double* W0) {
-  if ((D != 2 && D != 3) || K != 0 || nc <= 0 || nf <= 0 || nv <= 0) return nullptr;
+  if ((D != 2 && D != 3) || K < 0 || nc <= 0 || nf <= 0 || nv <= 0) return nullptr;
   oracle_ctx* o = new oracle_ctx();
   o->D = D;
-  o->kxi = 3 - D;
+  o->K = K;
+  o->kxi = K + 3 - D;
   o->nr = o->kxi > 0 ? 2 : 1;
   o->nc = nc; o->nf = nf; o->nv = nv;
   o->Pr = Pr; o->Rg = Rg; o->Tref = Tref; o->muref = muref; o->omega = omega;
@@ -640,27 +647,37 @@ void oracle_half_moments(double Un, double lam, int sign, int nm, double* out) {
   for (int m = 0; m + 2 < nm; ++m) out[m + 2] = Un * out[m + 1] + (m + 1) / (2.0 * lam) * out[m];
 }
 
-// Interface state W0 from left/right conservative states and the unit normal.
-int oracle_interface_state(int D, const double* Wl, const double* Wr, const double* n, double* W0);
+// Interface state W0 from left/right conservative states and the unit normal
+// (a gas of K internal degrees of freedom).
+int oracle_interface_state_k(int D, int K, const double* Wl, const double* Wr, const double* n,
+                             double* W0);
+int oracle_interface_state(int D, const double* Wl, const double* Wr, const double* n, double* W0) {
+  return oracle_interface_state_k(D, 0, Wl, Wr, n, W0);
+}
 
 // Slopes: given the interface state (rho, U, lam) and conservative-variable
 // derivatives dW (D rows of D+2), return the spatial slopes a (D x (D+2)) and the
 // time slope A (D+2), each in the psi basis (step 6.4-6.5).
+int oracle_slopes_k(int D, int K, double rho, const double* U, double lam, const double* dW,
+                    double* a, double* A);
 int oracle_slopes(int D, double rho, const double* U, double lam, const double* dW, double* a,
-                  double* A);
+                  double* A) {
+  return oracle_slopes_k(D, 0, rho, U, lam, dW, a, A);
+}
 
 // Gram matrix E[psi psi^T] (normalised) for a check of the solve.
-void oracle_gram(int D, const double* U, double lam, double* M) {
-  Gauss g{D, 3 - D, {0, 0, 0}, 1.0 / (2.0 * lam)};
+void oracle_gram_k(int D, int K, const double* U, double lam, double* M) {
+  Gauss g{D, K + 3 - D, {0, 0, 0}, 1.0 / (2.0 * lam)};
   for (int d = 0; d < D; ++d) g.U[d] = U[d];
   std::vector<Poly> psi = invariants(D);
   std::vector<double> G = gram(g, psi);
   std::copy(G.begin(), G.end(), M);
 }
+void oracle_gram(int D, const double* U, double lam, double* M) { oracle_gram_k(D, 0, U, lam, M); }
 
 // E[u_d psi psi^T] (normalised), D x (D+2) x (D+2).
-void oracle_gram_u(int D, const double* U, double lam, double* Mu) {
-  Gauss g{D, 3 - D, {0, 0, 0}, 1.0 / (2.0 * lam)};
+void oracle_gram_u_k(int D, int K, const double* U, double lam, double* Mu) {
+  Gauss g{D, K + 3 - D, {0, 0, 0}, 1.0 / (2.0 * lam)};
   for (int d = 0; d < D; ++d) g.U[d] = U[d];
   std::vector<Poly> psi = invariants(D);
   int n = D + 2;
@@ -673,6 +690,7 @@ void oracle_gram_u(int D, const double* U, double lam, double* Mu) {
       for (int b = 0; b < n; ++b) Mu[(d * n + a) * n + b] = g.expect(poly_mul(ud, poly_mul(psi[a], psi[b])));
   }
 }
+void oracle_gram_u(int D, const double* U, double lam, double* Mu) { oracle_gram_u_k(D, 0, U, lam, Mu); }
 
 // Least-squares coefficients of cell i (D x m, row-major) and m.
 int oracle_ls_coeffs(const oracle_ctx* o, int64_t i, double* G) {
@@ -684,8 +702,9 @@ int oracle_ls_coeffs(const oracle_ctx* o, int64_t i, double* G) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-int oracle_interface_state(int D, const double* Wl, const double* Wr, const double* n, double* W0) {
-  const int kxi = 3 - D;
+int oracle_interface_state_k(int D, int K, const double* Wl, const double* Wr, const double* n,
+                             double* W0) {
+  const int kxi = K + 3 - D;
   const double* Ws[2] = {Wl, Wr};
   int sgn[2] = {+1, -1};
   for (int v = 0; v < D + 2; ++v) W0[v] = 0.0;
@@ -693,7 +712,7 @@ int oracle_interface_state(int D, const double* Wl, const double* Wr, const doub
     const double* Wc = Ws[s];
     double rho = Wc[0], U[3] = {0, 0, 0}, u2 = 0.0;
     for (int d = 0; d < D; ++d) { U[d] = Wc[1 + d] / rho; u2 += U[d] * U[d]; }
-    double lam = 3.0 * rho / (4.0 * (Wc[D + 1] - 0.5 * rho * u2));
+    double lam = (K + 3.0) * rho / (4.0 * (Wc[D + 1] - 0.5 * rho * u2));
     double Un = 0.0;
     for (int d = 0; d < D; ++d) Un += U[d] * n[d];
     double Ut[3], ut2 = 0.0;
@@ -707,9 +726,9 @@ int oracle_interface_state(int D, const double* Wl, const double* Wr, const doub
   return 0;
 }
 
-int oracle_slopes(int D, double rho, const double* U, double lam, const double* dW, double* a,
-                  double* A) {
-  Gauss g{D, 3 - D, {0, 0, 0}, 1.0 / (2.0 * lam)};
+int oracle_slopes_k(int D, int K, double rho, const double* U, double lam, const double* dW,
+                    double* a, double* A) {
+  Gauss g{D, K + 3 - D, {0, 0, 0}, 1.0 / (2.0 * lam)};
   for (int d = 0; d < D; ++d) g.U[d] = U[d];
   std::vector<Poly> psi = invariants(D);
   int n = D + 2;
@@ -818,7 +837,7 @@ int oracle_ctx::step_once() {
       for (int v = 0; v < nw; ++v) Wl[v] = W[L * nw + v];
     if (!prim(Wr).ok)
       for (int v = 0; v < nw; ++v) Wr[v] = ghost ? Wg[f * nw + v] : W[R * nw + v];
-    oracle_interface_state(D, Wl, Wr, &fnorm[f * D], e.W0);
+    oracle_interface_state_k(D, K, Wl, Wr, &fnorm[f * D], e.W0);
     Prim p0 = prim(e.W0);
     if (!p0.ok) { bad = true; continue; }
     e.rho0 = p0.rho; e.lam0 = p0.lam; e.tau0 = p0.tau;
@@ -829,7 +848,7 @@ int oracle_ctx::step_once() {
       for (int v = 0; v < nw; ++v)
         dW[d * nw + v] = 0.5 * (gW[(L * D + d) * nw + v] + (ghost ? 0.0 : gW[(R * D + d) * nw + v]));
     double a[15], A[5];
-    if (oracle_slopes(D, p0.rho, p0.U, p0.lam, dW, a, A)) { bad = true; continue; }
+    if (oracle_slopes_k(D, K, p0.rho, p0.U, p0.lam, dW, a, A)) { bad = true; continue; }
     for (int d = 0; d < D; ++d)
       for (int v = 0; v < nw; ++v) e.a[d][v] = a[d * nw + v];
     for (int v = 0; v < nw; ++v) e.A[v] = A[v];

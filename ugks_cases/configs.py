@@ -62,10 +62,11 @@ class Case:
         return self.mesh.n_cells * self.vel.nv
 
 
-def uniform_W(n_cells: int, dim: int, rho, U, T) -> np.ndarray:
-    """Conservative state (rho, rho U, rho E) of a monatomic ideal gas.
+def uniform_W(n_cells: int, dim: int, rho, U, T, K: int = 0) -> np.ndarray:
+    """Conservative state (rho, rho U, rho E) of an ideal gas with K internal
+    degrees of freedom (K = 0: monatomic).
 
-    rho E = rho |U|^2 / 2 + (3/2) rho R T; ``rho``, ``T`` may be per-cell arrays.
+    rho E = rho |U|^2 / 2 + ((K + 3)/2) rho R T; ``rho``, ``T`` may be per-cell arrays.
     """
     rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), (n_cells,))
     T = np.broadcast_to(np.asarray(T, dtype=np.float64), (n_cells,))
@@ -73,7 +74,7 @@ def uniform_W(n_cells: int, dim: int, rho, U, T) -> np.ndarray:
     W = np.zeros((n_cells, dim + 2))
     W[:, 0] = rho
     W[:, 1:1 + dim] = rho[:, None] * U
-    W[:, dim + 1] = 0.5 * rho * np.sum(U * U, axis=1) + 1.5 * rho * R_GAS * T
+    W[:, dim + 1] = 0.5 * rho * np.sum(U * U, axis=1) + 0.5 * (K + 3) * rho * R_GAS * T
     return np.ascontiguousarray(W)
 
 
