@@ -300,6 +300,7 @@ def run_sphere(steps: int, warmup: int):
 
 def run_warm_start(args):
     """Time to a steady density residual, plain FP64 against the learned start."""
+    import numpy as np
     import ugks_cases as uc
     from paper_2606_15720_amd import warmstart as WS
 
@@ -324,6 +325,7 @@ def run_warm_start(args):
                               deep_target=args.ws_deep or None, deep_max_steps=args.ws_max_steps,
                               flags=(0 if second else 16) | (128 if args.ws_local_dt else 0),
                               limiter=1 if second else 0, chunk=args.ws_chunk,
+                              deep_ref=np.load(args.ws_deep_ref) if args.ws_deep_ref else None,
                               limiter_k=args.ws_limiter_k, blunt=not args.ws_no_blunt)
     out["metric"] = "time to 1e-6 density residual (s)"
     out["reconstruction"] = (f"second order with Venkatakrishnan's limiter, K = {args.ws_limiter_k}"
@@ -336,7 +338,6 @@ def run_warm_start(args):
     if args.ws_compare and args.ws_save_ref and args.ws_deep:
         # another run's final W (for example the global step's at the target)
         # against this run's plain FP64 arm continued to the deep residual
-        import numpy as np
         Wd = np.load(args.ws_save_ref.replace(".npy", "") + "_deep.npy")
         Wc = np.load(args.ws_compare)
         out["compare"] = {"state": os.path.basename(args.ws_compare),
@@ -476,6 +477,8 @@ def main():
                     help="steps between residual checks (step counts are rounded up to it)")
     ap.add_argument("--ws-local-dt", action="store_true",
                     help="every arm with local time steps (each cell its own step)")
+    ap.add_argument("--ws-deep-ref", default="",
+                    help="a W (.npy) converged further, compared with every arm's final W")
     ap.add_argument("--ws-compare", default="",
                     help="a W (.npy) to compare with the plain arm's deep state")
     ap.add_argument("--ws-start", default="freestream",

@@ -244,7 +244,7 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
                      max_steps=60000, chunk=1000, flags=16, train_seed=4, log=None,
                      arms_run=("plain64", "maxwell32", "learned32", "learned64"),
                      ref_out=None, ref_in=None, deep_target=None, deep_max_steps=200000,
-                     limiter=0, limiter_k=0.0, blunt=True):
+                     limiter=0, limiter_k=0.0, blunt=True, deep_ref=None):
     """Plain FP64 from the initial state against predictor + learned warm start.
 
     Arms (all to a density residual <= target, wall time from creation):
@@ -261,7 +261,9 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
     fields of each arm (at `target` and at `deep_target`) are compared with
     the plain FP64 arm's at `deep_target`: at `target` the remaining error
     of any run is about target * (decay time in steps), so a reference
-    converged further is what makes a field tolerance meaningful.
+    converged further is what makes a field tolerance meaningful.  A
+    `deep_ref` W (such a state from an earlier run) is compared with every
+    arm's final W instead, without running on.
     """
     import time
     out = {"case": case_fine.name, "n_cells": case_fine.mesh.n_cells, "nv": case_fine.vel.nv,
@@ -299,6 +301,8 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
                       "fallback_cells": nfall,
                       "r20": {"steps_to_target": r20.get("steps"), "last": r20.get("last"),
                               "note": "residual normalised by this run's own first density change"}}
+        if deep_ref is not None:
+            arms[name]["field_error_vs_deep_ref"] = field_errors(W, deep_ref, case_fine.mesh.dim)
         if deep_target:
             ds, dr, dok = run_to_residual(s, deep_target, deep_max_steps, chunk, log, name + "-deep")
             deep[name] = s.W()
