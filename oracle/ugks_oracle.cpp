@@ -330,7 +330,7 @@ struct oracle_ctx {
         Wg[1 + d] = rho * bcU[id * 3 + d];
         U2 += bcU[id * 3 + d] * bcU[id * 3 + d];
       }
-      Wg[D + 1] = 0.5 * rho * U2 + 1.5 * rho * Rg * T;
+      Wg[D + 1] = 0.5 * rho * U2 + 0.5 * (K + 3.0) * rho * Rg * T;  // K internal degrees (R1)
     } else {
       for (int v = 0; v < NW(); ++v) Wg[v] = WL[v];
     }

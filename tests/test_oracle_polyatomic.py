@@ -19,7 +19,8 @@ Pinned here against what K fixes independently of the oracle's code:
 - the homogeneous Shakhov heat-flux decay (1 + a (1 - 2 Pr)) / (1 + a) for a
   Grad-type f with the (K + 5) / 2 shift;
 - a uniform gas at rest stays, 2-D and 3-D (b in 3-D too), and the discrete
-  conservation balance holds;
+  conservation balance holds; a uniform stream through far-field and outflow
+  faces stays (the free stream's energy is (K + 3)/2 rho R T);
 - a sound wave runs at sqrt(gamma R T), gamma = (K + 5) / (K + 3), and decays
   at the Navier-Stokes-Fourier rate with the BGK bulk viscosity
   mu (2/3 - 2/(K + 3)).
@@ -251,6 +252,32 @@ def test_conservation_balance_with_internal_dof(dim):
     if dim == 3:
         _, h, b, _ = o.state()
         assert np.abs(b - 1.0 * h).max() > 1e-6 * b.max()
+
+
+@pytest.mark.parametrize("dim,kind", [(2, uc.BC_FARFIELD), (3, uc.BC_FARFIELD), (2, uc.BC_OUTFLOW)])
+def test_uniform_stream_through_open_boundaries_with_internal_dof(dim, kind):
+    # the free stream of temperature T carries the energy (K + 3)/2 rho R T:
+    # a box open on every side keeps it (reading R16 with K = 2; Pr = 1 keeps
+    # the discrete heat flux inert)
+    K = 2
+    U = (0.4, -0.25, 0.15)[:dim]
+    if dim == 2:
+        mesh, nb, nv = uc.quad_mesh(5, 5, wall_ids=(0, 0, 0, 0)), 1, 14
+    else:
+        mesh, nb, nv = uc.kuhn_tet_cube(2, jitter=0.15, seed=2), 6, 8
+    bnd = mesh.face_bc != uc.BC_INTERIOR
+    mesh.face_bc = np.where(bnd, kind, mesh.face_bc).astype(mesh.face_bc.dtype)
+    bcs = [uc.BC(kind, 1.0, tuple(U) + (0.0,) * (3 - dim), 1.0) for _ in range(nb)]
+    gas = uc.Gas(K=K, mu_ref=uc.hard_sphere_mu_ref(0.05), Pr=1.0)
+    case = uc.Case("stream", mesh, uc.midpoint_grid(nv, 5.0, dim), gas, bcs,
+                   uc.uniform_W(mesh.n_cells, dim, 1.0, U, 1.0, K=K), 0)
+    o = Oracle(case)
+    W0, h0, b0, _ = o.state()
+    o.step(6)
+    W, h, b, _ = o.state()
+    np.testing.assert_allclose(W, W0, rtol=0, atol=2e-14)
+    np.testing.assert_allclose(h, h0, rtol=0, atol=2e-14 * h0.max())
+    np.testing.assert_allclose(b, b0, rtol=0, atol=2e-14 * b0.max())
 
 
 def test_sound_wave_with_internal_dof():
