@@ -25,10 +25,14 @@
  *     global mutable state; calls on different contexts are independent.
  *   - Units are the caller's; the workloads of this project use rho0 = 1,
  *     T0 = 1, length 1, speed sqrt(2 R T0) (so R = 1/2).
- *   - Only monatomic gases (K = 0) are supported: then K_xi = 3 - D and, in
- *     3-D, b = B = B+ = 0 so only h is stored.  K > 0 returns
- *     UGKS_EUNSUPPORTED (the reduced Shakhov b-equation, Eq. B_plus, is only
- *     consistent with the Shakhov model, Eq. shakhov_fp, for K = 0).
+ *   - A gas has K >= 0 internal degrees of freedom; K_xi = K + 3 - D
+ *     (Eq. Kxi_def).  For a monatomic gas in 3-D, K_xi = 0 and b = B = B+ = 0,
+ *     so only h is stored; otherwise h and b are.  For K > 0 the Shakhov
+ *     correction of Eq. shakhov_fp takes (2 lambda (c^2 + xi^2) - (K + 5)) and
+ *     the factor 4 (1 - Pr) lambda^2 / ((K + 5) rho), which conserve momentum
+ *     and give the heat flux (1 - Pr) q; reduced, H+ = A c.q (2 lambda c^2 -
+ *     D - 2) H and B+ = A c.q (K_xi / 2 lambda)(2 lambda c^2 - D) H (for K = 0
+ *     these are Eqs. H_plus, B_plus; the printed B_plus holds for K = 0 only).
  */
 #ifndef UGKS_H
 #define UGKS_H
@@ -107,7 +111,7 @@ typedef struct {
 
 /*
  * Gas model (Eqs. bgk_shakhov, shakhov_fp, lambda_def):
- *   K internal degrees of freedom (must be 0), Pr Prandtl number, R gas
+ *   K internal degrees of freedom (>= 0; 0 = monatomic), Pr Prandtl number, R gas
  *   constant, mu = mu_ref (T / T_ref)^omega, tau = mu / p.
  *   dt > 0 fixes the time step; dt = 0 takes
  *     dt = cfl * min_i 2 |Omega_i| / max_k sum_{j in faces(i)} S_j |u_k . n_j|.
@@ -219,7 +223,7 @@ typedef struct {
  *   opt         may be NULL (all defaults)
  *   out         receives the new context; unchanged on failure
  * Errors: UGKS_EINVAL (bad mesh, velocity set, table or state),
- *         UGKS_EUNSUPPORTED (K != 0), UGKS_ENOMEM, UGKS_EHIP.
+ *         UGKS_ENOMEM, UGKS_EHIP.
  */
 int ugks_create(const ugks_mesh* mesh, const ugks_velocity* vel, const ugks_gas* gas,
                 const ugks_bc* bcs, int32_t n_bc, const double* W0, const ugks_options* opt,
@@ -359,8 +363,9 @@ typedef struct {
 /*
  * ugks_batch_create - cases[0..n_cases-1] are copied; the caller keeps its
  * arrays.  Errors: UGKS_EINVAL (any case invalid, mixed dim, n_cases < 1),
- * UGKS_EUNSUPPORTED (a case does not qualify for the fused sweep),
- * UGKS_ENOMEM, UGKS_EHIP.  The failing case is named in ugks_batch_last_error(NULL).
+ * UGKS_EUNSUPPORTED (a case does not qualify for the fused sweep, or its gas
+ * has K > 0; options with the limiter or local time steps), UGKS_ENOMEM,
+ * UGKS_EHIP.  The failing case is named in ugks_batch_last_error(NULL).
  */
 int ugks_batch_create(const ugks_case* cases, int32_t n_cases, const ugks_options* opt,
                       ugks_batch** out);
@@ -462,6 +467,7 @@ const char* ugks_mlp_last_error(const ugks_mlp* net);
 /*
  * ugks_snapshot - features and targets of every cell of the current state
  * (host arrays of n_cells*9 floats, caller's cell order; either may be NULL).
+ * Monatomic gases only (K > 0: UGKS_EUNSUPPORTED), as ugks_warm_start.
  */
 int ugks_snapshot(ugks_ctx* ctx, float* features, float* targets);
 
@@ -470,7 +476,8 @@ int ugks_snapshot(ugks_ctx* ctx, float* features, float* targets);
  * replace h and b of every cell by the Grad-type distribution from the
  * network's prediction for its features, or by the Maxwellian of W where the
  * features leave the training box.  *n_fallback (may be NULL) receives the
- * number of Maxwellian cells.  The residual normalisation restarts.
+ * number of Maxwellian cells.  The residual normalisation restarts.  The
+ * closure is defined for monatomic gases: K > 0 returns UGKS_EUNSUPPORTED.
  */
 int ugks_warm_start(ugks_ctx* ctx, const ugks_mlp* net, const double* W, int64_t* n_fallback);
 

@@ -27,8 +27,8 @@ __device__ __forceinline__ double maxw_norm(double lam) {
   else return r * sqrt(r);
 }
 
-// Primitive variables of a conservative state (monatomic, K = 0):
-// lambda = 3 rho / (4 (rho E - rho|U|^2/2)), p = rho/(2 lambda),
+// Primitive variables of a conservative state of a gas with K internal
+// degrees of freedom: lambda = (K + 3) rho / (4 (rho E - rho|U|^2/2)), p = rho/(2 lambda),
 // T = 1/(2 R lambda), tau = mu(T)/p with mu = mu_ref (T/T_ref)^omega.
 template <int D>
 __device__ __forceinline__ bool prim_of(const double* W, const GasP& g, double* P) {
@@ -40,7 +40,7 @@ __device__ __forceinline__ bool prim_of(const double* W, const GasP& g, double* 
     u2 += U[d] * U[d];
   }
   double eint = W[D + 1] - 0.5 * rho * u2;
-  double lam = 3.0 * rho / (4.0 * eint);
+  double lam = (g.K + 3.0) * rho / (4.0 * eint);
   double p = rho / (2.0 * lam);
   double T = 1.0 / (2.0 * g.R * lam);
   double tau = g.muref * pow(T / g.Tref, g.omega) / p;
@@ -55,23 +55,24 @@ __device__ __forceinline__ bool prim_of(const double* W, const GasP& g, double* 
   return (rho > 0.0) && (eint > 0.0) && isfinite(lam) && isfinite(tau);
 }
 
-// Conservative state of (rho, U, T) for a monatomic gas.
+// Conservative state of (rho, U, T) for a gas with K internal degrees of freedom.
 template <int D>
-__device__ __forceinline__ void cons_of(double rho, const double* U, double T, double R, double* W) {
+__device__ __forceinline__ void cons_of(double rho, const double* U, double T, double R, double K,
+                                        double* W) {
   double u2 = 0.0;
   W[0] = rho;
   for (int d = 0; d < D; ++d) {
     W[1 + d] = rho * U[d];
     u2 += U[d] * U[d];
   }
-  W[D + 1] = 0.5 * rho * u2 + 1.5 * rho * R * T;
+  W[D + 1] = 0.5 * rho * u2 + 0.5 * (K + 3.0) * rho * R * T;
 }
 
 // Far-field / outflow ghost state: free stream when it enters through the
 // face, otherwise the interior state.
 template <int D>
 __device__ __forceinline__ void ghost_state(int kind, const DevBC& bc, const double* n,
-                                            const double* Wi, double R, double* Wg) {
+                                            const double* Wi, double R, double K, double* Wg) {
   bool inflow = false;
   if (kind == UGKS_BC_FARFIELD) {
     double un = 0.0;
@@ -79,7 +80,7 @@ __device__ __forceinline__ void ghost_state(int kind, const DevBC& bc, const dou
     inflow = un < 0.0;
   }
   if (inflow) {
-    cons_of<D>(bc.rho, bc.U, bc.T, R, Wg);
+    cons_of<D>(bc.rho, bc.U, bc.T, R, K, Wg);
   } else {
     for (int v = 0; v < D + 2; ++v) Wg[v] = Wi[v];
   }
@@ -134,11 +135,11 @@ __device__ __forceinline__ void half_range(double Un, double lam, double s, doub
   m[2] = Un * m[1] + m[0] / (2.0 * lam);
 }
 
-// Solve E[psi psi^T] a = b for a Maxwellian (U, lam) with 3 translational plus
-// internal degrees of freedom, by elimination of a_0, a_j, a_E.
+// Solve E[psi psi^T] a = b for a Maxwellian (U, lam) with N = K + 3
+// translational plus internal degrees of freedom, by elimination of a_0, a_j, a_E.
 template <int D>
-__device__ __forceinline__ void slope_solve(const double* b, const double* U, double lam, double* a) {
-  const double N = 3.0;
+__device__ __forceinline__ void slope_solve(const double* b, const double* U, double lam, double N,
+                                            double* a) {
   double UU = 0.0, UR = 0.0, Rj[3];
   for (int d = 0; d < D; ++d) {
     UU += U[d] * U[d];
@@ -163,7 +164,7 @@ template <int D>
 struct Moments {
   double m[3][6];   // E[u_d^n], n <= 5 (m[d][0] = 1; unused dims are delta at 0)
   double x1, x2;    // E[xi^2], E[xi^4]
-  __device__ void init(const double* U, double lam) {
+  __device__ void init(const double* U, double lam, double kxi) {
     double var = 1.0 / (2.0 * lam);
     for (int d = 0; d < 3; ++d) {
       double mu = d < D ? U[d] : 0.0;
@@ -173,7 +174,6 @@ struct Moments {
       if (d >= D)
         for (int n = 1; n < 6; ++n) m[d][n] = 0.0;
     }
-    const int kxi = 3 - D;
     x1 = kxi * var;
     x2 = kxi * (kxi + 2.0) * var * var;
   }

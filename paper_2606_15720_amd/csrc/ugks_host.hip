@@ -66,7 +66,7 @@ void check_case_args(const ugks_mesh* mesh, const ugks_velocity* vel, const ugks
   fail_if(!mesh || !vel || !gas || !W0, "null argument");
   const int D = mesh->dim;
   fail_if(D != 2 && D != 3, "mesh.dim must be 2 or 3");
-  if (gas->K != 0) throw std::pair<int, std::string>(UGKS_EUNSUPPORTED, "only K = 0 (monatomic) is supported");
+  fail_if(gas->K < 0, "gas.K (internal degrees of freedom) must be >= 0");
   const int64_t nc = mesh->n_cells, nf = mesh->n_faces, nv = vel->nv;
   fail_if(nc <= 0 || nf <= 0 || nv <= 0, "empty mesh or velocity set");
   fail_if(nc >= (int64_t)INT32_MAX || nf >= (int64_t)INT32_MAX, "mesh too large for 32-bit indices");
@@ -94,8 +94,10 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   fail_if(lim != 0 && lim != 1, "limiter must be 0 (none) or 1 (Venkatakrishnan)");
   fail_if(lim == 1 && !(limk >= 0.0 && std::isfinite(limk)), "limiter_k must be finite and >= 0");
   c->D = D;
-  c->kxi = 3 - D;
-  c->nr = D == 2 ? 2 : 1;
+  // K_xi = K + 3 - D internal and out-of-plane dimensions (Eq. Kxi_def); b
+  // is carried when there are any (always in 2-D)
+  c->kxi = gas->K + 3 - D;
+  c->nr = c->kxi > 0 ? 2 : 1;
   c->prec = prec;
   c->Bv = Bv;
   c->flags = opt ? opt->flags : 0;
@@ -372,6 +374,8 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   v.u = upload(c, u);
   v.w = upload(c, w);
   v.u2 = upload(c, u2);
+  v.kxi = (double)c->kxi;
+  v.has_b = c->nr == 2 ? 1 : 0;
   std::vector<DevBC> hb(std::max(n_bc, 1));
   for (int i = 0; i < n_bc; ++i) {
     hb[i].kind = bcs[i].kind;
@@ -387,6 +391,7 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   c->gas.Tref = gas->T_ref;
   c->gas.muref = gas->mu_ref;
   c->gas.omega = gas->omega;
+  c->gas.K = (double)gas->K;
   const bool lts = (c->flags & 128) != 0;
   fail_if(lts && (c->flags & 64),
           "local time steps (flags bit 7) and boundary-flux tracking (bit 6) exclude each other");
@@ -762,8 +767,8 @@ void enqueue_step_fused(ugks_ctx* c) {
     TIMED(KK_WALL, launch_ghost_rows(D, P, c->fmesh, v, B.frec, B.h, B.b, B.flag, s));
   // (with boundary-flux tracking the wall pass also keeps each wall face's flux)
   const bool track = (c->flags & 64) != 0;
-  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, c->fmesh, g, B.h, B.frec, B.flag, s,
-                                        track ? (D == 2 ? B.b : B.h) : nullptr));
+  TIMED(KK_WALL, launch_wall_rho_inline(D, P, m, v, c->fmesh, g, B.h, B.frec, B.flag, s, track ? 1 : 0,
+                                        track ? (const void*)B.b : nullptr));
   if (track) TIMED(KK_RESID, launch_bflux(D, m, B.frec, B.F, 0, B.bflux, B.flag, s));
   // Maxwellian axis tables of every face and cell of this step
   TIMED(KK_TABLES, launch_tables(D, m, c->fmesh, g, B.frec, B.prim, B.cs, B.tabs, B.flag, s));
@@ -1135,6 +1140,10 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
   if (opt && (opt->flags & 128))
     throw std::pair<int, std::string>(UGKS_EUNSUPPORTED,
                                       "the batched form runs one global step (no local time steps)");
+  for (int32_t i = 0; i < n; ++i)
+    if (cases && cases[i].gas && cases[i].gas->K != 0)
+      throw std::pair<int, std::string>(UGKS_EUNSUPPORTED, "case " + std::to_string(i) +
+                                        ": the batched form takes monatomic gases (K = 0) only");
   if (opt && opt->limiter)
     throw std::pair<int, std::string>(UGKS_EUNSUPPORTED,
                                       "the batched sweep has no limiter");

@@ -120,6 +120,10 @@ struct DevVel {
   const double* u;          // [3*nvp] SoA: u[d*nvp + k]
   const double* w;          // [nvp]
   const double* u2;         // [nvp]
+  // internal and out-of-plane dimensions of the full velocity space,
+  // K_xi = K + 3 - D (Eq. Kxi_def); b is carried when K_xi > 0
+  double kxi = 0.0;
+  int32_t has_b = 0;
 };
 
 struct DevBC {
@@ -129,6 +133,7 @@ struct DevBC {
 
 struct GasP {
   double Pr, R, Tref, muref, omega, dt;
+  double K = 0.0;  // internal degrees of freedom (0: monatomic)
   // local time steps (flags bit 7): per-cell steps dt_i [nc], or null for
   // the global dt everywhere.  Faces always integrate over the global dt.
   const double* dtc = nullptr;
@@ -260,7 +265,8 @@ hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v
                            void* h, void* b, double* qn, const int32_t* flag, hipStream_t s);
 hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
                                   const FusedMesh& fm, const GasP& g, const void* h, double* frec,
-                                  const int32_t* flag, hipStream_t s, const void* b_bf = nullptr);
+                                  const int32_t* flag, hipStream_t s, int track = 0,
+                                  const void* b_bf = nullptr);
 hipError_t launch_bflux(int D, const DevMesh& m, const double* frec, const double* F, int staged,
                         double* acc, const int32_t* flag, hipStream_t s);
 hipError_t launch_ghost_rows(int D, int prec, const FusedMesh& fm, const DevVel& v,

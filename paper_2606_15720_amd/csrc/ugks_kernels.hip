@@ -44,7 +44,7 @@ __global__ __launch_bounds__(TPB) void k_heatflux(DevVel v, const T* __restrict_
       c2 += c[d] * c[d];
     }
     double hv = ld(h, i * v.nvp + k);
-    double bv = (D == 2) ? ld(b, i * v.nvp + k) : 0.0;
+    double bv = v.has_b ? ld(b, i * v.nvp + k) : 0.0;
     double s = v.w[k] * (c2 * hv + bv);
     for (int d = 0; d < D; ++d) acc[d] += s * c[d];
   }
@@ -99,7 +99,7 @@ __device__ __forceinline__ void gradW_at(int64_t i, const DevMesh& m, const DevB
     } else if (m.fbc[f] == UGKS_BC_WALL) {
       for (int v = 0; v < D + 2; ++v) nb[v] = Wi[v];
     } else {
-      ghost_state<D>(m.fbc[f], bcs[m.fbcid[f]], &m.fnorm[f * 3], Wi, g.R, nb);
+      ghost_state<D>(m.fbc[f], bcs[m.fbcid[f]], &m.fnorm[f * 3], Wi, g.R, g.K, nb);
     }
     for (int v = 0; v < D + 2; ++v) {
       vmin[v] = fmin(vmin[v], nb[v]);
@@ -151,7 +151,7 @@ __device__ __forceinline__ void face_eq_at(int64_t f, const DevMesh& m, const De
     R[FR_G + 1] = -0.5 * g.dt * g.dt;
     for (int x = 0; x < 20; ++x) {
       R[FR_PH + x] = x == 0 ? 1.0 : 0.0;
-      R[FR_PB + x] = x == 0 ? (3 - D) / (2.0 * lamw) : 0.0;
+      R[FR_PB + x] = x == 0 ? (g.K + 3.0 - D) / (2.0 * lamw) : 0.0;
     }
     return;
   }
@@ -160,7 +160,7 @@ __device__ __forceinline__ void face_eq_at(int64_t f, const DevMesh& m, const De
   const double* n = &m.fnorm[f * 3];
   double Wg[5];
   if (ghost) {
-    ghost_state<D>(kind, bcs[m.fbcid[f]], n, &W[(int64_t)L * (D + 2)], g.R, Wg);
+    ghost_state<D>(kind, bcs[m.fbcid[f]], n, &W[(int64_t)L * (D + 2)], g.R, g.K, Wg);
     double Pg[NPRIM];
     prim_of<D>(Wg, g, Pg);
     R[FR_GRHO] = Pg[0];
@@ -208,7 +208,7 @@ __device__ __forceinline__ void face_eq_at(int64_t f, const DevMesh& m, const De
     half_range(Un, lam, s == 0 ? 1.0 : -1.0, mo);
     W0[0] += rho * mo[0];
     for (int d = 0; d < D; ++d) W0[1 + d] += rho * (mo[1] * n[d] + mo[0] * Ut[d]);
-    W0[D + 1] += 0.5 * rho * (mo[2] + mo[0] * (Ut2 + 2.0 / (2.0 * lam)));
+    W0[D + 1] += 0.5 * rho * (mo[2] + mo[0] * (Ut2 + (g.K + 2.0) / (2.0 * lam)));
   }
   // 6.3 interface primitives, relaxation time and time coefficients
   double P0[NPRIM];
@@ -221,7 +221,8 @@ __device__ __forceinline__ void face_eq_at(int64_t f, const DevMesh& m, const De
   R[FR_C0] = rho0 * maxw_norm<D>(lam0);
   R[FR_LAM] = lam0;
   for (int d = 0; d < 3; ++d) R[FR_U + d] = U0[d];
-  R[FR_SH] = 4.0 * (1.0 - g.Pr) * lam0 * lam0 / (5.0 * rho0);
+  R[FR_SH] = 4.0 * (1.0 - g.Pr) * lam0 * lam0 / ((g.K + 5.0) * rho0);
+  const double kxi = g.K + 3.0 - D;
   time_coeffs(g.dt, P0[5], &R[FR_G]);
   // 6.4 spatial slopes from the averaged gradient
   double a[3][5];
@@ -234,14 +235,14 @@ __device__ __forceinline__ void face_eq_at(int64_t f, const DevMesh& m, const De
       double gr = ghost ? 0.0 : gW[((int64_t)Rc * 3 + d) * 5 + v];
       bvec[v] = 0.5 * (gl + gr) / rho0;
     }
-    slope_solve<D>(bvec, U0, lam0, a[d]);
+    slope_solve<D>(bvec, U0, lam0, g.K + 3.0, a[d]);
   }
   // 6.5 time slope from compatibility
   Moments<D> M;
-  M.init(U0, lam0);
+  M.init(U0, lam0, kxi);
   double r[5], At[5];
   time_slope_rhs<D>(M, a, r);
-  slope_solve<D>(r, U0, lam0, At);
+  slope_solve<D>(r, U0, lam0, g.K + 3.0, At);
   for (int d = 0; d < 3; ++d)
     for (int v = 0; v < 5; ++v) R[FR_A + d * 5 + v] = (d < D && v < D + 2) ? a[d][v] : 0.0;
   for (int v = 0; v < 5; ++v) R[FR_AT + v] = v < D + 2 ? At[v] : 0.0;
@@ -260,8 +261,8 @@ __device__ __forceinline__ void face_eq_at(int64_t f, const DevMesh& m, const De
     using Cb = Cubic<D>;
     double PH[Cb::N], PB[Cb::N];
     for (int x = 0; x < Cb::N; ++x) PH[x] = PB[x] = 0.0;
-    const double kap = (3 - D) / (2.0 * lam0);                         // B0 / H0
-    const double xi4 = (3 - D) * (5.0 - D) / (4.0 * lam0 * lam0);     // int xi^4 g / H0
+    const double kap = kxi / (2.0 * lam0);                             // B0 / H0
+    const double xi4 = kxi * (kxi + 2.0) / (4.0 * lam0 * lam0);       // int xi^4 g / H0
     const double G3 = R[FR_G + 2], G4 = R[FR_G + 3], G5 = R[FR_G + 4];
     const double sh = R[FR_SH];
     double a0v[3], a4v[3], Am[9], Atl[3];
@@ -283,7 +284,7 @@ __device__ __forceinline__ void face_eq_at(int64_t f, const DevMesh& m, const De
     Cb::add_const(PH, G5 * (At[0] + 0.5 * At[D + 1] * kap));
     Cb::add_lin(PH, G5, Atl);
     Cb::add_u2(PH, 0.5 * G5 * At[D + 1]);
-    if (D == 2) {
+    if (kxi > 0.0) {
       Cb::add_const(PB, G3 * kap);
       Cb::add_shakhov(PB, G3 * sh * kap, U0, q0, lam0, (double)D);
       Cb::add_lin(PB, G4 * kap, a0v);
@@ -322,7 +323,8 @@ __global__ __launch_bounds__(TPB) void k_grad_micro(DevMesh m, DevVel v,
   if (k >= v.nvp || *flag) return;
   const int64_t nvp = v.nvp;
   const double hi = ld(h, i * nvp + k);
-  const double bi = (D == 2) ? ld(b, i * nvp + k) : 0.0;
+  const bool hb = v.has_b;
+  const double bi = hb ? ld(b, i * nvp + k) : 0.0;
   double ah[3] = {0, 0, 0}, ab[3] = {0, 0, 0};
   double hmin = hi, hmax = hi, bmin = bi, bmax = bi;
   const int nfc = m.nfc[i];
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(TPB) void k_grad_micro(DevMesh m, DevVel v,
     double hn, bn;
     if (j >= 0) {
       hn = ld(h, (int64_t)j * nvp + k);
-      bn = (D == 2) ? ld(b, (int64_t)j * nvp + k) : 0.0;
+      bn = hb ? ld(b, (int64_t)j * nvp + k) : 0.0;
     } else {
       const int f = m.cface[i * MAXF + p];
       if (m.fbc[f] == UGKS_BC_WALL) {
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(TPB) void k_grad_micro(DevMesh m, DevVel v,
           c2 += c * c;
         }
         hn = R[FR_GC] * exp(-R[FR_GLAM] * c2);
-        bn = (3 - D) / (2.0 * R[FR_GLAM]) * hn;
+        bn = v.kxi / (2.0 * R[FR_GLAM]) * hn;
       }
     }
     hmin = fmin(hmin, hn);
@@ -355,12 +357,12 @@ __global__ __launch_bounds__(TPB) void k_grad_micro(DevMesh m, DevVel v,
     for (int d = 0; d < D; ++d) {
       const double G = m.lsG[(i * 3 + d) * MAXF + p];
       ah[d] += G * (hn - hi);
-      if (D == 2) ab[d] += G * (bn - bi);
+      if (hb) ab[d] += G * (bn - bi);
     }
   }
   if (m.limiter) {
     const double ph = venkat_phi<D>(m, i, nfc, hi, hmin, hmax, ah);
-    const double pb = (D == 2) ? venkat_phi<D>(m, i, nfc, bi, bmin, bmax, ab) : 1.0;
+    const double pb = hb ? venkat_phi<D>(m, i, nfc, bi, bmin, bmax, ab) : 1.0;
     for (int d = 0; d < D; ++d) {
       ah[d] *= ph;
       ab[d] *= pb;
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(TPB) void k_grad_micro(DevMesh m, DevVel v,
   }
   for (int d = 0; d < D; ++d) {
     gh[(i * 3 + d) * nvp + k] = ah[d];
-    if (D == 2) gb[(i * 3 + d) * nvp + k] = ab[d];
+    if (hb) gb[(i * 3 + d) * nvp + k] = ab[d];
   }
 }
 
@@ -428,17 +430,18 @@ __device__ __forceinline__ void face_flux(const DevMesh& m, const DevVel& v, con
     un += uk[d] * m.fnorm[f * 3 + d];
   }
   const double dt = g.dt;
-  constexpr int KXI = 3 - D;
+  const double KXI = v.kxi;
+  const bool hb = v.has_b;
   double ih = 0.0, ib = 0.0;
   if (kind == UGKS_BC_WALL) {
     if (un > 0.0) {
-      double hf = ld(h, (int64_t)L * nvp + k), bf = (D == 2) ? ld(b, (int64_t)L * nvp + k) : 0.0;
+      double hf = ld(h, (int64_t)L * nvp + k), bf = hb ? ld(b, (int64_t)L * nvp + k) : 0.0;
       double ugh = 0.0, ugb = 0.0;
       for (int d = 0; d < D; ++d) {
         double gd = gh[((int64_t)L * 3 + d) * nvp + k];
         hf += m.fdxL[f * 3 + d] * gd;
         ugh += uk[d] * gd;
-        if (D == 2) {
+        if (hb) {
           double gbd = gb[((int64_t)L * 3 + d) * nvp + k];
           bf += m.fdxL[f * 3 + d] * gbd;
           ugb += uk[d] * gbd;
@@ -475,12 +478,12 @@ __device__ __forceinline__ void face_flux(const DevMesh& m, const DevVel& v, con
     const int64_t up = left ? L : m.fR[f];
     const double* dx = left ? &m.fdxL[f * 3] : &m.fdxR[f * 3];
     hf = ld(h, up * nvp + k);
-    if (D == 2) bf = ld(b, up * nvp + k);
+    if (hb) bf = ld(b, up * nvp + k);
     for (int d = 0; d < D; ++d) {
       double gd = gh[(up * 3 + d) * nvp + k];
       hf += dx[d] * gd;
       ugh += uk[d] * gd;
-      if (D == 2) {
+      if (hb) {
         double gbd = gb[(up * 3 + d) * nvp + k];
         bf += dx[d] * gbd;
         ugb += uk[d] * gbd;
@@ -541,7 +544,7 @@ __global__ __launch_bounds__(TPB) void k_flux(DevMesh m, DevVel v, GasP g,
     double FH, FB;
     face_flux<D, T>(m, v, g, R, f, k, h, b, gh, gb, FH, FB);
     fh[f * nvp + k] = FH;
-    if (D == 2) fb[f * nvp + k] = FB;
+    if (v.has_b) fb[f * nvp + k] = FB;
     const double wk = v.w[k];
     acc[0] += wk * FH;
     for (int d = 0; d < D; ++d) acc[1 + d] += wk * v.u[d * nvp + k] * FH;
@@ -554,9 +557,9 @@ __global__ __launch_bounds__(TPB) void k_flux(DevMesh m, DevVel v, GasP g,
 
 // Reduced Maxwellian and Shakhov correction of a cell at one velocity.
 template <int D>
-__device__ __forceinline__ void cell_equilibrium(const double* P, const double* qv, double Pr,
+__device__ __forceinline__ void cell_equilibrium(const double* P, const double* qv, const GasP& g,
                                                  const double* uk, double& Hs, double& Bs) {
-  constexpr int KXI = 3 - D;
+  const double KXI = g.K + 3.0 - D, Pr = g.Pr;
   const double rho = P[0], lam = P[4];
   double c2 = 0.0, cq = 0.0;
   for (int d = 0; d < D; ++d) {
@@ -565,7 +568,7 @@ __device__ __forceinline__ void cell_equilibrium(const double* P, const double* 
     cq += c * qv[d];
   }
   const double H = rho * maxw_norm<D>(lam) * exp(-lam * c2);
-  const double pre = 4.0 * (1.0 - Pr) * lam * lam / (5.0 * rho) * cq;
+  const double pre = 4.0 * (1.0 - Pr) * lam * lam / ((g.K + 5.0) * rho) * cq;
   const double Hp = pre * (2.0 * lam * c2 - 2.0 - D) * H;
   const double Bp = pre * (2.0 * lam * c2 - D) * KXI / (2.0 * lam) * H;
   Hs = H + Hp;
@@ -592,18 +595,18 @@ __global__ __launch_bounds__(TPB) void k_stage1(DevMesh m, DevVel v, GasP g,
     const int64_t f = m.cface[i * MAXF + p];
     const double s = m.csign[i * MAXF + p] * area_for(g, i, m.farea[f]);
     sh += s * fh[f * nvp + k];
-    if (D == 2) sb += s * fb[f * nvp + k];
+    if (v.has_b) sb += s * fb[f * nvp + k];
   }
   const double* P = &prim[i * NPRIM];
   double uk[3] = {0, 0, 0};
   for (int d = 0; d < D; ++d) uk[d] = v.u[d * nvp + k];
   double Hs, Bs;
-  cell_equilibrium<D>(P, &q[i * 3], g.Pr, uk, Hs, Bs);
+  cell_equilibrium<D>(P, &q[i * 3], g, uk, Hs, Bs);
   const double c = dt_cell(g, i) / (2.0 * P[5]);
   const double iv = 1.0 / m.vol[i];
   const double hv = ld(h, i * nvp + k);
   st(ht, i * nvp + k, hv - sh * iv + c * (Hs - hv));
-  if (D == 2) {
+  if (v.has_b) {
     const double bv = ld(b, i * nvp + k);
     st(bt, i * nvp + k, bv - sb * iv + c * (Bs - bv));
   }
@@ -647,11 +650,11 @@ __global__ __launch_bounds__(TPB) void k_stage2(DevVel v, GasP g, const double* 
   double uk[3] = {0, 0, 0};
   for (int d = 0; d < D; ++d) uk[d] = v.u[d * nvp + k];
   double Hs, Bs;
-  cell_equilibrium<D>(P, &q[i * 3], g.Pr, uk, Hs, Bs);
+  cell_equilibrium<D>(P, &q[i * 3], g, uk, Hs, Bs);
   const double a = dt_cell(g, i) / (2.0 * P[5]);
   const double inv = 1.0 / (1.0 + a);
   st(h, i * nvp + k, (ld(ht, i * nvp + k) + a * Hs) * inv);
-  if (D == 2) st(b, i * nvp + k, (ld(bt, i * nvp + k) + a * Bs) * inv);
+  if (v.has_b) st(b, i * nvp + k, (ld(bt, i * nvp + k) + a * Bs) * inv);
 }
 
 // Residual of the density: one block, fixed summation order.
@@ -700,7 +703,7 @@ __global__ __launch_bounds__(TPB) void k_init_maxwellian(DevVel v, const double*
   }
   const double H = P[0] * maxw_norm<D>(P[4]) * exp(-P[4] * c2);
   st(h, i * v.nvp + k, H);
-  if (D == 2) st(b, i * v.nvp + k, (3 - D) / (2.0 * P[4]) * H);
+  if (v.has_b) st(b, i * v.nvp + k, v.kxi / (2.0 * P[4]) * H);
 }
 
 // Discrete moments sum_k w_k psi_k (h, b) per cell.
@@ -712,7 +715,7 @@ __global__ __launch_bounds__(TPB) void k_moments(DevVel v, const T* __restrict__
   double acc[5] = {0, 0, 0, 0, 0};
   for (int64_t k = threadIdx.x; k < v.nvp; k += TPB) {
     double wh = v.w[k] * ld(h, i * v.nvp + k);
-    double wb = (D == 2) ? v.w[k] * ld(b, i * v.nvp + k) : 0.0;
+    double wb = v.has_b ? v.w[k] * ld(b, i * v.nvp + k) : 0.0;
     acc[0] += wh;
     for (int d = 0; d < D; ++d) acc[1 + d] += wh * v.u[d * v.nvp + k];
     acc[D + 1] += 0.5 * (wh * v.u2[k] + wb);

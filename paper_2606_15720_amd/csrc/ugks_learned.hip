@@ -792,6 +792,8 @@ const char* ugks_mlp_last_error(const ugks_mlp* n) {
 
 int ugks_snapshot(ugks_ctx* c, float* feat, float* targ) {
   if (!c || (!feat && !targ)) return ctx_err(c, UGKS_EINVAL, "null argument");
+  if (c->gas.K != 0.0)
+    return ctx_err(c, UGKS_EUNSUPPORTED, "the learned closure is defined for monatomic gases (K = 0)");
   const int D = c->D;
   try {
     StepBuffers& B = c->buf;
@@ -841,6 +843,8 @@ int ugks_snapshot(ugks_ctx* c, float* feat, float* targ) {
 
 int ugks_warm_start(ugks_ctx* c, const ugks_mlp* net, const double* W, int64_t* n_fallback) {
   if (!c || !net) return ctx_err(c, UGKS_EINVAL, "null argument");
+  if (c->gas.K != 0.0)
+    return ctx_err(c, UGKS_EUNSUPPORTED, "the learned closure is defined for monatomic gases (K = 0)");
   const int D = c->D;
   Range range("ugks_warm_start");
   try {

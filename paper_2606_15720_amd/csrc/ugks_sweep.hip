@@ -129,14 +129,14 @@ __device__ __forceinline__ void cell_prep_at(int64_t i, const GasP& g, const dou
   double SH[Cb::N], SB[Cb::N];
   for (int x = 0; x < Cb::N; ++x) SH[x] = SB[x] = 0.0;
   const double lam = P[4], rho = P[0];
-  const double sh = 4.0 * (1.0 - g.Pr) * lam * lam / (5.0 * rho);
+  const double sh = 4.0 * (1.0 - g.Pr) * lam * lam / ((g.K + 5.0) * rho);
   const double U[3] = {P[1], P[2], P[3]};
   const double qc[3] = {q[i * 3], q[i * 3 + 1], q[i * 3 + 2]};
   Cb::add_shakhov(SH, sh, U, qc, lam, 2.0 + D);
   Cb::add_shakhov(SB, sh, U, qc, lam, (double)D);
   double* C = &cs[i * CSREC];
   C[CS_CC] = dt_cell(g, i) / (2.0 * P[5]);
-  C[CS_KAP] = (3 - D) / (2.0 * lam);
+  C[CS_KAP] = (g.K + 3.0 - D) / (2.0 * lam);
   C[CS_NORM] = rho * maxw_norm<D>(lam);
   for (int x = 0; x < 20; ++x) {
     C[CS_SH + x] = x < Cb::N ? SH[x] : 0.0;
@@ -209,7 +209,8 @@ struct SweepLds {
 // Every read-only array is its own __restrict__ argument so that the
 // compiler can prove no store of the sweep clobbers it and serve the
 // wave-uniform reads from the scalar cache.
-template <int D, typename T, typename C, bool SPLIT, bool LIM = false, bool SPARSE = false>
+template <int D, typename T, typename C, bool SPLIT, bool LIM = false, bool SPARSE = false,
+          bool NB = false>
 __device__ __forceinline__ void sweep_item(
     const FusedMesh& fm, int64_t nvp, const SweepSched& sc, const int32_t* __restrict__ crec_i,
     const C* __restrict__ crec_d, const C* __restrict__ crec_l, const int32_t* __restrict__ vidx,
@@ -726,7 +727,8 @@ __device__ __forceinline__ void sweep_item(
       }
     };
     pass(std::integral_constant<int, 0>{});
-    if constexpr (D == 2) pass(std::integral_constant<int, 1>{});
+    // b: always in 2-D; in 3-D for a gas with internal degrees of freedom
+    if constexpr (D == 2 || NB) pass(std::integral_constant<int, 1>{});
   }
   block_sum<NM>(mw, L.red);
   if (threadIdx.x == 0)
@@ -737,8 +739,9 @@ __device__ __forceinline__ void sweep_item(
 // Single case: the sweep computes in the storage type T (FP32 storage uses
 // FP32 copies of the records and tables; moment sums stay FP64).  The FP32
 // body fits in half the registers; its bound asks for the occupancy that
-// hides the gathers' latency (measured: 7 waves per SIMD, no spills).
-template <int D, typename T, bool LIM, bool SPARSE>
+// hides the gathers' latency (measured: 7 waves per SIMD, no spills).  NB:
+// a 3-D gas with internal degrees of freedom, whose b runs a second pass.
+template <int D, typename T, bool LIM, bool SPARSE, bool NB>
 __global__ __launch_bounds__(SWT, (sizeof(T) == 4 ? 6 : 4)) void k_sweep(
     FusedMesh fm, int64_t nvp, SweepSched sc, const int32_t* __restrict__ crec_i,
     const T* __restrict__ crec_d, const T* __restrict__ crec_l, const int32_t* __restrict__ vidx,
@@ -759,8 +762,8 @@ __global__ __launch_bounds__(SWT, (sizeof(T) == 4 ? 6 : 4)) void k_sweep(
   const int64_t chunk = rem / sc.tile;
   const int64_t ic = tile * sc.tile + rem % sc.tile;
   if (ic >= fm.nc) return;
-  sweep_item<D, T, T, true, LIM, SPARSE>(fm, nvp, sc, crec_i, crec_d, crec_l, vidx, w, cs, frec, tabs,
-                                         h, b, ht, bt, dWp, flag, ic, chunk, L);
+  sweep_item<D, T, T, true, LIM, SPARSE, NB>(fm, nvp, sc, crec_i, crec_d, crec_l, vidx, w, cs, frec,
+                                             tabs, h, b, ht, bt, dWp, flag, ic, chunk, L);
 }
 
 // The fused sweep over a batch of cases: a persistent grid walks a list of
@@ -882,7 +885,9 @@ __device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, i
   const unsigned nv = (unsigned)fm.nv;
   crec_t<double>* csh = (crec_t<double>*)(cc + CS_SH);  // scalar loads of the uniform polynomials
   crec_t<double>* csb = (crec_t<double>*)(cc + CS_SB);
-  const T* __restrict__ bti = D == 2 ? bt + ic * nvp : nullptr;
+  // b: always in 2-D; in 3-D when the gas has internal degrees of freedom
+  const bool hb = bt != nullptr;
+  const T* __restrict__ bti = hb ? bt + ic * nvp : nullptr;
   auto body = [&](unsigned k, int pk, double htk, double btk, double wk) {
     double vv[3] = {0, 0, 0};
     double c0 = 1.0;
@@ -898,7 +903,7 @@ __device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, i
     const double hn = (htk + A * c0 * (1.0 + E + O)) * inv;
     __builtin_nontemporal_store((T)hn, &hi[k]);
     double bn = 0.0;
-    if (D == 2) {
+    if (hb) {
       double Eb, Ob;
       cubic_eo<D>(csb, vv, v2, Eb, Ob);
       bn = (btk + A * kc * c0 * (1.0 + Eb + Ob)) * inv;
@@ -924,7 +929,7 @@ __device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, i
 #pragma unroll
     for (unsigned u = 0; u < UN; ++u) {
       hv[u] = __builtin_nontemporal_load(&hti[k + u * SWT]);
-      bv[u] = D == 2 ? bti[k + u * SWT] : T(0);
+      bv[u] = hb ? bti[k + u * SWT] : T(0);
     }
     // the HBM reads go out first, the small cached arrays next, and no
     // arithmetic is moved between them
@@ -938,7 +943,7 @@ __device__ __forceinline__ void stage2_q_cell(int64_t ic, const FusedMesh& fm, i
 #pragma unroll
     for (unsigned u = 0; u < UN; ++u) body(k + u * SWT, pk[u], (double)hv[u], (double)bv[u], wv[u]);
   }
-  for (; k < nv; k += SWT) body(k, fm.vidx[k], ld(hti, k), D == 2 ? ld(bti, k) : 0.0, w[k]);
+  for (; k < nv; k += SWT) body(k, fm.vidx[k], ld(hti, k), hb ? ld(bti, k) : 0.0, w[k]);
   block_sum<3>(acc, L.red);
   if (threadIdx.x == 0)
     for (int d = 0; d < 3; ++d) qn[ic * 3 + d] = d < D ? 0.5 * acc[d] : 0.0;
@@ -1103,7 +1108,7 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
           }
           bfi[0] += fh;
           bfi[D + 1] += 0.5 * u2 * fh;
-          if constexpr (D == 2) {
+          if (b != nullptr) {
             // the b part of the energy: the same free transport of the wall cell's b
             const unsigned kk = k0 + u * nb;
             const T* __restrict__ bl_row = b + L * nvp;
@@ -1151,8 +1156,8 @@ __device__ __forceinline__ void wall_rho_at(int64_t wi, const DevMesh& m, const 
             u2 += uu[u][d] * uu[u][d];
           }
           bfr[0] += fm_;
-          // 2-D: the re-emitted b = K_xi/(2 lambda_w) H_w adds to the energy
-          bfr[D + 1] += 0.5 * (u2 + (D == 2 ? 1.0 / (2.0 * lamw) : 0.0)) * fm_;
+          // the re-emitted b = K_xi/(2 lambda_w) H_w adds to the energy
+          bfr[D + 1] += 0.5 * (u2 + v.kxi / (2.0 * lamw)) * fm_;
         }
       }
     }
@@ -1181,9 +1186,12 @@ template <int D, typename T>
 __global__ __launch_bounds__(WALLT) void k_wall_rho_inline(DevMesh m, DevVel v, FusedMesh fm, GasP g,
                                                          const T* __restrict__ h,
                                                          double* __restrict__ frec,
-                                                         const int32_t* flag, const T* b_bf) {
+                                                         const int32_t* flag, const T* b_bf,
+                                                         int track) {
   __shared__ WallLds S;
-  if (b_bf) {
+  // with tracking the pass also keeps each wall face's flux; b_bf is the b
+  // array where b is stored (its part of the energy flux), else null
+  if (track) {
     if (fm.crec_l) wall_rho_at<D, T, true, true>(blockIdx.x, m, v, fm, g, h, frec, flag, S, b_bf);
     else wall_rho_at<D, T, false, true>(blockIdx.x, m, v, fm, g, h, frec, flag, S, b_bf);
   } else {
@@ -1193,8 +1201,8 @@ __global__ __launch_bounds__(WALLT) void k_wall_rho_inline(DevMesh m, DevVel v, 
 }
 
 // Ghost rows of the far-field / outflow faces: the Maxwellian of the face's
-// ghost state W_g (written by the interface-equilibrium pass), h and, in
-// 2-D, b = K_xi/(2 lambda_g) h, so the sweep reads them as neighbour rows.
+// ghost state W_g (written by the interface-equilibrium pass), h and, where
+// b is stored, b = K_xi/(2 lambda_g) h, so the sweep reads them as neighbour rows.
 template <int D, typename T>
 __device__ __forceinline__ void ghost_row_at(int64_t m, int64_t nc, const int32_t* __restrict__ ffaces,
                                              const DevVel& v, const double* __restrict__ frec,
@@ -1216,7 +1224,7 @@ __device__ __forceinline__ void ghost_row_at(int64_t m, int64_t nc, const int32_
       hv = C * exp(-lam * c2);
     }
     st(h, row + k, hv);
-    if (D == 2) st(b, row + k, (3 - D) / (2.0 * lam) * hv);
+    if (v.has_b) st(b, row + k, v.kxi / (2.0 * lam) * hv);
   }
 }
 
@@ -1329,6 +1337,18 @@ __global__ __launch_bounds__(WALLT) void k_wall_rho_b(BatchDev bd) {
     }                                   \
   } while (0)
 
+// precision only (the dimension fixed by the kernel named)
+#define UGKS_DISPATCH_T(P_, ...)      \
+  do {                                \
+    if ((P_) == UGKS_FP32) {          \
+      using TT = float;               \
+      __VA_ARGS__;                    \
+    } else {                          \
+      using TT = double;              \
+      __VA_ARGS__;                    \
+    }                                 \
+  } while (0)
+
 hipError_t launch_apply_dW(int D, const DevMesh& m, int64_t nchunk, const double* W,
                           const double* dWp, double* Wn, double* cellred, const int32_t* flag,
                           hipStream_t s) {
@@ -1366,13 +1386,21 @@ hipError_t launch_sweep(int D, int prec, const FusedMesh& fm, const DevVel& v, c
 #define UGKS_SWEEP_ARGS                                                                       \
   fm, v.nvp, sc, fm.crec_i, (const TT*)crec_d, (const TT*)crec_l, pv, v.w, (const TT*)cs,      \
       (const TT*)frec, (const TT*)tabs, (const TT*)h, (const TT*)b, (TT*)ht, (TT*)bt, dWp, flag
+#define UGKS_SWEEP_NB(LIMV, SPV)                                                             \
+  do {                                                                                        \
+    if (D == 3 && b)                                                                          \
+      UGKS_DISPATCH_T(prec, (k_sweep<3, TT, LIMV, SPV, true><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS))); \
+    else                                                                                      \
+      UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, LIMV, SPV, false><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS))); \
+  } while (0)
   if (fm.sparse) {
-    if (crec_l) UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, true, true><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
-    else UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, false, true><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+    if (crec_l) UGKS_SWEEP_NB(true, true);
+    else UGKS_SWEEP_NB(false, true);
   } else {
-    if (crec_l) UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, true, false><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
-    else UGKS_DISPATCH_DT(D, prec, (k_sweep<DD, TT, false, false><<<grid, SWT, 0, s>>>(UGKS_SWEEP_ARGS)));
+    if (crec_l) UGKS_SWEEP_NB(true, false);
+    else UGKS_SWEEP_NB(false, false);
   }
+#undef UGKS_SWEEP_NB
 #undef UGKS_SWEEP_ARGS
   return hipGetLastError();
 }
@@ -1406,10 +1434,10 @@ hipError_t launch_stage2_q(int D, int prec, const FusedMesh& fm, const DevVel& v
 
 hipError_t launch_wall_rho_inline(int D, int prec, const DevMesh& m, const DevVel& v,
                                   const FusedMesh& fm, const GasP& g, const void* h, double* frec,
-                                  const int32_t* flag, hipStream_t s, const void* b_bf) {
+                                  const int32_t* flag, hipStream_t s, int track, const void* b_bf) {
   if (m.nwall == 0) return hipSuccess;
   UGKS_DISPATCH_DT(D, prec, k_wall_rho_inline<DD, TT><<<(unsigned)m.nwall, WALLT, 0, s>>>(
-      m, v, fm, g, (const TT*)h, frec, flag, (const TT*)b_bf));
+      m, v, fm, g, (const TT*)h, frec, flag, (const TT*)b_bf, track));
   return hipGetLastError();
 }
 

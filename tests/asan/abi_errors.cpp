@@ -47,7 +47,7 @@ int main() {
   W0[0] = 0; expect("zero density", create(), UGKS_EINVAL, err()); W0[0] = 1;
   area[1] = 1.5; expect("cell not closed", create(), UGKS_EINVAL, err()); area[1] = 1;
   fc[2] = 5; expect("cell index out of range", create(), UGKS_EINVAL, err()); fc[2] = 0;
-  g.K = 2; expect("internal dof K > 0", create(), UGKS_EUNSUPPORTED, err()); g.K = 0;
+  g.K = -1; expect("negative internal dof", create(), UGKS_EINVAL, err()); g.K = 0;
   m.n_cells = 0; expect("empty mesh", create(), UGKS_EINVAL, err()); m.n_cells = 1;
   v.nv = 0; expect("empty velocity set", create(), UGKS_EINVAL, err()); v.nv = 4;
   // valid: stops at the first device call, nothing leaks

@@ -45,12 +45,12 @@ def _create(case, **kw):
     return ugks.ugks_create(case.mesh, case.vel, case.gas, case.bcs, case.W0, **kw)
 
 
-def test_rejects_polyatomic_gas():
+def test_rejects_negative_internal_degrees_of_freedom():
     case = uc.cavity2d(n=4, nv=4)
-    case.gas.K = 2
+    case.gas.K = -1
     with pytest.raises(ugks.UGKSError) as e:
         _create(case)
-    assert e.value.code == ugks.UGKS_EUNSUPPORTED
+    assert e.value.code == ugks.UGKS_EINVAL and "gas.K" in str(e.value)
 
 
 @pytest.mark.parametrize("what", ["volume", "normal", "weight", "bcid", "state", "precision", "open"])
