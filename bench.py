@@ -136,12 +136,13 @@ def measure_copy_bandwidth(gib: float = 2.0, reps: int = 5) -> dict:
             "kernel": f"torch device-to-device copy of {gib:g} GiB, {reps} repetitions"}
 
 
-def run_gpu(case, precision: int, steps: int, warmup: int, flags: int = 0):
+def run_gpu(case, precision: int, steps: int, warmup: int, flags: int = 0, limiter: int = 0):
     import torch
     from paper_2606_15720_amd.ugks import Solver, ugks_profile_enable, ugks_profile_read
 
     stream = torch.cuda.current_stream()
-    s = Solver(case, precision=precision, stream=stream.cuda_stream, flags=flags)
+    s = Solver(case, precision=precision, stream=stream.cuda_stream, flags=flags, limiter=limiter,
+               limiter_k=0.0)
     info = s.info
     if warmup:
         s.step(warmup)
@@ -273,15 +274,18 @@ def run_nontensor(steps: int, warmup: int):
 
 def run_sphere(steps: int, warmup: int):
     """The Mach-5 sphere at the paper's size (101,376 tets x 28^3 velocities on
-    [-11, 11]^3, Kn 0.01, potential-flow start), FP64 and FP32, at the order
-    the time-to-residual runs use."""
+    [-11, 11]^3, Kn 0.01, potential-flow start), FP64 and FP32: at first order
+    (the sweep's roofline, 233 flops per update), and at the paper's second
+    order with Venkatakrishnan's limiter (K = 0), the form the time-to-residual
+    runs use, whose limiter arithmetic the flop count leaves out."""
     import ugks_cases as uc
 
     case = uc.sphere_mach5(n_ang=8, n_rad=22, nv=28, a=11.0, kn=0.01, first=0.05, start="potential")
     first_order = 16  # ugks_options.flags bit: piecewise-constant reconstruction
     out = {"workload": f"sphere_m5_kn0.01_{case.mesh.n_cells}x28^3", "n_cells": case.mesh.n_cells,
            "n_faces": case.mesh.n_faces, "nv": case.vel.nv,
-           "reconstruction": "first order (unlimited second-order slopes fail at Mach 5)",
+           "reconstruction": "first order here; second order with the limiter under "
+                             "second_order_limited (unlimited second-order slopes fail at Mach 5)",
            "steps": steps, "warmup": warmup}
     for prec in (64, 32):
         r = run_gpu(case, prec, steps, warmup, flags=first_order)
@@ -295,7 +299,49 @@ def run_sphere(steps: int, warmup: int):
                                  "frac": r["achieved"] / HBM_PEAK_GBS}}}
         print(f"sphere fp{prec}: {r['ms_per_step']:.2f} ms/step, sweep {r['sweep_ms']:.2f} ms",
               file=sys.stderr, flush=True)
+    out["second_order_limited"] = {}
+    for prec in (64, 32):
+        r = run_gpu(case, prec, steps, warmup, limiter=1)
+        out["second_order_limited"][f"fp{prec}"] = {
+            "value": r["value"], "unit": "cell-velocity updates/s", "ms_per_step": r["ms_per_step"],
+            "sweep_ms": r["sweep_ms"]}
+        print(f"sphere limited fp{prec}: {r['ms_per_step']:.2f} ms/step, sweep {r['sweep_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
     return out
+
+
+def run_steady():
+    """Time to a 1e-6 density residual on the paper-size Mach-5 sphere
+    (101,376 tets x 28^3, Kn 0.01, second order with the limiter, potential-
+    flow start), in its fastest form here: local time steps, the FP32 form,
+    started from a coarse-velocity (20^3) FP32 run with local time steps to
+    5e-6.  Wall time from creating the predictor to the residual."""
+    import ugks_cases as uc
+    from paper_2606_15720_amd import warmstart as WS
+
+    kw = dict(n_ang=8, n_rad=22, kn=0.01, mach=5.0, first=0.05, start="potential")
+    fine = uc.sphere_mach5(nv=28, a=11.0, **kw)
+    coarse = uc.sphere_mach5(nv=20, a=11.0, **kw)
+    t0 = time.perf_counter()
+
+    def log(*x):
+        print(f"[steady {time.perf_counter() - t0:6.1f}s]", *x, file=sys.stderr, flush=True)
+
+    r = WS.time_to_residual(fine, coarse, target=1e-6, predictor_target=5e-6, max_steps=16000,
+                            chunk=250, flags=128, arms_run=("maxwell32",), limiter=1,
+                            limiter_k=0.0, log=log)
+    a = r["arms"]["maxwell32"]
+    return {"workload": "sphere_m5_kn0.01_101376x28^3, second order with Venkatakrishnan's "
+                        "limiter (K = 0), potential-flow start",
+            "metric": "time to 1e-6 density residual", "unit": "s",
+            "value": a["seconds"], "reached": a["reached"], "steps": a["steps"],
+            "residual": a["residual"], "predictor": r["predictor"],
+            "form": "local time steps, FP32, from the FP32 20^3-velocity predictor's W with the "
+                    "Maxwellian f (the predictor's time included)",
+            "context_s": {"fp64_global_dt": 781.5, "fp64_local_dt": 297.9,
+                          "note": "builder-run records on the same workload "
+                                  "(profiles/warmstart_*101k_2nd_order_limited*, "
+                                  "profiles/steady_sphere_*)"}}
 
 
 def run_warm_start(args):
@@ -444,6 +490,9 @@ def main():
     ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--no-nontensor", action="store_true",
                     help="leave out the refined (non-tensor) velocity set record")
+    ap.add_argument("--no-steady", action="store_true",
+                    help="leave out the time to a 1e-6 residual on the paper-size sphere "
+                         "(about 100 s)")
     ap.add_argument("--warm-start", action="store_true",
                     help="instead of the throughput line, the time to a 1e-6 density residual on "
                          "the reduced sphere: plain FP64 against predictor + learned warm start")
@@ -588,6 +637,8 @@ def main():
         out["sphere"] = run_sphere(args.sphere_steps, 2)
     if not args.no_nontensor:
         out["nontensor"] = run_nontensor(5, 1)
+    if not args.no_steady:
+        out["steady"] = run_steady()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_n, args.cpu_sample_n1)
     print(json.dumps(out), flush=True)
