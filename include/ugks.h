@@ -138,7 +138,7 @@ typedef struct {
  * Options.
  *   precision  UGKS_FP64 (default when 0) or UGKS_FP32.
  *   block_v    velocity-block size B_v of the fused sweep: velocities per
- *              work item (a multiple of 64, at least 128; 0 = 4096), the
+ *              work item (a multiple of 64; 0 = 4096), the
  *              paper's B_v (Eq. velocity_block_partition) as a scheduling unit.
  *   tile_cells cells per tile of the fused sweep's schedule (0 = 32); each
  *              XCD runs one tile through one velocity block at a time.

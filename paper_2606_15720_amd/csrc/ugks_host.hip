@@ -634,8 +634,10 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
   if (c->fused) {
     // velocity block: B_v velocities = B_v/2 mirror pairs per work item
     const int64_t npairs = c->fmesh.npairs;
+    // (at least 32 pairs, or all: the batched form's smallest block, whose
+    // per-block moment buffer below is sized from this)
     int64_t cp = Bv ? Bv / 2 : 2048;
-    cp = std::max<int64_t>(64, std::min<int64_t>(cp, npairs));
+    cp = std::max<int64_t>(std::min<int64_t>(32, npairs), std::min<int64_t>(cp, npairs));
     c->sched.nf = nf;
     c->sched.chunk_pairs = cp;
     c->sched.nchunk = (npairs + cp - 1) / cp;
@@ -1048,8 +1050,8 @@ double time_sweep(ugks_batch* b, const std::vector<int32_t>& items, int32_t** bu
 
 void apply_sched(ugks_ctx* c, int64_t chunk_pairs, int64_t tile) {
   const int64_t npairs = c->fmesh.npairs;
-  // at least 64 pairs (or all): the per-block moment buffer was sized for that
-  chunk_pairs = std::max(std::min<int64_t>(64, npairs), std::min(chunk_pairs, npairs));
+  // at least 32 pairs (or all): the per-block moment buffer was sized for that
+  chunk_pairs = std::max(std::min<int64_t>(32, npairs), std::min(chunk_pairs, npairs));
   c->sched.chunk_pairs = chunk_pairs;
   c->sched.nchunk = (npairs + chunk_pairs - 1) / chunk_pairs;
   c->sched.tile = std::max<int64_t>(1, std::min(tile, c->nc));
@@ -1093,8 +1095,10 @@ void autotune(ugks_batch* b) {
         const int64_t npairs = c->fmesh.npairs;
         tc.us = INFINITY;
         int64_t last_cp = -1;
-        for (int mult : {1, 2, 4, 8, 1 << 20}) {
-          const int64_t cp = std::min<int64_t>(npairs, (int64_t)mult * th);
+        // velocity blocks from 64 velocities (half a wave of pairs) up to the whole set
+        for (int mult2 : {1, 2, 4, 8, 16, 1 << 21}) {
+          if (mult2 == 1 && th != 64) continue;
+          const int64_t cp = std::min<int64_t>(npairs, (int64_t)mult2 * th / 2);
           if (cp == last_cp) continue;
           last_cp = cp;
           for (int64_t tile : {16, 64, 256}) {
@@ -1177,7 +1181,7 @@ void batch_build(ugks_batch* b, const ugks_case* cases, int32_t n, const ugks_op
     const ugks_case& k = cases[i];
     ugks_options o{};
     o.precision = prec;
-    o.block_v = 128;  // smallest velocity block: sizes the per-block moment buffer
+    o.block_v = 64;  // smallest velocity block: sizes the per-block moment buffer
     o.tile_cells = 0;
     o.flags = b->flags & ~(2 | 8);
     o.stream = b->stream;

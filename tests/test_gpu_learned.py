@@ -74,7 +74,13 @@ def test_mlp_inference_matches_oracle_bf16():
     print("bf16 inference: max", err.max() / scale, "mean", err.mean() / scale,
           "vs FP64 network", np.abs(y - y64).max() / scale, flush=True)
     # same roundings on both sides; a hidden activation whose bf16 rounding
-    # flips on an accumulation-order difference moves an output by ~2^-8 |w|
+    # flips on an accumulation-order difference moves an output by ~2^-8 |w|.
+    # Such flips need a pre-activation within an FP32 rounding of a bf16
+    # rounding boundary, so almost every row agrees to FP32 accumulation
+    # error and the few that do not stay within the flip bound.
+    rows_ok = np.mean(err.max(axis=1) <= 1e-5 * scale)
+    print("rows within 1e-5 of the emulation:", rows_ok, flush=True)
+    assert rows_ok >= 0.99
     assert err.max() <= 1e-2 * scale and err.mean() <= 1e-3 * scale
     assert np.abs(y - y64).max() <= 5e-2 * scale
     # empty and single-row calls

@@ -257,7 +257,7 @@ def test_block_size_and_tile_invariance(flags):
     # (the paper's algebraic equivalence of partitioned velocity moments)
     case = uc.cavity2d(n=8, nv=28)
     Ws = []
-    for bv, tile in ((128, 1), (256, 7), (1024, 64), (0, 0)):
+    for bv, tile in ((128, 1), (64, 3), (256, 7), (1024, 64), (0, 0)):
         s = Solver(case, block_v=bv, tile_cells=tile, flags=flags)
         s.step(5)
         Ws.append(s.W())

@@ -51,6 +51,18 @@ def test_internal_degrees_of_freedom_follow_the_oracle(which, K, flags):
     _compare_step(case, steps, flags=flags, **lim)
 
 
+@pytest.mark.parametrize("flags", PATHS)
+def test_internal_degrees_of_freedom_on_a_refined_velocity_set(flags):
+    # 3-D, K = 2, a velocity set refined off centre (the fused sweep's pair
+    # table with pad partners, and its b pass), with the limiter
+    case = _with_K(uc.sod3d_tets(n=2, nv=6, jitter=0.15, seed=4), 2)
+    case.vel = uc.locally_refined_grid(6, 4.0, 3, (0.9, 0.0, -0.3), 1.2)
+    s = Solver(case, flags=flags, limiter=1)
+    assert s.info["fused"] == (0 if flags & STAGED else 1) and s.info["n_r"] == 2
+    s.close()
+    _compare_step(case, 4, flags=flags, limiter=1, limiter_k=0.0)
+
+
 def test_internal_degrees_of_freedom_fp32_form():
     case, _, _ = _case("sod3d", 2)
     o = Oracle(case)
