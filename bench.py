@@ -201,7 +201,25 @@ def run_batched(steps: int, warmup: int):
             "create_and_tune_s": create_s, "lanes": info["threads"],
             "work_items": info["work_items"], "graph": bool(info["graph"]),
             "workload": "64 uneven 2-D cavity/Couette cases (16^2..96^2 cells, 16^2..40^2 "
-                        "velocities, Kn 1e-3..10), FP64"}
+                        "velocities, Kn 1e-3..10), FP64",
+            "fp32": _batched_fp32(cases, ups, steps, warmup)}
+
+
+def _batched_fp32(cases, ups, steps, warmup):
+    """The same batch in the FP32 form (FP32 storage and sweep arithmetic)."""
+    from paper_2606_15720_amd.ugks import UGKS_FP32, Batch
+
+    b = Batch(cases, precision=UGKS_FP32)
+    b.step(warmup)
+    t = time.perf_counter()
+    b.step(steps)
+    wall = time.perf_counter() - t
+    b.close()
+    gbs = 32.0 * ups / (wall / steps) / 1e9
+    return {"value": ups * steps / wall, "unit": "cell-velocity updates/s",
+            "ms_per_step": wall / steps * 1e3, "dtype": "f32",
+            "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS, "bytes_per_update": 32}}
 
 
 def _cpu_model() -> str:

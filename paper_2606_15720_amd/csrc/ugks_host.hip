@@ -651,6 +651,10 @@ void build(ugks_ctx* c, const ugks_mesh* mesh, const ugks_velocity* vel, const u
       B.frec32 = dalloc<float>(c, nf * FREC);
       B.cs32 = dalloc<float>(c, nc * CSREC);
       B.tabs32 = dalloc<float>(c, (nf + nc) * (int64_t)D * c->fmesh.na);
+      // defined before the first step (the batched autotuner times the sweep on them)
+      HIP_TRY(hipMemset(B.frec32, 0, nf * FREC * sizeof(float)));
+      HIP_TRY(hipMemset(B.cs32, 0, nc * CSREC * sizeof(float)));
+      HIP_TRY(hipMemset(B.tabs32, 0, (nf + nc) * (int64_t)D * c->fmesh.na * sizeof(float)));
     }
   } else {
     B.dW = dalloc<double>(c, nc * 5);
@@ -1011,6 +1015,8 @@ void enqueue_batch_step(ugks_batch* b, int par) {
   HIP_TRY(launch_wall_rho_b(D, P, bd, b->nwall, s));
   // Maxwellian axis tables
   HIP_TRY(launch_tables_b(D, bd, b->ntab, s));
+  // the FP32 form's sweep computes from FP32 copies of the step's records
+  if (P == UGKS_FP32) HIP_TRY(launch_to_f32_b(bd, b->nface, b->ncell, b->ntab, s));
   // 5, 6.7-6.8, 9: the fused velocity sweep, one persistent launch
   HIP_TRY(launch_sweep_b(D, P, bd, b->grid, b->threads, s));
   // 8 conservative update; 10 new equilibrium

@@ -278,6 +278,8 @@ hipError_t launch_cell_prep_b(int D, const BatchDev& bd, int64_t ncell, int next
 hipError_t launch_gradW_b(int D, const BatchDev& bd, int64_t ncell, hipStream_t s);
 hipError_t launch_face_eq_b(int D, const BatchDev& bd, int64_t nface, hipStream_t s);
 hipError_t launch_wall_rho_b(int D, int prec, const BatchDev& bd, int64_t nwall, hipStream_t s);
+hipError_t launch_to_f32_b(const BatchDev& bd, int64_t nface, int64_t ncell, int64_t ntab,
+                           hipStream_t s);
 hipError_t launch_tables_b(int D, const BatchDev& bd, int64_t ntab, hipStream_t s);
 hipError_t launch_ghost_rows_b(int D, int prec, const BatchDev& bd, int64_t nff, hipStream_t s);
 hipError_t launch_sweep_b(int D, int prec, const BatchDev& bd, int64_t grid, int threads,

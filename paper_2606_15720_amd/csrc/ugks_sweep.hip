@@ -774,7 +774,9 @@ __global__ __launch_bounds__(SWT, (sizeof(T) == 4 ? 6 : 4)) void k_sweep(
 // third wave per SIMD.
 template <int D, typename T>
 __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 3)) void k_sweep_b(BatchDev bd) {
-  __shared__ SweepLds<double> L;
+  // computes in the storage type, as the single case does: an FP32 batch
+  // reads the FP32 copies of its records and tables
+  __shared__ SweepLds<T> L;
   // The work list and the case table are read-only for the whole launch:
   // read through the constant address space they are scalar loads, so the
   // case's pointers and sizes land in scalar registers as kernel arguments do.
@@ -802,9 +804,18 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 3)) void k_sweep_b(BatchDev bd) 
     sc.chunk_pairs = cases[c].sc.chunk_pairs;
     const int64_t nvp = cases[c].v.nvp;
     const double* w = cases[c].v.w;
-    const double* cs = cases[c].B.cs;
-    const double* frec = cases[c].B.frec;
-    const double* tabs = cases[c].B.tabs;
+    const T *crec_d, *cs, *frec, *tabs;
+    if constexpr (sizeof(T) == 4) {
+      crec_d = cases[c].fm.crec_d32;
+      cs = cases[c].B.cs32;
+      frec = cases[c].B.frec32;
+      tabs = cases[c].B.tabs32;
+    } else {
+      crec_d = cases[c].fm.crec_d;
+      cs = cases[c].B.cs;
+      frec = cases[c].B.frec;
+      tabs = cases[c].B.tabs;
+    }
     const T* h = (const T*)cases[c].B.h;
     const T* b = (const T*)cases[c].B.b;
     T* ht = (T*)cases[c].B.ht;
@@ -812,8 +823,8 @@ __global__ __launch_bounds__(SWT, (D == 3 ? 4 : 3)) void k_sweep_b(BatchDev bd) 
     double* dW = cases[c].B.dW;
     const int32_t* flag = cases[c].B.flag;
     __syncthreads();  // the previous item's readers of L are done
-    sweep_item<D, T, double, false>(fm, nvp, sc, fm.crec_i, fm.crec_d, nullptr, fm.vidx, w, cs, frec, tabs, h, b, ht, bt,
-                     dW, flag, ic, chunk, L);
+    sweep_item<D, T, T, false>(fm, nvp, sc, fm.crec_i, crec_d, nullptr, fm.vidx, w, cs, frec, tabs, h, b,
+                               ht, bt, dW, flag, ic, chunk, L);
   }
 }
 
@@ -1270,6 +1281,34 @@ __global__ void k_tables_b(BatchDev bd) {
                C.B.cs, C.B.tabs, C.B.flag);
 }
 
+// FP32 copies of every case's per-step face records, cell records and axis
+// tables (an FP32 batch's sweep computes from them): three flattened ranges.
+__global__ void k_to_f32_b(BatchDev bd, int64_t nfr, int64_t ncs, int64_t ntab) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < nfr) {
+    const int c = case_of(bd.face_off, bd.n, t / FREC);
+    const CaseDev& C = bd.cases[c];
+    const int64_t i = t - bd.face_off[c] * FREC;
+    C.B.frec32[i] = (float)C.B.frec[i];
+    return;
+  }
+  t -= nfr;
+  if (t < ncs) {
+    const int c = case_of(bd.cell_off, bd.n, t / CSREC);
+    const CaseDev& C = bd.cases[c];
+    const int64_t i = t - bd.cell_off[c] * CSREC;
+    C.B.cs32[i] = (float)C.B.cs[i];
+    return;
+  }
+  t -= ncs;
+  if (t < ntab) {
+    const int c = case_of(bd.tab_off, bd.n, t);
+    const CaseDev& C = bd.cases[c];
+    const int64_t i = t - bd.tab_off[c];
+    C.B.tabs32[i] = (float)C.B.tabs[i];
+  }
+}
+
 template <int D>
 __global__ void k_apply_dW_b(BatchDev bd) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1479,6 +1518,14 @@ hipError_t launch_cell_prep_b(int D, const BatchDev& bd, int64_t ncell, int next
   if (ncell == 0) return hipSuccess;
   const unsigned grid = (unsigned)((ncell + 127) / 128);
   UGKS_DISPATCH_D(D, k_cell_prep_b<DD><<<grid, 128, 0, s>>>(bd, next));
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32_b(const BatchDev& bd, int64_t nface, int64_t ncell, int64_t ntab,
+                           hipStream_t s) {
+  const int64_t n = nface * FREC + ncell * CSREC + ntab;
+  if (n == 0) return hipSuccess;
+  k_to_f32_b<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(bd, nface * FREC, ncell * CSREC, ntab);
   return hipGetLastError();
 }
 

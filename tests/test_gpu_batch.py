@@ -33,6 +33,32 @@ def _small_batch(seed=7, count=6):
     return uc.batch_cases(seed=seed, count=count, n_range=(5, 12), nv_range=(8, 16))
 
 
+def test_fp32_batch_computes_in_fp32():
+    """An FP32 batch computes its sweep in FP32 from FP32 copies of the
+    step's records, as the single-case FP32 form does: each case follows the
+    FP64 oracle to the FP32 form's bound, and the same case run alone in the
+    FP32 form with the batch's schedule to FP32 rounding."""
+    cases = _small_batch(seed=13, count=4) + [uc.channel2d(n=6, nv=10, kn=0.1)]
+    b = U.Batch(cases, precision=U.UGKS_FP32)
+    b.step(10)
+    for i, c in enumerate(cases):
+        o = Oracle(c)
+        o.step(10)
+        Wb = b.W(i)
+        Wo = o.state(with_h=False)[0]
+        err = np.abs(Wb - Wo).max(axis=0) / _scales(Wo)
+        ci = b.case_info(i)
+        bv = ci["block_v"] if ci["block_v"] < c.vel.nv else 0
+        s = U.Solver(c, precision=U.UGKS_FP32, block_v=bv, tile_cells=ci["tile_cells"])
+        s.step(10)
+        es = np.abs(Wb - s.W()).max(axis=0) / _scales(Wo)
+        s.close()
+        print(i, c.name, "FP32 batch vs oracle", err, "vs the FP32 case alone", es, flush=True)
+        assert np.all(err <= 1e-5), (i, err)
+        assert np.all(es <= 1e-6), (i, es)
+    b.close()
+
+
 def test_batch_cases_follow_the_oracle():
     # uneven cavities and Couette flows, plus a channel with far-field ends
     cases = _small_batch() + [uc.channel2d(n=6, nv=10, kn=0.1)]

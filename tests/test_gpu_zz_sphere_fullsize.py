@@ -1,6 +1,7 @@
 """GPU: the Mach-5 sphere workload at full size (101,376 tets x 28^3
-velocities) against the CPU oracle.  The oracle's step of this workload takes
-about a minute on the host cores, so the file is collected last."""
+velocities) against the CPU oracle, at first order and at second order with
+the limiter.  The oracle's step of this workload takes a minute or more on the
+host cores, so the file is collected last."""
 
 import numpy as np
 import pytest
@@ -82,3 +83,41 @@ def test_sphere_full_size_first_step_and_warm_start():
     assert err <= 1e-13
     net.close()
     s.close()
+
+
+def test_sphere_full_size_second_order_limited_step():
+    """The same workload at the paper's second order with Venkatakrishnan's
+    limiter (K = 0), the form the time-to-residual runs use: one FP64 step
+    against the oracle with the same limiter (W per component and per cell,
+    sampled rows of h)."""
+    import gc
+
+    case = uc.sphere_mach5(n_ang=8, n_rad=22, nv=28, a=11.0, kn=0.01, mach=5.0, first=0.05,
+                           start="potential")
+    nc = case.mesh.n_cells
+    print("full-size case, second order with the limiter:", nc, "cells x", case.vel.nv,
+          "velocities", flush=True)
+    s = Solver(case, limiter=1, limiter_k=0.0)
+    assert s.info["fused"] == 1
+    s.step(1)
+    Wg, hg, _ = s.state()
+    s.close()
+    rows = np.random.default_rng(2).choice(nc, 400, replace=False)
+    hg_rows = hg[rows]
+    del hg
+    gc.collect()
+    print("GPU step done; oracle step (all host cores)", flush=True)
+    o = Oracle(case, limiter=1, limiter_k=0.0)
+    o.step(1)
+    Wo, ho, _, _ = o.state()
+    D = 3
+    rho, rE = Wo[:, 0], Wo[:, D + 1]
+    scale = np.array([rho.max()] + [np.max(np.sqrt(2 * rho * rE))] * D + [np.abs(rE).max()])
+    err = np.abs(Wg - Wo).max(axis=0) / scale
+    pc = np.array([np.max(np.abs(Wg[:, 0] - rho) / rho), np.max(np.abs(Wg[:, D + 1] - rE) / rE)])
+    print("W normwise error", err, "per-cell rho, rho E", pc, flush=True)
+    assert np.all(err <= 1e-12), err
+    assert np.all(pc <= 1e-12), pc
+    herr = np.abs(hg_rows - ho[rows]).max() / np.abs(ho).max()
+    print("h error on 400 sampled cells", herr, flush=True)
+    assert herr <= 1e-12
