@@ -10,7 +10,7 @@ import ugks_cases as uc
 from oracle import Oracle
 from paper_2606_15720_amd.ugks import (UGKS_EUNSUPPORTED, UGKS_FP32, Batch, Solver, UGKSError,
                                        ugks_snapshot)
-from test_gpu_parity import PATHS, STAGED, TRACK, _compare_step, _normwise
+from test_gpu_parity import LOCAL_DT, PATHS, STAGED, TRACK, _compare_step, _normwise
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +61,14 @@ def test_internal_degrees_of_freedom_on_a_refined_velocity_set(flags):
     assert s.info["fused"] == (0 if flags & STAGED else 1) and s.info["n_r"] == 2
     s.close()
     _compare_step(case, 4, flags=flags, limiter=1, limiter_k=0.0)
+
+
+@pytest.mark.parametrize("flags", PATHS)
+def test_internal_degrees_of_freedom_with_local_time_steps(flags):
+    # K = 2 on the graded sphere shell, second order with the limiter, each
+    # cell on its own step
+    case, steps, lim = _case("sphere", 2)
+    _compare_step(case, 4, flags=flags | LOCAL_DT, **lim)
 
 
 def test_internal_degrees_of_freedom_fp32_form():
