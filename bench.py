@@ -635,30 +635,42 @@ def main():
         "hbm_copy": copy,
         "kernels_ms_per_step": {k: v[1] / max(args.steps, 1) for k, v in r64["prof"].items()},
     }
-    if not args.no_fp32:
+    # the records beside the throughput line: a failure in one is reported in
+    # its place and does not cost the line
+    def record(name, fn, *a):
+        try:
+            out[name] = fn(*a)
+        except Exception as e:  # noqa: BLE001
+            print(f"{name} record failed: {e!r}", file=sys.stderr, flush=True)
+            out[name] = {"error": repr(e)}
+
+    def fp32_record():
         r32 = run_gpu(case, 32, args.steps, args.warmup)
-        out["fp32"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
-                       "sweep_ms": r32["sweep_ms"],
-                       "alu": {"achieved": r32["tflops"], "peak": FP32_VECTOR_TFLOPS,
-                               "unit": "TFLOP/s", "frac": r32["tflops"] / FP32_VECTOR_TFLOPS,
-                               "peak_note": "unpacked FP32 vector rate (packed FP32 is kept out "
-                                            "of the kernels); the published 157.3 TFLOP/s counts "
-                                            "packed forms",
-                               "frac_of_published": r32["tflops"] / FP32_PEAK_TFLOPS},
-                       "hbm": {"achieved": r32["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": r32["achieved"] / HBM_PEAK_GBS},
-                       "traffic": _traffic(32),
-                       "step_hbm": _step_hbm(r32, 32, case.mesh.n_cells * case.vel.nv, copy)}
+        return {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
+                "sweep_ms": r32["sweep_ms"],
+                "alu": {"achieved": r32["tflops"], "peak": FP32_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": r32["tflops"] / FP32_VECTOR_TFLOPS,
+                        "peak_note": "unpacked FP32 vector rate (packed FP32 is kept out "
+                                     "of the kernels); the published 157.3 TFLOP/s counts "
+                                     "packed forms",
+                        "frac_of_published": r32["tflops"] / FP32_PEAK_TFLOPS},
+                "hbm": {"achieved": r32["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": r32["achieved"] / HBM_PEAK_GBS},
+                "traffic": _traffic(32),
+                "step_hbm": _step_hbm(r32, 32, case.mesh.n_cells * case.vel.nv, copy)}
+
+    if not args.no_fp32:
+        record("fp32", fp32_record)
     if not args.no_batched:
-        out["batched"] = run_batched(args.steps, args.warmup)
+        record("batched", run_batched, args.steps, args.warmup)
     if not args.no_sphere:
-        out["sphere"] = run_sphere(args.sphere_steps, 2)
+        record("sphere", run_sphere, args.sphere_steps, 2)
     if not args.no_nontensor:
-        out["nontensor"] = run_nontensor(5, 1)
+        record("nontensor", run_nontensor, 5, 1)
     if not args.no_steady:
-        out["steady"] = run_steady()
+        record("steady", run_steady)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = run_cpu_baseline(args.cpu_sample_n, args.cpu_sample_n1)
+        record("cpu_baseline", run_cpu_baseline, args.cpu_sample_n, args.cpu_sample_n1)
     print(json.dumps(out), flush=True)
 
 
