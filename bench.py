@@ -390,6 +390,7 @@ def run_warm_start(args):
                               flags=(0 if second else 16) | (128 if args.ws_local_dt else 0),
                               limiter=1 if second else 0, chunk=args.ws_chunk,
                               deep_ref=np.load(args.ws_deep_ref) if args.ws_deep_ref else None,
+                              predictor_first_order=args.ws_predictor_order == 1,
                               limiter_k=args.ws_limiter_k, blunt=not args.ws_no_blunt)
     out["metric"] = "time to 1e-6 density residual (s)"
     out["reconstruction"] = (f"second order with Venkatakrishnan's limiter, K = {args.ws_limiter_k}"
@@ -540,6 +541,8 @@ def main():
                     help="Venkatakrishnan's K at second order")
     ap.add_argument("--ws-no-blunt", action="store_true",
                     help="train without the supersonic cylinder flows")
+    ap.add_argument("--ws-predictor-order", type=int, default=0, choices=(0, 1),
+                    help="1: the predictor at first order (0: the arms' order)")
     ap.add_argument("--ws-chunk", type=int, default=1000,
                     help="steps between residual checks (step counts are rounded up to it)")
     ap.add_argument("--ws-local-dt", action="store_true",

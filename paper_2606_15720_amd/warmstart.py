@@ -244,7 +244,8 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
                      max_steps=60000, chunk=1000, flags=16, train_seed=4, log=None,
                      arms_run=("plain64", "maxwell32", "learned32", "learned64"),
                      ref_out=None, ref_in=None, deep_target=None, deep_max_steps=200000,
-                     limiter=0, limiter_k=0.0, blunt=True, deep_ref=None):
+                     limiter=0, limiter_k=0.0, blunt=True, deep_ref=None,
+                     predictor_first_order=False):
     """Plain FP64 from the initial state against predictor + learned warm start.
 
     Arms (all to a density residual <= target, wall time from creation):
@@ -333,12 +334,17 @@ def time_to_residual(case_fine, case_coarse, *, target=1e-6, predictor_target=1e
             net.close()
         return out
     t = time.perf_counter()
-    p = U.Solver(case_coarse, precision=U.UGKS_FP32, flags=flags, **lim)
+    # the predictor may run at first order (no gradients, no limiter): cheaper
+    # steps toward a W that the fine run then corrects
+    pflags = (flags | 16) if predictor_first_order else flags
+    plim = dict(limiter=0, limiter_k=0.0) if predictor_first_order else lim
+    p = U.Solver(case_coarse, precision=U.UGKS_FP32, flags=pflags, **plim)
     psteps, pr, pok = run_to_residual(p, predictor_target, max_steps, chunk, log, "predictor")
     Wp = p.W()
     p.close()
     tp = time.perf_counter() - t
-    out["predictor"] = {"steps": psteps, "residual": pr, "reached": pok, "seconds": tp}
+    out["predictor"] = {"steps": psteps, "residual": pr, "reached": pok, "seconds": tp,
+                        "first_order": bool(predictor_first_order)}
     for name, prec, warm in (("maxwell32", U.UGKS_FP32, False), ("learned32", U.UGKS_FP32, True),
                              ("learned64", U.UGKS_FP64, True)):
         if name not in arms_run:
