@@ -63,6 +63,19 @@ def test_internal_degrees_of_freedom_on_a_refined_velocity_set(flags):
     _compare_step(case, 4, flags=flags, limiter=1, limiter_k=0.0)
 
 
+def test_internal_degrees_of_freedom_on_six_faced_cells():
+    # graded hexahedra (the staged sweep), walls at different temperatures, K = 2
+    case = uc.Case("hexes", uc.hex_box(4, 3, 3, grading=0.6, seed=5), uc.midpoint_grid(8, 4.0, 3),
+                   uc.Gas(mu_ref=uc.hard_sphere_mu_ref(0.05)),
+                   [uc.BC(uc.BC_WALL, 1.0, (0.0, 0.0, 0.0), 1.0 + 0.1 * s) for s in range(6)], None, 0)
+    case.W0 = uc.uniform_W(case.mesh.n_cells, 3, 1.0, (0.1, 0.0, 0.0), 1.0)
+    case = _with_K(case, 2)
+    s = Solver(case)
+    assert s.info["fused"] == 0 and s.info["n_r"] == 2
+    s.close()
+    _compare_step(case, 6, flags=STAGED)
+
+
 @pytest.mark.parametrize("flags", PATHS)
 def test_internal_degrees_of_freedom_with_local_time_steps(flags):
     # K = 2 on the graded sphere shell, second order with the limiter, each
