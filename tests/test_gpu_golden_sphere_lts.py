@@ -60,3 +60,31 @@ def test_sphere_limited_local_steps_match_the_stored_oracle_state():
     assert abs(r[1] - ro[1]) <= max(1e-12 * ro[1], 2.0 * tol), (r, ro)
     bound = 2.0 * tol * ro[0] * (1.0 / ro[1] + 1.0 / r_first[1])
     assert abs(r[0] - ro[0]) <= max(1e-12 * ro[0], bound), (r, ro)
+
+
+def test_sphere_limited_local_steps_fp32_stays_near_the_stored_oracle_state():
+    # the FP32 form that the time-to-residual runs use (f and its fluxes in
+    # FP32, moments and the conservative update in FP64): after 10 steps from
+    # the same start each cell's rho, rho E and momentum within 4e-6 of the
+    # FP64 oracle's (FP32 rounding of f, 6e-8 relative, entering every step's
+    # update; measured 9e-7)
+    from paper_2606_15720_amd.ugks import UGKS_FP32
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    case = uc.sphere_mach5(**KW)
+    steps = int(g["steps"])
+    s = Solver(case, precision=UGKS_FP32, flags=LOCAL_DT, limiter=1, limiter_k=0.0)
+    s.step(steps)
+    W = s.W()
+    s.close()
+    D = 3
+    cells = np.asarray(g["cells"])
+    Wo = np.asarray(g["W"])
+    Wg = W[cells]
+    rho, rE = Wo[:, 0], Wo[:, D + 1]
+    pc = np.array([np.max(np.abs(Wg[:, 0] - rho) / rho), np.max(np.abs(Wg[:, D + 1] - rE) / rE)])
+    merr = np.max(np.abs(Wg[:, 1:D + 1] - Wo[:, 1:D + 1]) / np.sqrt(2.0 * rho * rE)[:, None])
+    print("FP32 per-cell relative error of rho, rho E, momentum after", steps, "steps:", pc, merr,
+          flush=True)
+    assert np.all(pc <= 4e-6), pc
+    assert merr <= 4e-6, merr
