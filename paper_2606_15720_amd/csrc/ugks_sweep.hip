@@ -1259,6 +1259,10 @@ __device__ __forceinline__ int case_of(const int64_t* __restrict__ off, int n, i
   return lo;
 }
 
+// elements per lane of the batch's flattened element-wise kernels (k_tables_b,
+// k_to_f32_b)
+constexpr int PER_LANE = 16;
+
 // next = 0: W^n, q -> prim, cs;  next = 1: W^{n+1}, q -> primn, csn
 template <int D>
 __global__ void k_cell_prep_b(BatchDev bd, int next) {
@@ -1273,39 +1277,66 @@ __global__ void k_cell_prep_b(BatchDev bd, int next) {
 
 template <int D>
 __global__ void k_tables_b(BatchDev bd) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= bd.tab_off[bd.n]) return;
-  const int c = case_of(bd.tab_off, bd.n, t);
-  const CaseDev& C = bd.cases[c];
-  tables_at<D>(t - bd.tab_off[c], C.m.nf, C.fm.na, C.fm.axis, C.m.fbc, C.g, C.B.frec, C.B.prim,
-               C.B.cs, C.B.tabs, C.B.flag);
+  // each wave takes PER_LANE consecutive runs of 64 entries; a lane searches
+  // for an entry's case only when it leaves the previous entry's case
+  const int64_t lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t n = bd.tab_off[bd.n];
+  int c = 0;
+  int64_t lo = 0, hi = 0;
+  for (int j = 0; j < PER_LANE; ++j) {
+    const int64_t t = (wave * PER_LANE + j) * 64 + lane;
+    if (t >= n) break;
+    if (t < lo || t >= hi) {
+      c = case_of(bd.tab_off, bd.n, t);
+      lo = bd.tab_off[c];
+      hi = bd.tab_off[c + 1];
+    }
+    const CaseDev& C = bd.cases[c];
+    tables_at<D>(t - lo, C.m.nf, C.fm.na, C.fm.axis, C.m.fbc, C.g, C.B.frec, C.B.prim, C.B.cs,
+                 C.B.tabs, C.B.flag);
+  }
 }
 
 // FP32 copies of every case's per-step face records, cell records and axis
 // tables (an FP32 batch's sweep computes from them): three flattened ranges.
+// Each wave converts PER_LANE consecutive runs of 64 elements, so that the
+// search for an element's case (a chain of dependent loads) is made once per
+// case a lane meets, not once per element.
 __global__ void k_to_f32_b(BatchDev bd, int64_t nfr, int64_t ncs, int64_t ntab) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < nfr) {
-    const int c = case_of(bd.face_off, bd.n, t / FREC);
-    const CaseDev& C = bd.cases[c];
-    const int64_t i = t - bd.face_off[c] * FREC;
-    C.B.frec32[i] = (float)C.B.frec[i];
-    return;
-  }
-  t -= nfr;
-  if (t < ncs) {
-    const int c = case_of(bd.cell_off, bd.n, t / CSREC);
-    const CaseDev& C = bd.cases[c];
-    const int64_t i = t - bd.cell_off[c] * CSREC;
-    C.B.cs32[i] = (float)C.B.cs[i];
-    return;
-  }
-  t -= ncs;
-  if (t < ntab) {
-    const int c = case_of(bd.tab_off, bd.n, t);
-    const CaseDev& C = bd.cases[c];
-    const int64_t i = t - bd.tab_off[c];
-    C.B.tabs32[i] = (float)C.B.tabs[i];
+  const int64_t lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  // the case of the lane's previous element: its range kind, the range's
+  // first unit (face, cell or table entry) and end, and the arrays
+  int kind_c = -1;
+  int64_t lo = 0, hi = 0;
+  const double* src = nullptr;
+  float* dst = nullptr;
+  for (int j = 0; j < PER_LANE; ++j) {
+    const int64_t t = (wave * PER_LANE + j) * 64 + lane;
+    int kind;
+    int64_t e, unit;  // element within its range, and the unit holding it
+    const int64_t* off;
+    if (t < nfr) {
+      kind = 0, e = t, unit = t / FREC, off = bd.face_off;
+    } else if (t - nfr < ncs) {
+      kind = 1, e = t - nfr, unit = e / CSREC, off = bd.cell_off;
+    } else if (t - nfr - ncs < ntab) {
+      kind = 2, e = t - nfr - ncs, unit = e, off = bd.tab_off;
+    } else {
+      break;
+    }
+    if (kind != kind_c || unit < lo || unit >= hi) {
+      const int c = case_of(off, bd.n, unit);
+      const CaseDev& C = bd.cases[c];
+      kind_c = kind;
+      lo = off[c];
+      hi = off[c + 1];
+      src = kind == 0 ? C.B.frec : kind == 1 ? C.B.cs : C.B.tabs;
+      dst = kind == 0 ? C.B.frec32 : kind == 1 ? C.B.cs32 : C.B.tabs32;
+    }
+    const int64_t i = e - lo * (kind == 0 ? FREC : kind == 1 ? CSREC : 1);
+    dst[i] = (float)src[i];
   }
 }
 
@@ -1525,13 +1556,15 @@ hipError_t launch_to_f32_b(const BatchDev& bd, int64_t nface, int64_t ncell, int
                            hipStream_t s) {
   const int64_t n = nface * FREC + ncell * CSREC + ntab;
   if (n == 0) return hipSuccess;
-  k_to_f32_b<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(bd, nface * FREC, ncell * CSREC, ntab);
+  const int64_t waves = (n + 64 * PER_LANE - 1) / (64 * PER_LANE);
+  k_to_f32_b<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(bd, nface * FREC, ncell * CSREC, ntab);
   return hipGetLastError();
 }
 
 hipError_t launch_tables_b(int D, const BatchDev& bd, int64_t ntab, hipStream_t s) {
   if (ntab == 0) return hipSuccess;
-  const unsigned grid = (unsigned)((ntab + 255) / 256);
+  const int64_t waves = (ntab + 64 * PER_LANE - 1) / (64 * PER_LANE);
+  const unsigned grid = (unsigned)((waves + 3) / 4);
   UGKS_DISPATCH_D(D, k_tables_b<DD><<<grid, 256, 0, s>>>(bd));
   return hipGetLastError();
 }
